@@ -1,0 +1,181 @@
+"""CPU oracle for the product-reduced Taylor matrix exponential (test infrastructure).
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may import this
+package.  It shares no code with the GPU library: the arithmetic lives in ``expm_oracle.c``
+(plain C loop nests, long double / double) and ``theta.py`` (exact rational series).
+
+Every function takes and returns numpy arrays (row-major, float64 or complex128).
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "expm_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force=False):
+    """Compile ``liboracle.so`` with gcc (no FMA contraction, OpenMP over batches)."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-ffp-contract=off", "-fopenmp",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB_PATH)
+        i64, i32, dbl = ctypes.c_int64, ctypes.c_int, ctypes.c_double
+        vp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)
+        L.or_norm1.argtypes = [i64, vp]; L.or_norm1.restype = dbl
+        L.or_norm1_z.argtypes = [i64, vp]; L.or_norm1_z.restype = dbl
+        L.or_expm_taylor.argtypes = [i64, vp, vp, i32, ip]; L.or_expm_taylor.restype = i32
+        L.or_expm_taylor_z.argtypes = [i64, vp, vp, ip]; L.or_expm_taylor_z.restype = i32
+        L.or_expm_taylor_batch.argtypes = [i64, vp, vp, vp, vp, i32, vp]; L.or_expm_taylor_batch.restype = i32
+        L.or_expm_pade26.argtypes = [i64, vp, vp, dbl, ip]; L.or_expm_pade26.restype = i32
+        L.or_reduced_Tm.argtypes = [i64, vp, i32, vp]; L.or_reduced_Tm.restype = i32
+        L.or_expm_reduced.argtypes = [i64, vp, i32, i32, vp]; L.or_expm_reduced.restype = i32
+        L.or_select_plain.argtypes = [dbl, vp, ip, ip]; L.or_select_plain.restype = None
+        L.or_select_alpha.argtypes = [vp, vp, ip, ip]; L.or_select_alpha.restype = None
+        L.or_powers_norms.argtypes = [i64, vp, i32, vp]; L.or_powers_norms.restype = None
+        _lib = L
+    return _lib
+
+
+def _f64(A):
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    assert A.ndim == 2 and A.shape[0] == A.shape[1]
+    return A
+
+
+def _c128(A):
+    A = np.ascontiguousarray(A, dtype=np.complex128)
+    assert A.ndim == 2 and A.shape[0] == A.shape[1]
+    return A
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def norm1(A):
+    """||A||_1 = max_j sum_i |a_ij|, accumulated in long double."""
+    if np.iscomplexobj(A):
+        A = _c128(A)
+        return lib().or_norm1_z(A.shape[0], _p(A))
+    A = _f64(A)
+    return lib().or_norm1(A.shape[0], _p(A))
+
+
+def expm_taylor(A, prec="ld"):
+    """e^A by the plain Taylor series with the oracle's own scaling (||X||_1 <= 1/2) and
+    squaring.  prec: "ld" (long double) or "d" (double); complex input always uses long
+    double complex.  Returns (E, s)."""
+    s = ctypes.c_int(0)
+    if np.iscomplexobj(A):
+        A = _c128(A)
+        E = np.empty_like(A)
+        rc = lib().or_expm_taylor_z(A.shape[0], _p(A), _p(E), ctypes.byref(s))
+    else:
+        A = _f64(A)
+        E = np.empty_like(A)
+        rc = lib().or_expm_taylor(A.shape[0], _p(A), _p(E), 1 if prec == "ld" else 0, ctypes.byref(s))
+    if rc < 0:
+        raise ValueError("non-finite input")
+    return E, s.value
+
+
+def expm_taylor_batch(mats, prec="d"):
+    """Direct-Taylor e^A of a list of real matrices, OpenMP over matrices."""
+    ns = np.array([m.shape[0] for m in mats], dtype=np.int64)
+    offs = np.zeros(len(mats), dtype=np.int64)
+    if len(mats) > 1:
+        offs[1:] = np.cumsum(ns[:-1] ** 2)
+    packed = np.concatenate([np.ascontiguousarray(m, dtype=np.float64).ravel() for m in mats])
+    out = np.empty_like(packed)
+    svals = np.zeros(len(mats), dtype=np.int32)
+    bad = lib().or_expm_taylor_batch(len(mats), _p(ns), _p(offs), _p(packed), _p(out),
+                                     1 if prec == "ld" else 0, _p(svals))
+    if bad:
+        raise ValueError("non-finite input in %d matrices" % bad)
+    return [out[o:o + n * n].reshape(n, n) for o, n in zip(offs, ns)], svals
+
+
+def expm_pade26(A, theta26=None):
+    """Diagonal Pade r_26 with scaling and squaring (long double).  Returns (E, s)."""
+    if theta26 is None:
+        from . import theta as _theta
+        theta26 = _theta.pade_theta(13, 2.0 ** -53)
+    A = _f64(A)
+    E = np.empty_like(A)
+    s = ctypes.c_int(0)
+    rc = lib().or_expm_pade26(A.shape[0], _p(A), _p(E), float(theta26), ctypes.byref(s))
+    if rc < 0:
+        raise ValueError("non-finite input or singular denominator")
+    return E, s.value
+
+
+def reduced_Tm(X, m):
+    """T_m(X) by the paper's product-reduced sequence, evaluated in long double.
+    Returns (T, number_of_products)."""
+    X = _f64(X)
+    T = np.empty_like(X)
+    p = lib().or_reduced_Tm(X.shape[0], _p(X), int(m), _p(T))
+    if p < 0:
+        raise ValueError("unsupported degree %r" % (m,))
+    return T, p
+
+
+def expm_reduced(A, m, s):
+    """T_m(A/2^s)^(2^s) in long double: the method's output for a given (m, s)."""
+    A = _f64(A)
+    E = np.empty_like(A)
+    p = lib().or_expm_reduced(A.shape[0], _p(A), int(m), int(s), _p(E))
+    if p < 0:
+        raise ValueError("unsupported degree %r" % (m,))
+    return E
+
+
+def powers_norms(A, kmax=5):
+    """[||A^k||_1 for k = 1..kmax] from explicit long-double powers."""
+    A = _f64(A)
+    out = np.zeros(kmax, dtype=np.float64)
+    lib().or_powers_norms(A.shape[0], _p(A), int(kmax), _p(out))
+    return out
+
+
+def _theta_row(u):
+    from . import theta as _theta
+    return np.array(_theta.taylor_thetas(u), dtype=np.float64)
+
+
+def select_plain(eta, u=2.0 ** -53):
+    """(m, s) of the plain norm rule for ||A||_1 = eta."""
+    th = _theta_row(u)
+    m, s = ctypes.c_int(0), ctypes.c_int(0)
+    lib().or_select_plain(float(eta), _p(th), ctypes.byref(m), ctypes.byref(s))
+    return m.value, s.value
+
+
+def select_alpha(dk, u=2.0 ** -53):
+    """(m, s) of the alpha_p rule given d_1..d_5 (exact values or upper bounds)."""
+    th = _theta_row(u)
+    d = np.ascontiguousarray(dk, dtype=np.float64)
+    assert d.shape == (5,)
+    m, s = ctypes.c_int(0), ctypes.c_int(0)
+    lib().or_select_alpha(_p(d), _p(th), ctypes.byref(m), ctypes.byref(s))
+    return m.value, s.value
+
+
+def rel_err_1(X, R):
+    """Relative 1-norm error ||X - R||_1 / ||R||_1 (long double accumulation)."""
+    D = np.asarray(X) - np.asarray(R)
+    return norm1(D) / norm1(R)
