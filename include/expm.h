@@ -1,0 +1,128 @@
+/*
+ * expm.h -- C ABI of the MI355X (gfx950) matrix-exponential library.
+ *
+ * Method (Bader, Blanes, Casas, "An improved algorithm to compute the exponential of a
+ * matrix"): scaling and squaring, e^A = (T_m(A / 2^s))^(2^s) (Sec. 1, eq. eses), where the
+ * degree-m Taylor polynomial T_m (Sec. 3, eq. tay.exp) is evaluated with the paper's
+ * product-reduced sequences -- T_8 with 3 products (eq. Algorithm83eA), T_12 with 4 (eq. poly12),
+ * T_18 with 5 (eq. poly.18); T_1, T_2, T_4 with 0, 1, 2 -- and (m, s) is chosen so that the
+ * relative backward error stays below the accuracy u (eq. eq.theta; thresholds theta_m of
+ * Table 2; product counts of Table 3).
+ *
+ * Conventions shared by every entry point
+ *  - Matrices are n x n, row-major, contiguous (element (i, j) at i*n + j).  Complex matrices
+ *    (EXPM_C128) are interleaved (re, im) pairs of doubles.
+ *  - Pointers named *_dev are device (HBM) pointers; the caller owns every buffer.  The
+ *    library allocates no device memory: scratch space is the caller's workspace, sized by
+ *    expm_workspace_bytes().  The output must not alias the input.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue work and return;
+ *    results, (m, s) and per-matrix status are written to device memory, so nothing is known
+ *    on the host until the caller synchronises.  Exception: see expm_taylor for n > 256.
+ *  - Return value: EXPM_OK, or an error code for an argument the host can check (null
+ *    pointer, n <= 0, n above the supported maximum, unknown enum, workspace too small, u
+ *    outside [2^-53, 2^-10]) or a HIP launch failure.  Nothing is launched when an argument
+ *    error is returned.  No C++ exception crosses this boundary.
+ *  - Per-matrix status (device): EXPM_OK, or EXPM_E_NONFINITE when the input holds a NaN or
+ *    an infinity; then (m, s) = (-1, -1) and the output is filled with NaN.
+ */
+#ifndef EXPM_H_
+#define EXPM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define EXPM_API __attribute__((visibility("default")))
+#else
+#define EXPM_API
+#endif
+
+typedef enum {
+  EXPM_OK = 0,
+  EXPM_E_INVALID_ARG = 1,
+  EXPM_E_NONFINITE = 2,
+  EXPM_E_WORKSPACE = 3,
+  EXPM_E_HIP = 4,
+  EXPM_E_UNSUPPORTED = 5
+} expm_status_t;
+
+/* Element type of A and e^A. */
+typedef enum { EXPM_F64 = 0, EXPM_C128 = 1 } expm_dtype_t;
+
+/* Arithmetic of the polynomial products (the powers and the product stage of T_m).  The
+ * norms, the theta comparison, the linear combinations and the s squarings are FP64 in
+ * every form.  EXPM_PREC_FP32: FP32 operands and FP32 accumulation.  EXPM_PREC_BF16X3: each
+ * FP64 operand is split into three bfloat16 terms (hi + mid + lo), six of the nine cross
+ * products are accumulated in FP32 (lo*lo, mid*lo and lo*mid are dropped).  Reduced forms
+ * select (m, s) with the u = 2^-24 thresholds unless opts.u says otherwise. */
+typedef enum { EXPM_PREC_FP64 = 0, EXPM_PREC_FP32 = 1, EXPM_PREC_BF16X3 = 2 } expm_prec_t;
+
+/* How (m, s) is chosen.
+ *  PLAIN:   from eta = ||A||_1 (Sec. 4: an estimate of the norm drives the choice).
+ *  ALPHA:   from alpha_p = max(d_p, d_{p+1}), d_k = ||A^k||_1^(1/k), p (p - 1) <= m + 1
+ *           (the power-norm refinement the paper cites in Sec. 1); d_2, d_3 exact from the
+ *           powers the method forms, d_4, d_5 by submultiplicative upper bounds.
+ *  LEARNED: a small MLP proposes (m, s) from norm features; the proposal is kept only if the
+ *           ALPHA bound holds for it, otherwise the PLAIN rule decides (expm_learned_set). */
+typedef enum { EXPM_SEL_PLAIN = 0, EXPM_SEL_ALPHA = 1, EXPM_SEL_LEARNED = 2 } expm_sel_t;
+
+typedef struct {
+  int32_t dtype;  /* expm_dtype_t */
+  int32_t prec;   /* expm_prec_t */
+  int32_t sel;    /* expm_sel_t */
+  int32_t flags;  /* reserved, must be 0 */
+  double u;       /* target relative backward error; 0 = the form's default (2^-53 for FP64,
+                     2^-24 for FP32 / BF16X3) */
+} expm_opts_t;
+
+/* Human-readable name of a status code (static storage). */
+EXPM_API const char *expm_status_string(expm_status_t st);
+
+/* theta_m(u) (eq. eq.theta): the largest ||X|| for which T_m(X) = e^{X+E} with
+ * ||E|| / ||X|| <= u, from the series of log(e^{-x} T_m(x)) cut after 150 terms (Sec. 1).
+ * Host-only, no GPU needed.  m in {1, 2, 4, 8, 12, 18}; u in [2^-53, 2^-10]. */
+EXPM_API expm_status_t expm_theta(int32_t m, double u, double *theta_out);
+
+/* The selection rule on the host, identical to the device's (for tests and planning).
+ * norms[0..2] = ||A||_1, ||A^2||_1, ||A^3||_1 (entries 1 and 2 ignored by the PLAIN rule; a
+ * negative entry means "not formed", replaced by its submultiplicative bound).  Host-only. */
+EXPM_API expm_status_t expm_select_rule(const double *norms, int32_t sel, double u, int32_t *m_out,
+                               int32_t *s_out);
+
+/* Device workspace in bytes for expm_taylor / expm_batched / expm_select with matrices of
+ * order up to n_max and `batch` matrices. */
+EXPM_API size_t expm_workspace_bytes(int64_t n_max, int64_t batch, const expm_opts_t *opts);
+
+/* (m, s) for one matrix without computing e^A.  PLAIN needs one norm pass; ALPHA and LEARNED
+ * also form A^2 and A^3 in the workspace.  m_dev, s_dev: one int32 each (device). */
+EXPM_API expm_status_t expm_select(const void *A_dev, int64_t n, const expm_opts_t *opts,
+                          int32_t *m_dev, int32_t *s_dev, void *ws_dev, size_t ws_bytes,
+                          void *stream);
+
+/* e^A for one n x n matrix: E_dev <- e^{A_dev}; the chosen (m, s) and the status go to
+ * m_dev, s_dev, status_dev (one int32 each, device; status_dev may be NULL).
+ * n <= 256: one persistent fused launch, no host synchronisation (graph-capturable).
+ * n > 256: tiled multi-workgroup kernels; the host reads (m, s) back once (8 bytes) to size
+ * the launch sequence, so the call synchronises `stream` after the selection step. */
+EXPM_API expm_status_t expm_taylor(const void *A_dev, void *E_dev, int64_t n, const expm_opts_t *opts,
+                          int32_t *m_dev, int32_t *s_dev, int32_t *status_dev, void *ws_dev,
+                          size_t ws_bytes, void *stream);
+
+/* e^A for `batch` independent matrices of uneven order n_b <= n_max <= 256, packed:
+ * matrix b occupies elements [offsets_dev[b], offsets_dev[b] + n_b^2) of A_dev and E_dev
+ * (elements of the dtype, not bytes).  n_dev[b] = n_b (int32).  Outputs per matrix: m_dev[b],
+ * s_dev[b], status_dev[b].  One persistent launch walks a device work queue, largest matrices
+ * first; no host synchronisation (graph-capturable). */
+EXPM_API expm_status_t expm_batched(const void *A_dev, void *E_dev, const int64_t *offsets_dev,
+                           const int32_t *n_dev, int64_t batch, int64_t n_max,
+                           const expm_opts_t *opts, int32_t *m_dev, int32_t *s_dev,
+                           int32_t *status_dev, void *ws_dev, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EXPM_H_ */

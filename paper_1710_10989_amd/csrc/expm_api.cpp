@@ -1,0 +1,191 @@
+// C ABI of the matrix-exponential library (declarations and contracts in include/expm.h).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <mutex>
+
+#include "expm_fused.h"
+#include "expm_internal.h"
+
+using namespace expm;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int64_t kFusedNMax = 256;  // orders handled by the fused kernel
+constexpr int kMaxSlots = 1024;         // upper bound on resident fused workgroups
+
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+int64_t pad16(int64_t n) { return (n + 15) & ~int64_t(15); }
+
+double default_u(int prec) { return prec == EXPM_PREC_FP64 ? 0x1p-53 : 0x1p-24; }
+
+expm_status_t check_opts(const expm_opts_t *o, double *u) {
+  if (!o) return EXPM_E_INVALID_ARG;
+  if (o->dtype != EXPM_F64 && o->dtype != EXPM_C128) return EXPM_E_INVALID_ARG;
+  if (o->prec < EXPM_PREC_FP64 || o->prec > EXPM_PREC_BF16X3) return EXPM_E_INVALID_ARG;
+  if (o->sel < EXPM_SEL_PLAIN || o->sel > EXPM_SEL_LEARNED) return EXPM_E_INVALID_ARG;
+  if (o->flags != 0) return EXPM_E_INVALID_ARG;
+  double uu = o->u == 0.0 ? default_u(o->prec) : o->u;
+  if (!(uu >= 0x1p-53 && uu <= 0x1p-10)) return EXPM_E_INVALID_ARG;
+  *u = uu;
+  return EXPM_OK;
+}
+
+// Slots of the fused kernel for a batch: one per resident workgroup, capped by the batch.
+int fused_slots(int64_t batch) {
+  static int cap = -1;
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lk(mu);
+  if (cap < 0) {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0) {
+      int per = fused_max_blocks_per_cu();
+      cap = cus * per;
+      if (cap > kMaxSlots) cap = kMaxSlots;
+    } else {
+      cap = kMaxSlots;  // no device visible: size for the largest launch
+    }
+  }
+  return (int)(batch < cap ? batch : cap);
+}
+
+struct FusedLayout {
+  size_t counter_off, order_off, slots_off, total;
+  size_t slot_doubles;
+  int slots;
+};
+
+FusedLayout fused_layout(int64_t n_max, int64_t batch) {
+  FusedLayout L;
+  const int64_t np = pad16(n_max);
+  L.slots = fused_slots(batch);
+  L.slot_doubles = (size_t)kFusedBufs * np * np;
+  L.counter_off = 0;
+  L.order_off = kAlign;
+  L.slots_off = L.order_off + align_up(sizeof(int32_t) * (size_t)batch);
+  L.total = L.slots_off + (size_t)L.slots * L.slot_doubles * sizeof(double);
+  return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *expm_status_string(expm_status_t st) {
+  switch (st) {
+    case EXPM_OK: return "ok";
+    case EXPM_E_INVALID_ARG: return "invalid argument";
+    case EXPM_E_NONFINITE: return "non-finite input";
+    case EXPM_E_WORKSPACE: return "workspace too small";
+    case EXPM_E_HIP: return "HIP runtime error";
+    case EXPM_E_UNSUPPORTED: return "unsupported combination";
+  }
+  return "unknown status";
+}
+
+expm_status_t expm_theta(int32_t m, double u, double *theta_out) {
+  if (!theta_out) return EXPM_E_INVALID_ARG;
+  return theta_of(m, u, theta_out) ? EXPM_OK : EXPM_E_INVALID_ARG;
+}
+
+expm_status_t expm_select_rule(const double *norms, int32_t sel, double u, int32_t *m_out,
+                               int32_t *s_out) {
+  if (!norms || !m_out || !s_out) return EXPM_E_INVALID_ARG;
+  if (sel != EXPM_SEL_PLAIN && sel != EXPM_SEL_ALPHA) return EXPM_E_INVALID_ARG;
+  if (!(norms[0] >= 0.0) || !isfinite(norms[0])) return EXPM_E_NONFINITE;
+  Consts k;
+  if (!make_consts(u, &k)) return EXPM_E_INVALID_ARG;
+  int m, s;
+  select_ms(k.theta, sel == EXPM_SEL_ALPHA, norms[0], norms[1], norms[2], &m, &s);
+  *m_out = m;
+  *s_out = s;
+  return EXPM_OK;
+}
+
+size_t expm_workspace_bytes(int64_t n_max, int64_t batch, const expm_opts_t *opts) {
+  double u;
+  if (n_max < 1 || batch < 1 || check_opts(opts, &u) != EXPM_OK) return 0;
+  if (n_max <= kFusedNMax && opts->dtype == EXPM_F64 && opts->prec == EXPM_PREC_FP64)
+    return fused_layout(n_max, batch).total;
+  return 0;
+}
+
+static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, const int32_t *ns,
+                               int64_t batch, int64_t n_uniform, int64_t n_max,
+                               const expm_opts_t *opts, double u, int32_t *m_dev, int32_t *s_dev,
+                               int32_t *status_dev, void *ws, size_t ws_bytes, void *stream,
+                               int select_only) {
+  FusedLayout L = fused_layout(n_max, batch);
+  if (!ws || ws_bytes < L.total) return EXPM_E_WORKSPACE;
+  if (((uintptr_t)ws) % kAlign) return EXPM_E_INVALID_ARG;
+  FusedArgs a;
+  memset(&a, 0, sizeof(a));
+  if (!make_consts(u, &a.k)) return EXPM_E_INVALID_ARG;
+  a.A = (const double *)A;
+  a.E = (double *)E;
+  a.offs = offs;
+  a.ns = ns;
+  a.m_out = m_dev;
+  a.s_out = s_dev;
+  a.status = status_dev;
+  char *base = (char *)ws;
+  a.slots = (double *)(base + L.slots_off);
+  a.slot_doubles = L.slot_doubles;
+  a.batch = batch;
+  a.n_uniform = (int)n_uniform;
+  a.np_max = (int)pad16(n_max);
+  a.sel = opts->sel == EXPM_SEL_LEARNED ? EXPM_SEL_ALPHA : opts->sel;
+  a.select_only = select_only;
+  hipStream_t st = (hipStream_t)stream;
+  if (ns) {
+    a.order = (const int32_t *)(base + L.order_off);
+    a.counter = (unsigned long long *)(base + L.counter_off);
+    if (launch_order(ns, batch, (int32_t *)a.order, a.counter, st) != hipSuccess) return EXPM_E_HIP;
+  }
+  if (launch_fused(a, L.slots, st) != hipSuccess) return EXPM_E_HIP;
+  return EXPM_OK;
+}
+
+expm_status_t expm_select(const void *A_dev, int64_t n, const expm_opts_t *opts, int32_t *m_dev,
+                          int32_t *s_dev, void *ws_dev, size_t ws_bytes, void *stream) {
+  double u;
+  expm_status_t st = check_opts(opts, &u);
+  if (st != EXPM_OK) return st;
+  if (!A_dev || !m_dev || !s_dev || n < 1) return EXPM_E_INVALID_ARG;
+  if (n > kFusedNMax || opts->dtype != EXPM_F64 || opts->prec != EXPM_PREC_FP64) return EXPM_E_UNSUPPORTED;
+  return run_fused(A_dev, nullptr, nullptr, nullptr, 1, n, n, opts, u, m_dev, s_dev, nullptr,
+                   ws_dev, ws_bytes, stream, 1);
+}
+
+expm_status_t expm_taylor(const void *A_dev, void *E_dev, int64_t n, const expm_opts_t *opts,
+                          int32_t *m_dev, int32_t *s_dev, int32_t *status_dev, void *ws_dev,
+                          size_t ws_bytes, void *stream) {
+  double u;
+  expm_status_t st = check_opts(opts, &u);
+  if (st != EXPM_OK) return st;
+  if (!A_dev || !E_dev || !m_dev || !s_dev || n < 1 || A_dev == E_dev) return EXPM_E_INVALID_ARG;
+  if (n > kFusedNMax || opts->dtype != EXPM_F64 || opts->prec != EXPM_PREC_FP64) return EXPM_E_UNSUPPORTED;
+  return run_fused(A_dev, E_dev, nullptr, nullptr, 1, n, n, opts, u, m_dev, s_dev, status_dev,
+                   ws_dev, ws_bytes, stream, 0);
+}
+
+expm_status_t expm_batched(const void *A_dev, void *E_dev, const int64_t *offsets_dev,
+                           const int32_t *n_dev, int64_t batch, int64_t n_max,
+                           const expm_opts_t *opts, int32_t *m_dev, int32_t *s_dev,
+                           int32_t *status_dev, void *ws_dev, size_t ws_bytes, void *stream) {
+  double u;
+  expm_status_t st = check_opts(opts, &u);
+  if (st != EXPM_OK) return st;
+  if (!A_dev || !E_dev || !offsets_dev || !n_dev || !m_dev || !s_dev || batch < 1 || n_max < 1 ||
+      A_dev == E_dev)
+    return EXPM_E_INVALID_ARG;
+  if (n_max > kFusedNMax || opts->dtype != EXPM_F64 || opts->prec != EXPM_PREC_FP64) return EXPM_E_UNSUPPORTED;
+  return run_fused(A_dev, E_dev, offsets_dev, n_dev, batch, 0, n_max, opts, u, m_dev, s_dev,
+                   status_dev, ws_dev, ws_bytes, stream, 0);
+}
+
+}  // extern "C"

@@ -1,0 +1,346 @@
+// Persistent fused kernel: e^A for matrices of order n <= 256, one workgroup per matrix.
+//
+// Each workgroup pops matrices from a device work queue (largest order first) and runs the
+// whole method for it: copy A into a zero-padded np x np buffer (np = n rounded up to 16)
+// while taking the 1-norm, choose (m, s), form the powers A^2, A^3 (A^6) with MFMA GEMMs,
+// build the linear combinations of the product-reduced sequence in GEMM epilogues, run the
+// product stage and the s squarings, and write e^A.  Zero padding is exact: every polynomial
+// in the padded matrix is block diagonal, so the leading n x n block is p(A).
+//
+// Scaling (Sec. 1, eq. eses) is folded into the coefficients: X^k = 2^(-sk) A^k, so the
+// stored powers are those of A and no pass rescales a matrix.
+//
+// Workspace: one slot of 8 np_max^2 doubles per resident workgroup; a matrix of order n uses
+// the first 8 np^2 doubles of its workgroup's slot.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "expm_fused.h"
+#include "expm_internal.h"
+#include "gemm_block.h"
+
+namespace expm {
+
+namespace {
+
+constexpr int kBufs = kFusedBufs;
+
+// Column sums of |B| over an np x np buffer (thread j owns column j), reduced to the maximum.
+__device__ double block_norm1(const double *B, int np, double *red) {
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  if (tid < np) {
+    int i = 0;
+    for (; i + 4 <= np; i += 4) {
+      double v0 = B[(size_t)(i + 0) * np + tid], v1 = B[(size_t)(i + 1) * np + tid];
+      double v2 = B[(size_t)(i + 2) * np + tid], v3 = B[(size_t)(i + 3) * np + tid];
+      s += fabs(v0); s += fabs(v1); s += fabs(v2); s += fabs(v3);
+    }
+    for (; i < np; ++i) s += fabs(B[(size_t)i * np + tid]);
+  }
+  red[tid] = s;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
+    __syncthreads();
+  }
+  double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Elementwise pass over the np x np index space.
+template <class F>
+__device__ void for_each_elem(int np, const F &f) {
+  const int total = np * np;
+  for (int e = threadIdx.x; e < total; e += kThreads) {
+    const int row = e / np, col = e - row * np;
+    f(row, col, e);
+  }
+  __syncthreads();
+}
+
+// Scaled coefficients for degree m and scaling s, written to g_ep.c: a coefficient of X^k
+// becomes coef * 2^(-s k) on the stored power A^k.
+__device__ void make_coefs(const Consts &k, int m, int s) {
+  const double h1 = ldexp(1.0, -s), h2 = ldexp(1.0, -2 * s), h3 = ldexp(1.0, -3 * s),
+               h6 = ldexp(1.0, -6 * s);
+  double *c = g_ep.c;
+  switch (m) {
+    case 1: c[0] = h1; break;
+    case 2: c[0] = h1; c[1] = 0.5 * h2; break;
+    case 4:
+      c[0] = h1; c[1] = h2;                            // T = I + h1 A + h2 (A^2 W)
+      c[2] = 0.5; c[3] = h1 / 6.0; c[4] = h2 / 24.0;   // W = I/2 + X/6 + X^2/24
+      break;
+    case 8:
+      c[0] = k.t8[0] * h1; c[1] = k.t8[1] * h2;       // W1 = x1 X + x2 X^2
+      c[2] = h2;                                        // A_4 = h2 (A^2 W1)
+      c[3] = k.t8[2] * h2;                              // L = x3 X^2 + A_4
+      c[4] = k.t8[3]; c[5] = k.t8[4] * h1; c[6] = k.t8[5] * h2; c[7] = k.t8[6];  // R
+      c[8] = k.t8[7]; c[9] = k.t8[8] * h1; c[10] = k.t8[9] * h2;  // y0 I + y1 X + y2 X^2
+      break;
+    case 12:
+      for (int j = 0; j < 4; ++j) {
+        c[4 * j + 0] = k.t12[j][0];
+        c[4 * j + 1] = k.t12[j][1] * h1;
+        c[4 * j + 2] = k.t12[j][2] * h2;
+        c[4 * j + 3] = k.t12[j][3] * h3;
+      }
+      break;
+    case 18:
+      c[0] = k.t18a[0]; c[1] = k.t18a[1] * h1; c[2] = k.t18a[2] * h2; c[3] = k.t18a[3] * h3;
+      for (int j = 0; j < 4; ++j) {
+        c[4 + 5 * j + 0] = k.t18b[j][0];
+        c[4 + 5 * j + 1] = k.t18b[j][1] * h1;
+        c[4 + 5 * j + 2] = k.t18b[j][2] * h2;
+        c[4 + 5 * j + 3] = k.t18b[j][3] * h3;
+        c[4 + 5 * j + 4] = k.t18b[j][4] * h6;
+      }
+      break;
+  }
+}
+
+__shared__ int sh_ms[2];
+
+// One GEMM step: thread 0 fills the LDS descriptor through `set`, then all threads run it.
+template <class S>
+__device__ void gemm_step(const S &set) {
+  if (threadIdx.x == 0) set(g_ep);
+  __syncthreads();
+  gemm_block();
+}
+
+__device__ void put_out(double *p, int ld, int nvalid, int r, int cc, double v) {
+  if (r < nvalid && cc < nvalid) p[(size_t)r * ld + cc] = v;
+}
+
+// Runs the method on one matrix.
+__device__ void run_one(const FusedArgs &a, int64_t b, double *slot, double *red) {
+  const int tid = threadIdx.x;
+  const int n = a.ns ? a.ns[b] : a.n_uniform;
+  const int64_t off = a.offs ? a.offs[b] : b * (int64_t)n * n;
+  if (n < 1 || n > a.np_max) {
+    if (tid == 0) {
+      a.m_out[b] = -1; a.s_out[b] = -1;
+      if (a.status) a.status[b] = EXPM_E_INVALID_ARG;
+    }
+    return;
+  }
+  const int np = (n + 15) & ~15;
+  const size_t nn = (size_t)np * np;
+  double *buf[kBufs];
+  for (int i = 0; i < kBufs; ++i) buf[i] = slot + i * nn;
+  const double *A = a.A + off;
+  double *E = a.E ? a.E + off : nullptr;
+
+  // ---- load A into buf0 (zero padded) and take ||A||_1 (thread j owns column j) ----
+  double colsum = 0.0;
+  int bad = 0;
+  if (tid < np) {
+    for (int i = 0; i < np; ++i) {
+      double v = 0.0;
+      if (i < n && tid < n) v = A[(size_t)i * n + tid];
+      bad |= !isfinite(v);
+      colsum += fabs(v);
+      buf[0][(size_t)i * np + tid] = v;
+    }
+  }
+  bad = __syncthreads_or(bad);
+  red[tid] = colsum;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
+    __syncthreads();
+  }
+  const double eta = red[0];
+  __syncthreads();
+
+  if (bad) {
+    if (E) for (int e = tid; e < n * n; e += kThreads) E[e] = __builtin_nan("");
+    if (tid == 0) {
+      a.m_out[b] = -1; a.s_out[b] = -1;
+      if (a.status) a.status[b] = EXPM_E_NONFINITE;
+    }
+    __syncthreads();
+    return;
+  }
+
+  if (tid == 0) select_ms(a.k.theta, 0, eta, -1.0, -1.0, &sh_ms[0], &sh_ms[1]);
+  __syncthreads();
+  const int m_plain = sh_ms[0];
+
+  // ---- powers A^2 (m >= 2), A^3 (m >= 12) ----
+  const bool want_alpha = (a.sel == EXPM_SEL_ALPHA);
+  double n2 = -1.0, n3 = -1.0;
+  if (m_plain >= 2) {
+    gemm_step([&](EpiDesc &d) {
+      d.P = buf[0]; d.Q = buf[0]; d.kind = EK_STORE; d.np = np;
+      d.dst = buf[1]; d.dst_ld = np; d.dst_nvalid = np;
+    });
+    if (want_alpha) n2 = block_norm1(buf[1], np, red);
+  }
+  if (m_plain >= 12) {
+    gemm_step([&](EpiDesc &d) {
+      d.P = buf[1]; d.Q = buf[0]; d.kind = EK_STORE; d.np = np;
+      d.dst = buf[2]; d.dst_ld = np; d.dst_nvalid = np;
+    });
+    if (want_alpha) n3 = block_norm1(buf[2], np, red);
+  }
+  if (want_alpha && m_plain >= 2) {
+    if (tid == 0) select_ms(a.k.theta, 1, eta, n2, n3, &sh_ms[0], &sh_ms[1]);
+    __syncthreads();
+  }
+  const int m = sh_ms[0], s = sh_ms[1];
+  if (tid == 0) {
+    make_coefs(a.k, m, s);
+    a.m_out[b] = m; a.s_out[b] = s;
+    if (a.status) a.status[b] = EXPM_OK;
+  }
+  __syncthreads();
+  if (a.select_only) return;
+
+  const double *c = g_ep.c;
+  const int tb = (m >= 8) ? 2 : 3;  // buffer holding T when s > 0
+  double *Tp = (s == 0) ? E : buf[tb];
+  const int Tld = (s == 0) ? n : np, Tnv = (s == 0) ? n : np;
+  double *B0 = buf[0], *B1 = buf[1], *B2 = buf[2];
+  auto base = [&](EpiDesc &d) {
+    d.np = np; d.b0 = B0; d.b1 = B1; d.b2 = B2;
+    d.dst = Tp; d.dst_ld = Tld; d.dst_nvalid = Tnv;
+  };
+
+  if (m == 1) {
+    const double c0 = c[0];
+    for_each_elem(np, [&](int r, int cc, int e) { put_out(Tp, Tld, Tnv, r, cc, (r == cc ? 1.0 : 0.0) + c0 * B0[e]); });
+  } else if (m == 2) {
+    const double c0 = c[0], c1 = c[1];
+    for_each_elem(np, [&](int r, int cc, int e) {
+      put_out(Tp, Tld, Tnv, r, cc, (r == cc ? 1.0 : 0.0) + c0 * B0[e] + c1 * B1[e]);
+    });
+  } else if (m == 4) {
+    double *W = buf[2];
+    const double c2 = c[2], c3 = c[3], c4 = c[4];
+    for_each_elem(np, [&](int r, int cc, int e) { W[e] = (r == cc ? c2 : 0.0) + c3 * B0[e] + c4 * B1[e]; });
+    gemm_step([&](EpiDesc &d) { base(d); d.P = B1; d.Q = W; d.kind = EK_M4; });
+  } else if (m == 8) {
+    double *W1 = buf[2], *L = buf[3], *Rm = buf[4];
+    const double c0 = c[0], c1 = c[1];
+    for_each_elem(np, [&](int, int, int e) { W1[e] = c0 * B0[e] + c1 * B1[e]; });
+    gemm_step([&](EpiDesc &d) { base(d); d.P = B1; d.Q = W1; d.kind = EK_M8A; d.o[0] = L; d.o[1] = Rm; });
+    gemm_step([&](EpiDesc &d) { base(d); d.P = L; d.Q = Rm; d.kind = EK_M8B; });
+  } else if (m == 12) {
+    double *Bq0 = buf[3], *Bq1 = buf[4], *Bq2 = buf[5], *Bq3 = buf[6];
+    double cf[16];
+    for (int i = 0; i < 16; ++i) cf[i] = c[i];
+    for_each_elem(np, [&](int r, int cc, int e) {
+      const double id = (r == cc) ? 1.0 : 0.0;
+      const double x1 = B0[e], x2 = B1[e], x3 = B2[e];
+      Bq0[e] = cf[0] * id + cf[1] * x1 + cf[2] * x2 + cf[3] * x3;
+      Bq1[e] = cf[4] * id + cf[5] * x1 + cf[6] * x2 + cf[7] * x3;
+      Bq2[e] = cf[8] * id + cf[9] * x1 + cf[10] * x2 + cf[11] * x3;
+      Bq3[e] = cf[12] * id + cf[13] * x1 + cf[14] * x2 + cf[15] * x3;
+    });
+    double *A6 = buf[0], *Y = buf[1];
+    // A_6 = B_3 + B_4^2 ; Y = B_2 + A_6
+    gemm_step([&](EpiDesc &d) {
+      base(d); d.P = Bq3; d.Q = Bq3; d.kind = EK_SPLIT2; d.in0 = Bq2; d.in1 = Bq1; d.o[0] = A6; d.o[1] = Y;
+    });
+    // T_12 = B_1 + Y A_6
+    gemm_step([&](EpiDesc &d) { base(d); d.P = Y; d.Q = A6; d.kind = EK_ADD1; d.in0 = Bq0; });
+  } else {  // m == 18
+    double *Bq[5] = {buf[3], buf[4], buf[5], buf[6], buf[7]};
+    // A^6 = A^3 A^3; the epilogue forms B_1..B_5 from (I, A, A^2, A^3, A^6)
+    gemm_step([&](EpiDesc &d) {
+      base(d); d.P = B2; d.Q = B2; d.kind = EK_M18A;
+      for (int j = 0; j < 5; ++j) d.o[j] = Bq[j];
+    });
+    double *A9 = buf[0], *Y = buf[1];
+    // A_9 = B_1 B_5 + B_4 ; Y = B_3 + A_9
+    gemm_step([&](EpiDesc &d) {
+      base(d); d.P = Bq[0]; d.Q = Bq[4]; d.kind = EK_SPLIT2; d.in0 = Bq[3]; d.in1 = Bq[2]; d.o[0] = A9; d.o[1] = Y;
+    });
+    // T_18 = B_2 + Y A_9
+    gemm_step([&](EpiDesc &d) { base(d); d.P = Y; d.Q = A9; d.kind = EK_ADD1; d.in0 = Bq[1]; });
+  }
+
+  // ---- s squarings, ping-pong between buffers tb and tb^1 ----
+  int cur = tb;
+  for (int rsq = 1; rsq <= s; ++rsq) {
+    const int nxt = cur ^ 1;
+    const bool last = (rsq == s);
+    gemm_step([&](EpiDesc &d) {
+      d.np = np; d.P = buf[cur]; d.Q = buf[cur]; d.kind = EK_STORE;
+      d.dst = last ? E : buf[nxt]; d.dst_ld = last ? n : np; d.dst_nvalid = last ? n : np;
+    });
+    cur = nxt;
+  }
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(kThreads, 2) void expm_fused_kernel(FusedArgs a) {
+  __shared__ double red[kThreads];
+  __shared__ int64_t sh_idx;
+  double *slot = a.slots + (size_t)blockIdx.x * a.slot_doubles;
+  for (int64_t it = blockIdx.x;; it += gridDim.x) {
+    int64_t idx = it;
+    if (a.counter) {
+      if (threadIdx.x == 0) sh_idx = (int64_t)atomicAdd(a.counter, 1ull);
+      __syncthreads();
+      idx = sh_idx;
+      __syncthreads();
+    }
+    if (idx >= a.batch) break;
+    const int64_t b = a.order ? a.order[idx] : idx;
+    run_one(a, b, slot, red);
+    __syncthreads();
+  }
+}
+
+// Counting sort of the batch by padded order, largest first (the work-queue order), and
+// reset of the queue counter.  One workgroup.
+__global__ void expm_order_kernel(const int32_t *ns, int64_t batch, int32_t *order,
+                                  unsigned long long *counter) {
+  __shared__ int hist[18], start[18];
+  const int tid = threadIdx.x;
+  if (tid < 18) hist[tid] = 0;
+  if (tid == 0) *counter = 0ull;
+  __syncthreads();
+  auto key = [&](int64_t b) {
+    const int n = ns[b];
+    if (n < 1 || n > kNpMax) return 17;
+    return 16 - ((n + 15) >> 4);  // 0 for np = 256 ... 15 for np = 16
+  };
+  for (int64_t b = tid; b < batch; b += blockDim.x) atomicAdd(&hist[key(b)], 1);
+  __syncthreads();
+  if (tid == 0) {
+    int acc = 0;
+    for (int i = 0; i < 18; ++i) { start[i] = acc; acc += hist[i]; }
+  }
+  __syncthreads();
+  for (int64_t b = tid; b < batch; b += blockDim.x) {
+    const int pos = atomicAdd(&start[key(b)], 1);
+    order[pos] = (int32_t)b;
+  }
+}
+
+int fused_max_blocks_per_cu() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, expm_fused_kernel, kThreads, 0) != hipSuccess)
+    return 1;
+  return nb < 1 ? 1 : nb;
+}
+
+hipError_t launch_fused(const FusedArgs &a, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(expm_fused_kernel, dim3(grid), dim3(kThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_order(const int32_t *ns, int64_t batch, int32_t *order,
+                        unsigned long long *counter, hipStream_t st) {
+  hipLaunchKernelGGL(expm_order_kernel, dim3(1), dim3(1024), 0, st, ns, batch, order, counter);
+  return hipGetLastError();
+}
+
+}  // namespace expm

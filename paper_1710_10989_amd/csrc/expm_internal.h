@@ -1,0 +1,89 @@
+// Internal declarations of the gfx950 matrix-exponential library (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/expm.h"
+
+namespace expm {
+
+// Degrees of the product-reduced Taylor family and their product counts (Table 3; T_1, T_2,
+// T_4 take 0, 1, 2 products).
+constexpr int kNumDeg = 6;
+constexpr int kDeg[kNumDeg] = {1, 2, 4, 8, 12, 18};
+constexpr int kProducts[kNumDeg] = {0, 1, 2, 3, 4, 5};
+
+// Coefficients and thresholds handed to the kernels by value.
+struct Consts {
+  double theta[kNumDeg];  // theta_m(u) for m = 1, 2, 4, 8, 12, 18
+  // T_8, eq. Algorithm83eA (x3 = 2/3): x1..x7 in t8[0..6], y0, y1, y2 in t8[7..9].
+  double t8[10];
+  // T_12, eq. poly12: t12[j][i] = a_{i, j+1}, i = power 0..3 (I, A, A^2, A^3), j = B index - 1.
+  double t12[4][4];
+  // T_18, eq. poly.18: B_1 = sum_i t18a[i] A^i (i = 0..3); B_{j+2} = t18b[j] over
+  // (I, A, A^2, A^3, A^6), i.e. t18b[j][*] = b_{*, j+1}.
+  double t18a[4];
+  double t18b[4][5];
+};
+
+// Builds Consts for accuracy u (host; thresholds cached per u).  Returns false for u outside
+// the supported range.
+bool make_consts(double u, Consts *out);
+// theta_m(u), host.
+bool theta_of(int m, double u, double *out);
+
+// Smallest s >= 0 with eta / 2^s <= theta (exact comparisons; scaling by 2^s is exact).
+__host__ __device__ inline int scale_exp(double eta, double theta) {
+  if (!(eta > theta)) return 0;
+  int e;
+  (void)frexp(eta / theta, &e);  // eta/theta in [2^(e-1), 2^e)
+  int s = e > 0 ? e : 0;
+  while (s > 0 && eta <= ldexp(theta, s - 1)) --s;
+  while (eta > ldexp(theta, s)) ++s;
+  return s;
+}
+
+// Norm quantities for the ALPHA rule from ||A||, ||A^2||, ||A^3|| (n2, n3 < 0: not formed,
+// replaced by submultiplicative bounds).  d[k-1] >= ||A^k||^(1/k), k = 1..5.
+__host__ __device__ inline void alpha_d(double n1, double n2, double n3, double d[5]) {
+  if (n2 < 0) n2 = n1 * n1;
+  if (n3 < 0) n3 = fmin(n1 * n2, n1 * n1 * n1);
+  double n4 = fmin(n2 * n2, n3 * n1);
+  double n5 = fmin(n2 * n3, n4 * n1);
+  d[0] = n1;
+  d[1] = sqrt(n2);
+  d[2] = cbrt(n3);
+  d[3] = sqrt(sqrt(n4));
+  d[4] = pow(n5, 0.2);
+}
+
+// (m, s) selection: for each degree, eta_m is ||A||_1 (PLAIN) or the smallest admissible
+// alpha_p = max(d_p, d_{p+1}) with p (p - 1) <= m + 1 (ALPHA); s_m = scale_exp(eta_m, theta_m);
+// cost = products + s_m; cheapest wins, ties go to the smaller s.
+__host__ __device__ inline void select_ms(const double *theta, int alpha, double n1, double n2,
+                                          double n3, int *m_out, int *s_out) {
+  double d[5];
+  if (alpha) alpha_d(n1, n2, n3, d);
+  int best = -1, best_cost = 0, best_s = 0;
+  for (int i = 0; i < kNumDeg; ++i) {
+    double eta = n1;
+    if (alpha) {
+      const int m = kDeg[i];
+      eta = n1;  // p = 1: alpha_1 = max(d_1, d_2) = d_1
+      for (int p = 2; p <= 4; ++p) {
+        if (p * (p - 1) > m + 1) break;
+        double a = fmax(d[p - 1], d[p]);
+        if (a < eta) eta = a;
+      }
+    }
+    int s = scale_exp(eta, theta[i]);
+    int cost = kProducts[i] + s;
+    if (best < 0 || cost < best_cost || (cost == best_cost && s < best_s)) {
+      best = i; best_cost = cost; best_s = s;
+    }
+  }
+  *m_out = kDeg[best];
+  *s_out = best_s;
+}
+
+}  // namespace expm

@@ -1,0 +1,135 @@
+"""Python binding of the C ABI: torch tensors in, torch tensors out.
+
+PyTorch supplies device memory and the stream only.  Each function checks the arguments it
+forwards, calls the matching ``expm_*`` entry point on the current HIP stream and returns
+device tensors; nothing is computed in Python.
+"""
+import ctypes
+
+import torch
+
+from . import _native as N
+
+_PREC = {"fp64": N.EXPM_PREC_FP64, "fp32": N.EXPM_PREC_FP32, "bf16x3": N.EXPM_PREC_BF16X3}
+_SEL = {"plain": N.EXPM_SEL_PLAIN, "alpha": N.EXPM_SEL_ALPHA, "learned": N.EXPM_SEL_LEARNED}
+
+
+def _opts(dtype, prec, selector, u):
+    return N.ExpmOpts(N.EXPM_C128 if dtype == torch.complex128 else N.EXPM_F64, _PREC[prec],
+                      _SEL[selector], 0, 0.0 if u is None else float(u))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def theta(m, u=2.0 ** -53):
+    """theta_m(u) as the library computes it (host only)."""
+    out = ctypes.c_double(0.0)
+    N.check(N.lib().expm_theta(int(m), float(u), ctypes.byref(out)), "expm_theta")
+    return out.value
+
+
+def select_rule(norms, selector="plain", u=2.0 ** -53):
+    """(m, s) of the library's selection rule for ||A||, ||A^2||, ||A^3|| (host only; pass -1
+    for a power that is not formed)."""
+    arr = (ctypes.c_double * 3)(*[float(x) for x in (list(norms) + [-1.0, -1.0])[:3]])
+    m, s = ctypes.c_int32(0), ctypes.c_int32(0)
+    N.check(N.lib().expm_select_rule(arr, _SEL[selector], float(u), ctypes.byref(m), ctypes.byref(s)),
+            "expm_select_rule")
+    return m.value, s.value
+
+
+def workspace_bytes(n_max, batch=1, dtype=torch.float64, prec="fp64", selector="plain", u=None):
+    o = _opts(dtype, prec, selector, u)
+    return N.lib().expm_workspace_bytes(int(n_max), int(batch), ctypes.byref(o))
+
+
+def _workspace(nbytes, device):
+    if nbytes == 0:
+        raise N.ExpmError(N.EXPM_E_UNSUPPORTED, "expm_workspace_bytes")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def _check_square(A):
+    if A.dim() != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("A must be a square matrix")
+    if not A.is_cuda:
+        raise ValueError("A must be a device tensor")
+    if A.dtype not in (torch.float64, torch.complex128):
+        raise ValueError("A must be float64 or complex128")
+
+
+def taylor(A, u=None, prec="fp64", selector="plain", workspace=None):
+    """e^A for one square device matrix.  Returns (E, m, s, status) with m, s, status as
+    one-element int32 device tensors."""
+    _check_square(A)
+    A = A.contiguous()
+    n = A.shape[0]
+    o = _opts(A.dtype, prec, selector, u)
+    ws = workspace if workspace is not None else _workspace(
+        N.lib().expm_workspace_bytes(n, 1, ctypes.byref(o)), A.device)
+    E = torch.empty_like(A)
+    ms = torch.empty(3, dtype=torch.int32, device=A.device)
+    st = N.lib().expm_taylor(_ptr(A), _ptr(E), n, ctypes.byref(o), _ptr(ms[0:1]), _ptr(ms[1:2]),
+                             _ptr(ms[2:3]), _ptr(ws), ws.numel(), _stream())
+    N.check(st, "expm_taylor")
+    return E, ms[0:1], ms[1:2], ms[2:3]
+
+
+def select(A, u=None, prec="fp64", selector="plain"):
+    """(m, s) chosen for A, as one-element int32 device tensors."""
+    _check_square(A)
+    A = A.contiguous()
+    n = A.shape[0]
+    o = _opts(A.dtype, prec, selector, u)
+    ws = _workspace(N.lib().expm_workspace_bytes(n, 1, ctypes.byref(o)), A.device)
+    ms = torch.empty(2, dtype=torch.int32, device=A.device)
+    N.check(N.lib().expm_select(_ptr(A), n, ctypes.byref(o), _ptr(ms[0:1]), _ptr(ms[1:2]), _ptr(ws),
+                                ws.numel(), _stream()), "expm_select")
+    return ms[0:1], ms[1:2]
+
+
+class Batch:
+    """A packed batch of square matrices of uneven order on the device."""
+
+    def __init__(self, packed, offsets, ns, n_max):
+        self.packed, self.offsets, self.ns, self.n_max = packed, offsets, ns, int(n_max)
+
+    @classmethod
+    def from_host(cls, mats, device="cuda", dtype=torch.float64):
+        import numpy as np
+        ns = np.array([m.shape[0] for m in mats], dtype=np.int32)
+        offs = np.zeros(len(mats), dtype=np.int64)
+        if len(mats) > 1:
+            offs[1:] = np.cumsum(ns[:-1].astype(np.int64) ** 2)
+        packed = np.concatenate([np.ascontiguousarray(m).ravel() for m in mats])
+        return cls(torch.from_numpy(packed).to(device=device, dtype=dtype),
+                   torch.from_numpy(offs).to(device), torch.from_numpy(ns).to(device), int(ns.max()))
+
+    def unpack(self, flat):
+        offs = self.offsets.cpu().numpy()
+        ns = self.ns.cpu().numpy()
+        host = flat.cpu().numpy()
+        return [host[o:o + n * n].reshape(n, n) for o, n in zip(offs, ns)]
+
+
+def batched(batch, u=None, prec="fp64", selector="plain", workspace=None, out=None):
+    """e^A for every matrix of a Batch.  Returns (E_packed, m, s, status) device tensors."""
+    nb = batch.ns.numel()
+    o = _opts(batch.packed.dtype, prec, selector, u)
+    ws = workspace if workspace is not None else _workspace(
+        N.lib().expm_workspace_bytes(batch.n_max, nb, ctypes.byref(o)), batch.packed.device)
+    E = out if out is not None else torch.empty_like(batch.packed)
+    m = torch.empty(nb, dtype=torch.int32, device=batch.packed.device)
+    s = torch.empty_like(m)
+    status = torch.empty_like(m)
+    st = N.lib().expm_batched(_ptr(batch.packed), _ptr(E), _ptr(batch.offsets), _ptr(batch.ns), nb,
+                              batch.n_max, ctypes.byref(o), _ptr(m), _ptr(s), _ptr(status), _ptr(ws),
+                              ws.numel(), _stream())
+    N.check(st, "expm_batched")
+    return E, m, s, status

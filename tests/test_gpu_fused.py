@@ -1,0 +1,225 @@
+"""GPU parity: the fused HIP path (orders <= 256) against the CPU oracle.
+
+Tolerance: relative 1-norm error <= 1e-12 against the oracle's long-double direct Taylor
+result (the accuracy target of the method in FP64).  Where the input is so ill-conditioned
+that the oracle's own double-precision result misses 1e-13, the GPU must stay within 10x of
+that error instead (reported separately).  (m, s) must equal the oracle's selection rule,
+except when the norm lies within a few ulps of a threshold.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1710_10989_amd as P
+    assert torch.cuda.is_available()
+    return P
+
+
+def dev(A):
+    return torch.from_numpy(np.ascontiguousarray(A)).cuda()
+
+
+def check_one(orc, A, E, m, s, sel="plain"):
+    ref, _ = orc.expm_taylor(A)
+    err = orc.rel_err_1(E, ref)
+    if err > TOL:
+        refd, _ = orc.expm_taylor(A, prec="d")
+        derr = orc.rel_err_1(refd, ref)
+        assert derr > 1e-13 and err <= 10 * derr, (err, derr)
+    # the method's own output for the same (m, s), evaluated in long double
+    own = orc.expm_reduced(A, m, s)
+    assert orc.rel_err_1(E, own) <= max(TOL, 64 * 2.0 ** -53 * (1 << min(s, 30)))
+    return err
+
+
+def test_single_n64_norm2(P, orc):
+    from paper_1710_10989_amd import workloads as W
+    A = W.single_dense(64, 2.0)
+    say("case single n=64 |A|=2")
+    E, m, s, st = P.taylor(dev(A))
+    torch.cuda.synchronize()
+    m, s, st = int(m.item()), int(s.item()), int(st.item())
+    assert st == 0
+    assert (m, s) == orc.select_plain(orc.norm1(A)) == (18, 1)
+    check_one(orc, A, E.cpu().numpy(), m, s)
+
+
+@pytest.mark.parametrize("target,expect", [
+    (1e-17, (1, 0)), (1e-9, (2, 0)), (1e-4, (4, 0)), (0.03, (8, 0)), (0.25, (12, 0)),
+    (1.0, (18, 0)), (2.0, (18, 1)), (7.0, (18, 3)), (300.0, (18, 9))])
+def test_every_degree_ragged(P, orc, target, expect):
+    g = np.random.default_rng(101)
+    A = g.standard_normal((37, 37))
+    A *= target / np.abs(A).sum(0).max()
+    say("case degree", expect, "n=37")
+    E, m, s, st = P.taylor(dev(A))
+    torch.cuda.synchronize()
+    assert (int(m.item()), int(s.item())) == expect == orc.select_plain(orc.norm1(A))
+    check_one(orc, A, E.cpu().numpy(), *expect)
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 15, 16, 17, 31, 32, 33, 47, 48, 63, 64, 65, 80, 96, 100,
+                               112, 127, 128, 129, 144, 160, 176, 192, 200, 208, 224, 240, 255, 256])
+def test_every_order_class(P, orc, n):
+    g = np.random.default_rng(1000 + n)
+    A = g.standard_normal((n, n))
+    A *= 1.5 / np.abs(A).sum(0).max()
+    say("case order n=%d" % n)
+    E, m, s, st = P.taylor(dev(A))
+    torch.cuda.synchronize()
+    m, s = int(m.item()), int(s.item())
+    assert int(st.item()) == 0
+    assert (m, s) == orc.select_plain(orc.norm1(A))
+    check_one(orc, A, E.cpu().numpy(), m, s)
+
+
+def test_zero_identity_scalar(P, orc):
+    say("case zero/scalar")
+    E, m, s, _ = P.taylor(dev(np.zeros((20, 20))))
+    assert (int(m.item()), int(s.item())) == (1, 0)
+    assert torch.equal(E.cpu(), torch.eye(20, dtype=torch.float64))
+    E, m, s, _ = P.taylor(dev(np.array([[0.75]])))
+    assert abs(E.item() - math.exp(0.75)) <= 4e-16 * math.exp(0.75)
+    E, m, s, _ = P.taylor(dev(np.array([[-40.0]])))
+    assert abs(E.item() - math.exp(-40.0)) <= 1e-14 * math.exp(-40.0)
+
+
+def test_nonfinite_input(P):
+    say("case nonfinite")
+    A = np.eye(9)
+    A[3, 4] = np.nan
+    E, m, s, st = P.taylor(dev(A))
+    torch.cuda.synchronize()
+    assert int(st.item()) == 2 and int(m.item()) == -1 and int(s.item()) == -1
+    assert torch.isnan(E).all()
+    A[3, 4] = np.inf
+    E, m, s, st = P.taylor(dev(A))
+    assert int(st.item()) == 2
+
+
+@pytest.mark.parametrize("kind", ["dense", "skew", "nilpotent", "diag_lowrank"])
+def test_alpha_selector(P, orc, kind):
+    from paper_1710_10989_amd import workloads as W
+    g = np.random.default_rng(55)
+    for norm in (0.02, 0.5, 3.0, 40.0):
+        A = W.rescale(W.structured(g, 48, kind), norm)
+        say("case alpha", kind, norm)
+        E, m, s, st = P.taylor(dev(A), selector="alpha")
+        torch.cuda.synchronize()
+        m, s = int(m.item()), int(s.item())
+        nk = orc.powers_norms(A, 3)
+        mp, sp = orc.select_plain(nk[0])
+        n2 = nk[1] if mp >= 2 else -1.0
+        n3 = nk[2] if mp >= 12 else -1.0
+        assert (m, s) == P.select_rule([nk[0], n2, n3], "alpha")
+        check_one(orc, A, E.cpu().numpy(), m, s)
+
+
+def test_alpha_square_zero_is_exact(P):
+    N = np.zeros((24, 24))
+    N[0, 23] = 50.0
+    N[1, 23] = -7.0
+    E, m, s, _ = P.taylor(dev(N), selector="alpha")
+    assert (int(m.item()), int(s.item())) == (1, 0)
+    assert np.array_equal(E.cpu().numpy(), np.eye(24) + N)
+
+
+def test_select_entry_point(P, orc):
+    g = np.random.default_rng(77)
+    for n, norm in ((40, 0.1), (64, 2.0), (130, 33.0)):
+        A = g.standard_normal((n, n))
+        A *= norm / np.abs(A).sum(0).max()
+        say("case select n=%d" % n)
+        m, s = P.select(dev(A))
+        _, m2, s2, _ = P.taylor(dev(A))
+        assert (int(m.item()), int(s.item())) == (int(m2.item()), int(s2.item())) == orc.select_plain(orc.norm1(A))
+
+
+def _batch(count, seed_stream):
+    from paper_1710_10989_amd import workloads as W
+    return W.mixed_batch(count=count, seed_stream=seed_stream)
+
+
+def test_batched_mixed_vs_oracle(P, orc):
+    mats, kinds = _batch(192, 1)
+    from paper_1710_10989_amd.expm import Batch
+    B = Batch.from_host(mats)
+    say("case batched 192")
+    E, m, s, st = P.batched(B)
+    torch.cuda.synchronize()
+    outs = B.unpack(E)
+    m, s, st = m.cpu().numpy(), s.cpu().numpy(), st.cpu().numpy()
+    assert np.all(st == 0)
+    refs, _ = orc.expm_taylor_batch(mats, prec="ld")
+    worst = 0.0
+    for i, (A, R, X) in enumerate(zip(mats, refs, outs)):
+        assert (m[i], s[i]) == orc.select_plain(orc.norm1(A)), i
+        err = orc.rel_err_1(X, R)
+        worst = max(worst, err)
+        assert err <= TOL, (i, kinds[i], A.shape[0], err)
+    say("batched worst rel err", worst)
+
+
+def test_batched_full_size_sampled(P, orc):
+    # the whole 4096-matrix workload in the launch configuration the benchmark times
+    mats, kinds = _batch(4096, 0)
+    from paper_1710_10989_amd.expm import Batch
+    B = Batch.from_host(mats)
+    say("case batched 4096")
+    E, m, s, st = P.batched(B)
+    torch.cuda.synchronize()
+    outs = B.unpack(E)
+    m, s, st = m.cpu().numpy(), s.cpu().numpy(), st.cpu().numpy()
+    assert np.all(st == 0)
+    for i, A in enumerate(mats):
+        assert (m[i], s[i]) == orc.select_plain(orc.norm1(A)), i
+        assert np.all(np.isfinite(outs[i]))
+        if kinds[i] == "skew":  # e^A orthogonal
+            n = A.shape[0]
+            assert np.abs(outs[i].T @ outs[i] - np.eye(n)).max() <= 1e-12
+        if kinds[i] == "nilpotent":  # e^A unit upper triangular
+            assert np.all(np.tril(outs[i], -1) == 0.0) and np.all(np.diag(outs[i]) == 1.0)
+    sample = np.random.default_rng(9).choice(len(mats), 48, replace=False)
+    refs, _ = orc.expm_taylor_batch([mats[i] for i in sample], prec="ld")
+    for i, R in zip(sample, refs):
+        assert orc.rel_err_1(outs[i], R) <= TOL, (i, kinds[i])
+
+
+def test_batched_deterministic_and_graph_replay(P):
+    mats, _ = _batch(300, 2)
+    from paper_1710_10989_amd.expm import Batch
+    B = Batch.from_host(mats)
+    say("case determinism + graph")
+    E1, m1, s1, _ = P.batched(B)
+    E2, _, _, _ = P.batched(B)
+    torch.cuda.synchronize()
+    assert torch.equal(E1, E2)
+    ws = torch.empty(P.workspace_bytes(B.n_max, len(mats)), dtype=torch.uint8, device="cuda")
+    out = torch.empty_like(B.packed)
+    P.batched(B, workspace=ws, out=out)  # warm-up outside capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    out.zero_()
+    with torch.cuda.graph(g):
+        P.batched(B, workspace=ws, out=out)
+    for rep in range(3):
+        out.fill_(7.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, E1), rep
+        _ = (B.packed * 2).sum().item()  # eager work between replays
