@@ -19,6 +19,7 @@ constexpr int kMaxSlots = 1024;         // upper bound on resident fused workgro
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 int64_t pad16(int64_t n) { return (n + 15) & ~int64_t(15); }
+int np_max_t(int64_t n) { return (int)(pad16(n) >> 4); }
 
 double default_u(int prec) { return prec == EXPM_PREC_FP64 ? 0x1p-53 : 0x1p-24; }
 
@@ -34,27 +35,40 @@ expm_status_t check_opts(const expm_opts_t *o, double *u) {
   return EXPM_OK;
 }
 
-// Slots of the fused kernel for a batch: one per resident workgroup, capped by the batch.
-int fused_slots(int64_t batch) {
-  static int cap = -1;
+// Resident workgroups of the two fused kernels on the current device (cached).
+struct FusedCaps {
+  int cus = 0, per4 = 1, per8 = 1;
+};
+
+FusedCaps fused_caps() {
+  static FusedCaps caps;
+  static bool init = false;
   static std::mutex mu;
   std::lock_guard<std::mutex> lk(mu);
-  if (cap < 0) {
+  if (!init) {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0) {
-      int per = fused_max_blocks_per_cu();
-      cap = cus * per;
-      if (cap > kMaxSlots) cap = kMaxSlots;
+      caps.cus = cus;
+      caps.per4 = fused_max_blocks_per_cu(4);
+      caps.per8 = fused_max_blocks_per_cu(8);
+      init = true;
     } else {
-      cap = kMaxSlots;  // no device visible: size for the largest launch
+      caps.cus = 0;  // no device visible: size for the largest launch, do not cache
     }
   }
+  return caps;
+}
+
+int grid_for(int nw, int64_t batch) {
+  FusedCaps c = fused_caps();
+  int cap = c.cus > 0 ? c.cus * (nw == 8 ? c.per8 : c.per4) : kMaxSlots;
+  if (cap > kMaxSlots) cap = kMaxSlots;
   return (int)(batch < cap ? batch : cap);
 }
 
 struct FusedLayout {
-  size_t counter_off, order_off, slots_off, total;
+  size_t queue_off, order_off, slots_off, total;
   size_t slot_doubles;
   int slots;
 };
@@ -62,9 +76,10 @@ struct FusedLayout {
 FusedLayout fused_layout(int64_t n_max, int64_t batch) {
   FusedLayout L;
   const int64_t np = pad16(n_max);
-  L.slots = fused_slots(batch);
+  const int g4 = grid_for(4, batch), g8 = grid_for(8, batch);
+  L.slots = g4 > g8 ? g4 : g8;
   L.slot_doubles = (size_t)kFusedBufs * np * np;
-  L.counter_off = 0;
+  L.queue_off = 0;
   L.order_off = kAlign;
   L.slots_off = L.order_off + align_up(sizeof(int32_t) * (size_t)batch);
   L.total = L.slots_off + (size_t)L.slots * L.slot_doubles * sizeof(double);
@@ -143,10 +158,17 @@ static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, cons
   hipStream_t st = (hipStream_t)stream;
   if (ns) {
     a.order = (const int32_t *)(base + L.order_off);
-    a.counter = (unsigned long long *)(base + L.counter_off);
-    if (launch_order(ns, batch, (int32_t *)a.order, a.counter, st) != hipSuccess) return EXPM_E_HIP;
+    a.queue = (unsigned long long *)(base + L.queue_off);
+    if (launch_order(ns, batch, (int32_t *)a.order, a.queue, st) != hipSuccess) return EXPM_E_HIP;
+    // largest orders first: the 8-wave kernel drains the front of the queue, then the 4-wave
+    // kernel the rest (either range may be empty)
+    if (np_max_t(n_max) >= kSplitT && launch_fused(a, 8, grid_for(8, batch), st) != hipSuccess) return EXPM_E_HIP;
+    if (launch_fused(a, 4, grid_for(4, batch), st) != hipSuccess) return EXPM_E_HIP;
+  } else {
+    const bool big = np_max_t(n_uniform) >= kSplitT;
+    a.split = big ? batch : 0;
+    if (launch_fused(a, big ? 8 : 4, grid_for(big ? 8 : 4, batch), st) != hipSuccess) return EXPM_E_HIP;
   }
-  if (launch_fused(a, L.slots, st) != hipSuccess) return EXPM_E_HIP;
   return EXPM_OK;
 }
 

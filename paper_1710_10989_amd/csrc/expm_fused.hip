@@ -1,14 +1,17 @@
-// Persistent fused kernel: e^A for matrices of order n <= 256, one workgroup per matrix.
+// Persistent fused kernels: e^A for matrices of order n <= 256, one workgroup per matrix.
 //
 // Each workgroup pops matrices from a device work queue (largest order first) and runs the
 // whole method for it: copy A into a zero-padded np x np buffer (np = n rounded up to 16)
-// while taking the 1-norm, choose (m, s), form the powers A^2, A^3 (A^6) with MFMA GEMMs,
-// build the linear combinations of the product-reduced sequence in GEMM epilogues, run the
+// while taking the 1-norm, choose (m, s), form the powers A^2, A^3 with MFMA GEMMs, build
+// the linear combinations of the product-reduced sequence in GEMM epilogues, run the
 // product stage and the s squarings, and write e^A.  Zero padding is exact: every polynomial
 // in the padded matrix is block diagonal, so the leading n x n block is p(A).
 //
 // Scaling (Sec. 1, eq. eses) is folded into the coefficients: X^k = 2^(-sk) A^k, so the
 // stored powers are those of A and no pass rescales a matrix.
+//
+// Two instantiations: 8 waves (orders 80..256, one workgroup per CU) take the front of the
+// queue, 4 waves (orders up to 64, two workgroups per CU) take the rest.
 //
 // Workspace: one slot of 8 np_max^2 doubles per resident workgroup; a matrix of order n uses
 // the first 8 np^2 doubles of its workgroup's slot.
@@ -26,21 +29,23 @@ namespace {
 constexpr int kBufs = kFusedBufs;
 
 // Column sums of |B| over an np x np buffer (thread j owns column j), reduced to the maximum.
+template <int NT>
 __device__ double block_norm1(const double *B, int np, double *red) {
   const int tid = threadIdx.x;
   double s = 0.0;
   if (tid < np) {
-    int i = 0;
-    for (; i + 4 <= np; i += 4) {
-      double v0 = B[(size_t)(i + 0) * np + tid], v1 = B[(size_t)(i + 1) * np + tid];
-      double v2 = B[(size_t)(i + 2) * np + tid], v3 = B[(size_t)(i + 3) * np + tid];
-      s += fabs(v0); s += fabs(v1); s += fabs(v2); s += fabs(v3);
+    cgdouble *Bg = gptr(B);
+    for (int i = 0; i < np; i += 16) {  // np is a multiple of 16: 16 loads in flight
+      double v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v[u] = Bg[(i + u) * np + tid];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) s += fabs(v[u]);
     }
-    for (; i < np; ++i) s += fabs(B[(size_t)i * np + tid]);
   }
   red[tid] = s;
   __syncthreads();
-  for (int w = kThreads / 2; w > 0; w >>= 1) {
+  for (int w = NT / 2; w > 0; w >>= 1) {
     if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
     __syncthreads();
   }
@@ -49,13 +54,32 @@ __device__ double block_norm1(const double *B, int np, double *red) {
   return r;
 }
 
-// Elementwise pass over the np x np index space.
-template <class F>
-__device__ void for_each_elem(int np, const F &f) {
+// Elementwise pass over the np x np index space: each thread gathers the NIN inputs of
+// kEpiU elements before computing, then calls f(row, col, e, x).
+template <int NT, int NIN, class F>
+__device__ void for_each_elem(int np, const double *const (&inp)[NIN], const F &f) {
   const int total = np * np;
-  for (int e = threadIdx.x; e < total; e += kThreads) {
-    const int row = e / np, col = e - row * np;
-    f(row, col, e);
+  cgdouble *in[NIN];
+#pragma unroll
+  for (int k = 0; k < NIN; ++k) in[k] = gptr(inp[k]);
+  for (int base = threadIdx.x; base < total; base += NT * kEpiU) {
+    double x[kEpiU][NIN];
+#pragma unroll
+    for (int u = 0; u < kEpiU; ++u) {
+      const int e = base + u * NT;
+      if (e < total) {
+#pragma unroll
+        for (int k = 0; k < NIN; ++k) x[u][k] = in[k][e];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kEpiU; ++u) {
+      const int e = base + u * NT;
+      if (e < total) {
+        const int row = e / np, col = e - row * np;
+        f(row, col, e, x[u]);
+      }
+    }
   }
   __syncthreads();
 }
@@ -104,19 +128,22 @@ __device__ void make_coefs(const Consts &k, int m, int s) {
 __shared__ int sh_ms[2];
 
 // One GEMM step: thread 0 fills the LDS descriptor through `set`, then all threads run it.
-template <class S>
+template <int NW, class S>
 __device__ void gemm_step(const S &set) {
   if (threadIdx.x == 0) set(g_ep);
   __syncthreads();
-  gemm_block();
+  gemm_block<NW>();
+  __syncthreads();
 }
 
 __device__ void put_out(double *p, int ld, int nvalid, int r, int cc, double v) {
-  if (r < nvalid && cc < nvalid) p[(size_t)r * ld + cc] = v;
+  if (r < nvalid && cc < nvalid) p[r * ld + cc] = v;
 }
 
 // Runs the method on one matrix.
+template <int NW>
 __device__ void run_one(const FusedArgs &a, int64_t b, double *slot, double *red) {
+  constexpr int NT = 64 * NW;
   const int tid = threadIdx.x;
   const int n = a.ns ? a.ns[b] : a.n_uniform;
   const int64_t off = a.offs ? a.offs[b] : b * (int64_t)n * n;
@@ -138,18 +165,24 @@ __device__ void run_one(const FusedArgs &a, int64_t b, double *slot, double *red
   double colsum = 0.0;
   int bad = 0;
   if (tid < np) {
-    for (int i = 0; i < np; ++i) {
-      double v = 0.0;
-      if (i < n && tid < n) v = A[(size_t)i * n + tid];
-      bad |= !isfinite(v);
-      colsum += fabs(v);
-      buf[0][(size_t)i * np + tid] = v;
+    cgdouble *Ag = gptr(A);
+    gdouble *B0g = gptr(buf[0]);
+    for (int i = 0; i < np; i += 16) {  // 16 loads in flight, then 16 stores
+      double v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v[u] = (i + u < n && tid < n) ? Ag[(size_t)(i + u) * n + tid] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        bad |= !isfinite(v[u]);
+        colsum += fabs(v[u]);
+        B0g[(i + u) * np + tid] = v[u];
+      }
     }
   }
   bad = __syncthreads_or(bad);
   red[tid] = colsum;
   __syncthreads();
-  for (int w = kThreads / 2; w > 0; w >>= 1) {
+  for (int w = NT / 2; w > 0; w >>= 1) {
     if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
     __syncthreads();
   }
@@ -157,7 +190,7 @@ __device__ void run_one(const FusedArgs &a, int64_t b, double *slot, double *red
   __syncthreads();
 
   if (bad) {
-    if (E) for (int e = tid; e < n * n; e += kThreads) E[e] = __builtin_nan("");
+    if (E) for (int e = tid; e < n * n; e += NT) E[e] = __builtin_nan("");
     if (tid == 0) {
       a.m_out[b] = -1; a.s_out[b] = -1;
       if (a.status) a.status[b] = EXPM_E_NONFINITE;
@@ -174,18 +207,18 @@ __device__ void run_one(const FusedArgs &a, int64_t b, double *slot, double *red
   const bool want_alpha = (a.sel == EXPM_SEL_ALPHA);
   double n2 = -1.0, n3 = -1.0;
   if (m_plain >= 2) {
-    gemm_step([&](EpiDesc &d) {
+    gemm_step<NW>([&](EpiDesc &d) {
       d.P = buf[0]; d.Q = buf[0]; d.kind = EK_STORE; d.np = np;
       d.dst = buf[1]; d.dst_ld = np; d.dst_nvalid = np;
     });
-    if (want_alpha) n2 = block_norm1(buf[1], np, red);
+    if (want_alpha) n2 = block_norm1<NT>(buf[1], np, red);
   }
   if (m_plain >= 12) {
-    gemm_step([&](EpiDesc &d) {
+    gemm_step<NW>([&](EpiDesc &d) {
       d.P = buf[1]; d.Q = buf[0]; d.kind = EK_STORE; d.np = np;
       d.dst = buf[2]; d.dst_ld = np; d.dst_nvalid = np;
     });
-    if (want_alpha) n3 = block_norm1(buf[2], np, red);
+    if (want_alpha) n3 = block_norm1<NT>(buf[2], np, red);
   }
   if (want_alpha && m_plain >= 2) {
     if (tid == 0) select_ms(a.k.theta, 1, eta, n2, n3, &sh_ms[0], &sh_ms[1]);
@@ -212,30 +245,39 @@ __device__ void run_one(const FusedArgs &a, int64_t b, double *slot, double *red
 
   if (m == 1) {
     const double c0 = c[0];
-    for_each_elem(np, [&](int r, int cc, int e) { put_out(Tp, Tld, Tnv, r, cc, (r == cc ? 1.0 : 0.0) + c0 * B0[e]); });
+    const double *in[1] = {B0};
+    for_each_elem<NT, 1>(np, in, [&](int r, int cc, int, const double *x) {
+      put_out(Tp, Tld, Tnv, r, cc, (r == cc ? 1.0 : 0.0) + c0 * x[0]);
+    });
   } else if (m == 2) {
     const double c0 = c[0], c1 = c[1];
-    for_each_elem(np, [&](int r, int cc, int e) {
-      put_out(Tp, Tld, Tnv, r, cc, (r == cc ? 1.0 : 0.0) + c0 * B0[e] + c1 * B1[e]);
+    const double *in[2] = {B0, B1};
+    for_each_elem<NT, 2>(np, in, [&](int r, int cc, int, const double *x) {
+      put_out(Tp, Tld, Tnv, r, cc, (r == cc ? 1.0 : 0.0) + c0 * x[0] + c1 * x[1]);
     });
   } else if (m == 4) {
     double *W = buf[2];
     const double c2 = c[2], c3 = c[3], c4 = c[4];
-    for_each_elem(np, [&](int r, int cc, int e) { W[e] = (r == cc ? c2 : 0.0) + c3 * B0[e] + c4 * B1[e]; });
-    gemm_step([&](EpiDesc &d) { base(d); d.P = B1; d.Q = W; d.kind = EK_M4; });
+    const double *in[2] = {B0, B1};
+    for_each_elem<NT, 2>(np, in, [&](int r, int cc, int e, const double *x) {
+      W[e] = (r == cc ? c2 : 0.0) + c3 * x[0] + c4 * x[1];
+    });
+    gemm_step<NW>([&](EpiDesc &d) { base(d); d.P = B1; d.Q = W; d.kind = EK_M4; });
   } else if (m == 8) {
     double *W1 = buf[2], *L = buf[3], *Rm = buf[4];
     const double c0 = c[0], c1 = c[1];
-    for_each_elem(np, [&](int, int, int e) { W1[e] = c0 * B0[e] + c1 * B1[e]; });
-    gemm_step([&](EpiDesc &d) { base(d); d.P = B1; d.Q = W1; d.kind = EK_M8A; d.o[0] = L; d.o[1] = Rm; });
-    gemm_step([&](EpiDesc &d) { base(d); d.P = L; d.Q = Rm; d.kind = EK_M8B; });
+    const double *in[2] = {B0, B1};
+    for_each_elem<NT, 2>(np, in, [&](int, int, int e, const double *x) { W1[e] = c0 * x[0] + c1 * x[1]; });
+    gemm_step<NW>([&](EpiDesc &d) { base(d); d.P = B1; d.Q = W1; d.kind = EK_M8A; d.o[0] = L; d.o[1] = Rm; });
+    gemm_step<NW>([&](EpiDesc &d) { base(d); d.P = L; d.Q = Rm; d.kind = EK_M8B; });
   } else if (m == 12) {
     double *Bq0 = buf[3], *Bq1 = buf[4], *Bq2 = buf[5], *Bq3 = buf[6];
     double cf[16];
     for (int i = 0; i < 16; ++i) cf[i] = c[i];
-    for_each_elem(np, [&](int r, int cc, int e) {
+    const double *in[3] = {B0, B1, B2};
+    for_each_elem<NT, 3>(np, in, [&](int r, int cc, int e, const double *x) {
       const double id = (r == cc) ? 1.0 : 0.0;
-      const double x1 = B0[e], x2 = B1[e], x3 = B2[e];
+      const double x1 = x[0], x2 = x[1], x3 = x[2];
       Bq0[e] = cf[0] * id + cf[1] * x1 + cf[2] * x2 + cf[3] * x3;
       Bq1[e] = cf[4] * id + cf[5] * x1 + cf[6] * x2 + cf[7] * x3;
       Bq2[e] = cf[8] * id + cf[9] * x1 + cf[10] * x2 + cf[11] * x3;
@@ -243,25 +285,25 @@ __device__ void run_one(const FusedArgs &a, int64_t b, double *slot, double *red
     });
     double *A6 = buf[0], *Y = buf[1];
     // A_6 = B_3 + B_4^2 ; Y = B_2 + A_6
-    gemm_step([&](EpiDesc &d) {
+    gemm_step<NW>([&](EpiDesc &d) {
       base(d); d.P = Bq3; d.Q = Bq3; d.kind = EK_SPLIT2; d.in0 = Bq2; d.in1 = Bq1; d.o[0] = A6; d.o[1] = Y;
     });
     // T_12 = B_1 + Y A_6
-    gemm_step([&](EpiDesc &d) { base(d); d.P = Y; d.Q = A6; d.kind = EK_ADD1; d.in0 = Bq0; });
+    gemm_step<NW>([&](EpiDesc &d) { base(d); d.P = Y; d.Q = A6; d.kind = EK_ADD1; d.in0 = Bq0; });
   } else {  // m == 18
     double *Bq[5] = {buf[3], buf[4], buf[5], buf[6], buf[7]};
     // A^6 = A^3 A^3; the epilogue forms B_1..B_5 from (I, A, A^2, A^3, A^6)
-    gemm_step([&](EpiDesc &d) {
+    gemm_step<NW>([&](EpiDesc &d) {
       base(d); d.P = B2; d.Q = B2; d.kind = EK_M18A;
       for (int j = 0; j < 5; ++j) d.o[j] = Bq[j];
     });
     double *A9 = buf[0], *Y = buf[1];
     // A_9 = B_1 B_5 + B_4 ; Y = B_3 + A_9
-    gemm_step([&](EpiDesc &d) {
+    gemm_step<NW>([&](EpiDesc &d) {
       base(d); d.P = Bq[0]; d.Q = Bq[4]; d.kind = EK_SPLIT2; d.in0 = Bq[3]; d.in1 = Bq[2]; d.o[0] = A9; d.o[1] = Y;
     });
     // T_18 = B_2 + Y A_9
-    gemm_step([&](EpiDesc &d) { base(d); d.P = Y; d.Q = A9; d.kind = EK_ADD1; d.in0 = Bq[1]; });
+    gemm_step<NW>([&](EpiDesc &d) { base(d); d.P = Y; d.Q = A9; d.kind = EK_ADD1; d.in0 = Bq[1]; });
   }
 
   // ---- s squarings, ping-pong between buffers tb and tb^1 ----
@@ -269,7 +311,7 @@ __device__ void run_one(const FusedArgs &a, int64_t b, double *slot, double *red
   for (int rsq = 1; rsq <= s; ++rsq) {
     const int nxt = cur ^ 1;
     const bool last = (rsq == s);
-    gemm_step([&](EpiDesc &d) {
+    gemm_step<NW>([&](EpiDesc &d) {
       d.np = np; d.P = buf[cur]; d.Q = buf[cur]; d.kind = EK_STORE;
       d.dst = last ? E : buf[nxt]; d.dst_ld = last ? n : np; d.dst_nvalid = last ? n : np;
     });
@@ -279,33 +321,37 @@ __device__ void run_one(const FusedArgs &a, int64_t b, double *slot, double *red
 
 }  // namespace
 
-__global__ __launch_bounds__(kThreads, 2) void expm_fused_kernel(FusedArgs a) {
-  __shared__ double red[kThreads];
+// Queue ranges: the 8-wave kernel serves queue entries [0, split), the 4-wave kernel
+// [split, batch); split = q[2] written by the order kernel (uniform batches: set by the host).
+template <int NW>
+__global__ __launch_bounds__(64 * NW, NW == 4 ? 2 : 1) void expm_fused_kernel(FusedArgs a) {
+  __shared__ double red[64 * NW];
   __shared__ int64_t sh_idx;
+  const int64_t lo = NW == 8 ? 0 : (a.queue ? (int64_t)a.queue[2] : a.split);
+  const int64_t hi = NW == 8 ? (a.queue ? (int64_t)a.queue[2] : a.split) : a.batch;
   double *slot = a.slots + (size_t)blockIdx.x * a.slot_doubles;
-  for (int64_t it = blockIdx.x;; it += gridDim.x) {
+  for (int64_t it = lo + blockIdx.x;; it += gridDim.x) {
     int64_t idx = it;
-    if (a.counter) {
-      if (threadIdx.x == 0) sh_idx = (int64_t)atomicAdd(a.counter, 1ull);
+    if (a.queue) {
+      if (threadIdx.x == 0) sh_idx = lo + (int64_t)atomicAdd(&a.queue[NW == 8 ? 0 : 1], 1ull);
       __syncthreads();
       idx = sh_idx;
       __syncthreads();
     }
-    if (idx >= a.batch) break;
+    if (idx >= hi) break;
     const int64_t b = a.order ? a.order[idx] : idx;
-    run_one(a, b, slot, red);
+    run_one<NW>(a, b, slot, red);
     __syncthreads();
   }
 }
 
-// Counting sort of the batch by padded order, largest first (the work-queue order), and
-// reset of the queue counter.  One workgroup.
+// Counting sort of the batch by padded order, largest first (the work-queue order); resets
+// both queue counters and records the split between the two kernels.  One workgroup.
 __global__ void expm_order_kernel(const int32_t *ns, int64_t batch, int32_t *order,
-                                  unsigned long long *counter) {
+                                  unsigned long long *queue) {
   __shared__ int hist[18], start[18];
   const int tid = threadIdx.x;
   if (tid < 18) hist[tid] = 0;
-  if (tid == 0) *counter = 0ull;
   __syncthreads();
   auto key = [&](int64_t b) {
     const int n = ns[b];
@@ -317,6 +363,9 @@ __global__ void expm_order_kernel(const int32_t *ns, int64_t batch, int32_t *ord
   if (tid == 0) {
     int acc = 0;
     for (int i = 0; i < 18; ++i) { start[i] = acc; acc += hist[i]; }
+    queue[0] = 0ull;
+    queue[1] = 0ull;
+    queue[2] = (unsigned long long)start[16 - kSplitT + 1];  // entries with T >= kSplitT
   }
   __syncthreads();
   for (int64_t b = tid; b < batch; b += blockDim.x) {
@@ -325,21 +374,24 @@ __global__ void expm_order_kernel(const int32_t *ns, int64_t batch, int32_t *ord
   }
 }
 
-int fused_max_blocks_per_cu() {
+int fused_max_blocks_per_cu(int nw) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, expm_fused_kernel, kThreads, 0) != hipSuccess)
-    return 1;
+  hipError_t e = nw == 8
+      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, expm_fused_kernel<8>, 512, 0)
+      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, expm_fused_kernel<4>, 256, 0);
+  if (e != hipSuccess) return 1;
   return nb < 1 ? 1 : nb;
 }
 
-hipError_t launch_fused(const FusedArgs &a, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(expm_fused_kernel, dim3(grid), dim3(kThreads), 0, st, a);
+hipError_t launch_fused(const FusedArgs &a, int nw, int grid, hipStream_t st) {
+  if (nw == 8) hipLaunchKernelGGL(expm_fused_kernel<8>, dim3(grid), dim3(512), 0, st, a);
+  else hipLaunchKernelGGL(expm_fused_kernel<4>, dim3(grid), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
 hipError_t launch_order(const int32_t *ns, int64_t batch, int32_t *order,
-                        unsigned long long *counter, hipStream_t st) {
-  hipLaunchKernelGGL(expm_order_kernel, dim3(1), dim3(1024), 0, st, ns, batch, order, counter);
+                        unsigned long long *queue, hipStream_t st) {
+  hipLaunchKernelGGL(expm_order_kernel, dim3(1), dim3(1024), 0, st, ns, batch, order, queue);
   return hipGetLastError();
 }
 

@@ -1,68 +1,27 @@
-// Workgroup-level FP64 MFMA GEMM for matrices resident in device memory (order np = 16 T,
-// T = 1..16): C = P * Q, with a fused elementwise epilogue chosen at run time.
+// Workgroup-level FP64 GEMM for matrices resident in device memory (order np = 16 T,
+// T = 1..16): C = P * Q, followed by a fused elementwise epilogue chosen at run time.
 //
-// Decomposition (compile time per T).  The output is a T x T grid of 16 x 16 tiles.  The four
-// waves form a WR x WC grid; each wave owns a BR x BC block of tiles, so one "chunk" covers
-// (WR BR) x (WC BC) tiles and the chunks are walked in row-major order.  A wave whose block
-// lies entirely outside the matrix skips the arithmetic (wave-uniform branch); tiles of a
-// partially covered block are computed on clamped indices and never stored.
+// Two workgroup shapes share the code: NW = 4 waves (orders up to 64, several workgroups
+// per CU) and NW = 8 waves (orders 80..256, one workgroup per CU, chunks of 96 x 128 or
+// 128 x 128).  For each
+// order class T the chunk and wave decomposition is fixed at compile time (TileFor); the
+// K loop is the direct-to-LDS pipeline of tile_gemm.h.
 //
-// Data path.  For every chunk the K dimension is walked in panels of 16: the P panel
-// (chunk rows x 16) and the Q panel (16 x chunk columns) are loaded from global memory into
-// registers one panel ahead (software prefetch), written to LDS, and consumed by
-// v_mfma_f64_16x16x4_f64.  Per 4-wide k step a wave reads BR A-fragments and BC B-fragments
-// from LDS for BR * BC MFMAs.  At the end of the chunk the accumulators are written to an
-// LDS copy of the chunk (sharing the panel storage), and the epilogue walks that copy with
-// consecutive threads on consecutive columns, so its global reads and writes are coalesced
-// and it holds no accumulator registers.
+// Epilogues.  A plain product (EK_STORE) is stored from the accumulators: lanes 0..15 of a
+// register cover 16 consecutive columns of one row.  Every other kind first copies the chunk
+// of C into LDS and then walks it with consecutive threads on consecutive columns; each thread
+// gathers the global inputs of 8 elements before computing, so the loads overlap.
 //
-// The operands, the epilogue kind and its arguments come from the workgroup's LDS
-// descriptor g_ep, filled before the call.  All LDS objects are file-scope __shared__
-// variables so every access compiles to ds_read / ds_write even in outlined functions.
-//
-// MFMA operand layout (gfx950, 16x16x4 f64): lane l supplies A[l % 16][l / 16] and
-// B[l / 16][l % 16]; accumulator register r of lane l holds D[4 r + l / 16][l % 16].
+// The operands, the epilogue kind and its arguments come from the LDS descriptor g_ep, filled
+// by thread 0 before the call.  LDS objects are file-scope so every access stays ds_*.
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "tile_gemm.h"
+
 namespace expm {
 
-typedef double dbl4 __attribute__((ext_vector_type(4)));
-// Pointers read back from the LDS descriptor are generic; casting them to the global address
-// space lets the compiler emit global_load / global_store instead of flat accesses.
-typedef __attribute__((address_space(1))) double gdouble;
-typedef __attribute__((address_space(1))) const double cgdouble;
-typedef double dv2 __attribute__((ext_vector_type(2)));
-typedef __attribute__((address_space(1))) const dv2 cgdv2;
-__device__ inline gdouble *gptr(double *p) { return (gdouble *)p; }
-__device__ inline cgdouble *gptr(const double *p) { return (cgdouble *)p; }
-
-constexpr int kThreads = 256;  // four wave64s
-constexpr int kKP = 16;        // K panel width
 constexpr int kNpMax = 256;
-
-template <int T> struct TileCfg { static constexpr int WR = 2, WC = 2, BR = 2, BC = 4; };
-template <> struct TileCfg<1> { static constexpr int WR = 1, WC = 1, BR = 1, BC = 1; };
-template <> struct TileCfg<2> { static constexpr int WR = 2, WC = 2, BR = 1, BC = 1; };
-template <> struct TileCfg<3> { static constexpr int WR = 4, WC = 1, BR = 1, BC = 3; };
-template <> struct TileCfg<4> { static constexpr int WR = 2, WC = 2, BR = 2, BC = 2; };
-template <> struct TileCfg<5> { static constexpr int WR = 4, WC = 1, BR = 1, BC = 5; };
-template <> struct TileCfg<6> { static constexpr int WR = 2, WC = 2, BR = 3, BC = 3; };
-template <> struct TileCfg<7> { static constexpr int WR = 4, WC = 1, BR = 1, BC = 7; };
-
-// LDS: panels (P <= 96 rows x (16 + 1), Q 16 x (<= 128 + 1)) or, after the K loop, the chunk
-// of C (<= 96 x (96 + 1) or 64 x (128 + 1)).  The +1 staggers banks.
-constexpr int kLdsP = 96 * (kKP + 1);
-constexpr int kLdsQ = kKP * (128 + 1);
-constexpr int kLdsC = 96 * 97;
-struct GemmPanels {
-  double p[kLdsP];
-  double q[kLdsQ];
-};
-union GemmSmem {
-  GemmPanels pan;
-  double c[kLdsC];
-};
 
 // Epilogue kinds.  v is the product element at (row, col); e = row * np + col indexes the
 // workspace buffers; "id" is the identity element (1 on the diagonal).
@@ -85,236 +44,227 @@ struct EpiDesc {
   double c[64];
 };
 
-__shared__ GemmSmem g_sm;
 __shared__ EpiDesc g_ep;
 
-template <class F>
-__device__ inline void for_chunk(int row0, int col0, int rows, int cols, int ldc, const F &f) {
+// Decomposition per (waves, order class).
+template <int NW, int T> struct TileFor;
+template <> struct TileFor<4, 1> { typedef TileShape<4, 16, 16, 1, 1, 1, 1> S; };
+template <> struct TileFor<4, 2> { typedef TileShape<4, 32, 32, 2, 2, 1, 1> S; };
+template <> struct TileFor<4, 3> { typedef TileShape<4, 48, 48, 3, 1, 1, 3> S; };
+template <> struct TileFor<4, 4> { typedef TileShape<4, 64, 64, 2, 2, 2, 2> S; };
+template <int T> struct TileFor<8, T> { typedef TileShape<8, 128, 128, 4, 2, 2, 4> S; };
+template <> struct TileFor<8, 5> { typedef TileShape<8, 96, 128, 2, 4, 3, 2> S; };
+template <> struct TileFor<8, 6> { typedef TileShape<8, 96, 128, 2, 4, 3, 2> S; };
+
+// LDS pools: the stage ring, reused after the K loop as the chunk copy of C.
+constexpr int kPool4 = 3 * (64 * 16 + 16 * 64);  // 3 stages of 64 x 16 + 16 x 64; >= 64 x (64 + 1)
+constexpr int kPool8 = 128 * 129;   // >= 3 stages of 128 x 16 + 16 x 128, >= 128 x (128 + 1)
+__shared__ double g_pool4[kPool4];
+__shared__ double g_pool8[kPool8];
+template <int NW> __device__ inline double *lds_pool() { return NW == 4 ? g_pool4 : g_pool8; }
+
+// Walks the LDS copy of a chunk (ld ldc) with consecutive threads on consecutive columns.
+// Each thread gathers the NIN global inputs of kEpiU elements before computing.
+constexpr int kEpiU = 8;
+
+template <int NW, int NIN, class F>
+__device__ inline void for_chunk(const double *cbuf, int row0, int col0, int rows, int cols, int ldc,
+                                 int np, cgdouble *const (&in)[NIN > 0 ? NIN : 1], const F &f) {
+  constexpr int NT = 64 * NW;
   const int total = rows * cols;
-  for (int e = threadIdx.x; e < total; e += kThreads) {
-    const int r = e / cols, cc = e - r * cols;
-    f(row0 + r, col0 + cc, g_sm.c[r * ldc + cc]);
+  for (int base = threadIdx.x; base < total; base += NT * kEpiU) {
+    double v[kEpiU], x[kEpiU][NIN > 0 ? NIN : 1];
+    int rr[kEpiU], cc[kEpiU];
+#pragma unroll
+    for (int u = 0; u < kEpiU; ++u) {
+      const int e = base + u * NT;
+      rr[u] = -1;
+      if (e < total) {
+        const int r = e / cols, c = e - r * cols;
+        rr[u] = row0 + r;
+        cc[u] = col0 + c;
+        v[u] = cbuf[r * ldc + c];
+        const int g = rr[u] * np + cc[u];
+#pragma unroll
+        for (int k = 0; k < NIN; ++k) x[u][k] = in[k][g];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kEpiU; ++u)
+      if (rr[u] >= 0) f(rr[u], cc[u], rr[u] * np + cc[u], v[u], x[u]);
   }
 }
 
+template <int NW>
 __device__ inline void run_epilogue(int row0, int col0, int rows, int cols, int ldc) {
+  const double *cbuf = lds_pool<NW>();
   const int np = g_ep.np;
   const double *c = g_ep.c;
   switch (g_ep.kind) {
-    case EK_STORE: {
-      gdouble *dst = gptr(g_ep.dst);
-      const int ld = g_ep.dst_ld, nv = g_ep.dst_nvalid;
-      for_chunk(row0, col0, rows, cols, ldc, [&](int r, int cc, double v) {
-        if (r < nv && cc < nv) dst[(size_t)r * ld + cc] = v;
-      });
-    } break;
     case EK_M4: {
       gdouble *dst = gptr(g_ep.dst);
       const int ld = g_ep.dst_ld, nv = g_ep.dst_nvalid;
-      cgdouble *b0 = gptr(g_ep.b0);
       const double c0 = c[0], c1 = c[1];
-      for_chunk(row0, col0, rows, cols, ldc, [&](int r, int cc, double v) {
-        const size_t e = (size_t)r * np + cc;
-        const double t = (r == cc ? 1.0 : 0.0) + c0 * b0[e] + c1 * v;
-        if (r < nv && cc < nv) dst[(size_t)r * ld + cc] = t;
+      cgdouble *const in[1] = {gptr(g_ep.b0)};
+      for_chunk<NW, 1>(cbuf, row0, col0, rows, cols, ldc, np, in, [&](int r, int cc, int, double v, const double *x) {
+        const double t = (r == cc ? 1.0 : 0.0) + c0 * x[0] + c1 * v;
+        if (r < nv && cc < nv) dst[r * ld + cc] = t;
       });
     } break;
     case EK_M8A: {
-      cgdouble *b0 = gptr(g_ep.b0), *b1 = gptr(g_ep.b1);
       gdouble *o0 = gptr(g_ep.o[0]), *o1 = gptr(g_ep.o[1]);
       const double c2 = c[2], c3 = c[3], c4 = c[4], c5 = c[5], c6 = c[6], c7 = c[7];
-      for_chunk(row0, col0, rows, cols, ldc, [&](int r, int cc, double v) {
-        const size_t e = (size_t)r * np + cc;
-        const double a4 = c2 * v, x2 = b1[e];
-        o0[e] = c3 * x2 + a4;
-        o1[e] = (r == cc ? c4 : 0.0) + c5 * b0[e] + c6 * x2 + c7 * a4;
+      cgdouble *const in[2] = {gptr(g_ep.b0), gptr(g_ep.b1)};
+      for_chunk<NW, 2>(cbuf, row0, col0, rows, cols, ldc, np, in, [&](int r, int cc, int e, double v, const double *x) {
+        const double a4 = c2 * v;
+        o0[e] = c3 * x[1] + a4;
+        o1[e] = (r == cc ? c4 : 0.0) + c5 * x[0] + c6 * x[1] + c7 * a4;
       });
     } break;
     case EK_M8B: {
       gdouble *dst = gptr(g_ep.dst);
       const int ld = g_ep.dst_ld, nv = g_ep.dst_nvalid;
-      cgdouble *b0 = gptr(g_ep.b0), *b1 = gptr(g_ep.b1);
       const double c8 = c[8], c9 = c[9], c10 = c[10];
-      for_chunk(row0, col0, rows, cols, ldc, [&](int r, int cc, double v) {
-        const size_t e = (size_t)r * np + cc;
-        const double t = v + (r == cc ? c8 : 0.0) + c9 * b0[e] + c10 * b1[e];
-        if (r < nv && cc < nv) dst[(size_t)r * ld + cc] = t;
+      cgdouble *const in[2] = {gptr(g_ep.b0), gptr(g_ep.b1)};
+      for_chunk<NW, 2>(cbuf, row0, col0, rows, cols, ldc, np, in, [&](int r, int cc, int, double v, const double *x) {
+        const double t = v + (r == cc ? c8 : 0.0) + c9 * x[0] + c10 * x[1];
+        if (r < nv && cc < nv) dst[r * ld + cc] = t;
       });
     } break;
     case EK_ADD1: {
       gdouble *dst = gptr(g_ep.dst);
       const int ld = g_ep.dst_ld, nv = g_ep.dst_nvalid;
-      cgdouble *in0 = gptr(g_ep.in0);
-      for_chunk(row0, col0, rows, cols, ldc, [&](int r, int cc, double v) {
-        const size_t e = (size_t)r * np + cc;
-        const double t = v + in0[e];
-        if (r < nv && cc < nv) dst[(size_t)r * ld + cc] = t;
+      cgdouble *const in[1] = {gptr(g_ep.in0)};
+      for_chunk<NW, 1>(cbuf, row0, col0, rows, cols, ldc, np, in, [&](int r, int cc, int, double v, const double *x) {
+        const double t = v + x[0];
+        if (r < nv && cc < nv) dst[r * ld + cc] = t;
       });
     } break;
     case EK_SPLIT2: {
-      cgdouble *in0 = gptr(g_ep.in0), *in1 = gptr(g_ep.in1);
       gdouble *o0 = gptr(g_ep.o[0]), *o1 = gptr(g_ep.o[1]);
-      for_chunk(row0, col0, rows, cols, ldc, [&](int r, int cc, double v) {
-        const size_t e = (size_t)r * np + cc;
-        const double t = v + in0[e];
+      cgdouble *const in[2] = {gptr(g_ep.in0), gptr(g_ep.in1)};
+      for_chunk<NW, 2>(cbuf, row0, col0, rows, cols, ldc, np, in, [&](int, int, int e, double v, const double *x) {
+        const double t = v + x[0];
         o0[e] = t;
-        o1[e] = t + in1[e];
+        o1[e] = t + x[1];
       });
     } break;
     case EK_M18A: {
-      cgdouble *b0 = gptr(g_ep.b0), *b1 = gptr(g_ep.b1), *b2 = gptr(g_ep.b2);
-      gdouble *o0 = gptr(g_ep.o[0]), *o1 = gptr(g_ep.o[1]), *o2 = gptr(g_ep.o[2]), *o3 = gptr(g_ep.o[3]), *o4 = gptr(g_ep.o[4]);
-      for_chunk(row0, col0, rows, cols, ldc, [&](int r, int cc, double v) {
-        const size_t e = (size_t)r * np + cc;
+      gdouble *o0 = gptr(g_ep.o[0]), *o1 = gptr(g_ep.o[1]), *o2 = gptr(g_ep.o[2]), *o3 = gptr(g_ep.o[3]),
+              *o4 = gptr(g_ep.o[4]);
+      double k[24];
+#pragma unroll
+      for (int i = 0; i < 24; ++i) k[i] = c[i];
+      cgdouble *const in[3] = {gptr(g_ep.b0), gptr(g_ep.b1), gptr(g_ep.b2)};
+      for_chunk<NW, 3>(cbuf, row0, col0, rows, cols, ldc, np, in, [&](int r, int cc, int e, double v, const double *x) {
         const double id = (r == cc) ? 1.0 : 0.0;
-        const double x1 = b0[e], x2 = b1[e], x3 = b2[e];
-        o0[e] = c[0] * id + c[1] * x1 + c[2] * x2 + c[3] * x3;
-        o1[e] = c[4] * id + c[5] * x1 + c[6] * x2 + c[7] * x3 + c[8] * v;
-        o2[e] = c[9] * id + c[10] * x1 + c[11] * x2 + c[12] * x3 + c[13] * v;
-        o3[e] = c[14] * id + c[15] * x1 + c[16] * x2 + c[17] * x3 + c[18] * v;
-        o4[e] = c[19] * id + c[20] * x1 + c[21] * x2 + c[22] * x3 + c[23] * v;
+        const double x1 = x[0], x2 = x[1], x3 = x[2];
+        o0[e] = k[0] * id + k[1] * x1 + k[2] * x2 + k[3] * x3;
+        o1[e] = k[4] * id + k[5] * x1 + k[6] * x2 + k[7] * x3 + k[8] * v;
+        o2[e] = k[9] * id + k[10] * x1 + k[11] * x2 + k[12] * x3 + k[13] * v;
+        o3[e] = k[14] * id + k[15] * x1 + k[16] * x2 + k[17] * x3 + k[18] * v;
+        o4[e] = k[19] * id + k[20] * x1 + k[21] * x2 + k[22] * x3 + k[23] * v;
       });
     } break;
+    default: break;
   }
 }
 
-template <int T>
+template <int NW, int T>
 __device__ __noinline__ void gemm_t() {
-  typedef TileCfg<T> C;
+  typedef typename TileFor<NW, T>::S S;
   constexpr int np = 16 * T;
-  constexpr int CR = C::WR * C::BR, CC = C::WC * C::BC;   // chunk size in tiles
-  constexpr int PROWS = CR * 16, QCOLS = CC * 16;
-  constexpr int LDP = kKP + 1, LDQ = QCOLS + 1, LDC = QCOLS + 1;
-  constexpr int PPT = (PROWS * 8 + kThreads - 1) / kThreads;  // P double2 per thread
-  constexpr int QPT = (QCOLS * 8 + kThreads - 1) / kThreads;  // Q double2 per thread
-  constexpr int NPAN = np / kKP;
-  constexpr int TPW = C::BR * C::BC;
-  static_assert(PROWS <= 96 && QCOLS <= 128 && PROWS * LDC <= kLdsC, "chunk exceeds LDS budget");
-
-  cgdouble *__restrict__ P = gptr(g_ep.P);
-  cgdouble *__restrict__ Q = gptr(g_ep.Q);
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
+  constexpr int LDC = S::BN + 1;
+  static_assert(3 * (S::P_STAGE + S::Q_STAGE) <= (NW == 4 ? kPool4 : kPool8), "stage ring exceeds pool");
+  static_assert(S::BM * LDC <= (NW == 4 ? kPool4 : kPool8), "chunk copy exceeds pool");
+  TileLds<S> &L = *reinterpret_cast<TileLds<S> *>(lds_pool<NW>());
+  cgdouble *P = gptr(g_ep.P);
+  cgdouble *Q = gptr(g_ep.Q);
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  const bool has_block = wave < C::WR * C::WC;
-  const int wr = wave / C::WC, wc = wave % C::WC;
+  const bool has_block = wave < S::WR * S::WC;
+  const int wr = wave / S::WC, wc = wave % S::WC;
+  const int kind = g_ep.kind;
 
 #pragma unroll 1
-  for (int cr0 = 0; cr0 < T; cr0 += CR) {
+  for (int m0 = 0; m0 < np; m0 += S::BM) {
 #pragma unroll 1
-    for (int cc0 = 0; cc0 < T; cc0 += CC) {
-      const int br0 = cr0 + wr * C::BR, bc0 = cc0 + wc * C::BC;
-      const bool active = has_block && br0 < T && bc0 < T;
-      dbl4 acc[TPW];
-#pragma unroll
-      for (int i = 0; i < TPW; ++i) acc[i] = dbl4{0.0, 0.0, 0.0, 0.0};
-      int aoff[C::BR], boff[C::BC];
-#pragma unroll
-      for (int i = 0; i < C::BR; ++i) aoff[i] = ((br0 - cr0 + i) * 16 + lr) * LDP + lk;
-#pragma unroll
-      for (int j = 0; j < C::BC; ++j) boff[j] = lk * LDQ + (bc0 - cc0 + j) * 16 + lr;
-
-      dv2 rp[PPT], rq[QPT];
-      auto load_panel = [&](int kp) {
-        const int k0 = kp * kKP;
-#pragma unroll
-        for (int i = 0; i < PPT; ++i) {
-          const int idx = tid + i * kThreads;
-          const int r = idx >> 3, c2 = idx & 7;
-          if (idx < PROWS * 8 && cr0 * 16 + r < np)
-            rp[i] = *reinterpret_cast<cgdv2 *>(P + (size_t)(cr0 * 16 + r) * np + k0 + 2 * c2);
-        }
-#pragma unroll
-        for (int i = 0; i < QPT; ++i) {
-          const int idx = tid + i * kThreads;
-          const int r = idx / (QCOLS / 2), c2 = idx % (QCOLS / 2);
-          if (idx < QCOLS * 8 && cc0 * 16 + 2 * c2 < np)
-            rq[i] = *reinterpret_cast<cgdv2 *>(Q + (size_t)(k0 + r) * np + cc0 * 16 + 2 * c2);
-        }
-      };
-      auto store_panel = [&]() {
-#pragma unroll
-        for (int i = 0; i < PPT; ++i) {
-          const int idx = tid + i * kThreads;
-          const int r = idx >> 3, c2 = idx & 7;
-          if (idx < PROWS * 8 && cr0 * 16 + r < np) {
-            g_sm.pan.p[r * LDP + 2 * c2] = rp[i].x;
-            g_sm.pan.p[r * LDP + 2 * c2 + 1] = rp[i].y;
-          }
-        }
-#pragma unroll
-        for (int i = 0; i < QPT; ++i) {
-          const int idx = tid + i * kThreads;
-          const int r = idx / (QCOLS / 2), c2 = idx % (QCOLS / 2);
-          if (idx < QCOLS * 8 && cc0 * 16 + 2 * c2 < np) {
-            g_sm.pan.q[r * LDQ + 2 * c2] = rq[i].x;
-            g_sm.pan.q[r * LDQ + 2 * c2 + 1] = rq[i].y;
-          }
-        }
-      };
-
-      load_panel(0);
-#pragma unroll 1
-      for (int kp = 0; kp < NPAN; ++kp) {
-        __syncthreads();  // previous panel (or previous chunk's C copy) consumed
-        store_panel();
-        __syncthreads();
-        if (kp + 1 < NPAN) load_panel(kp + 1);
+    for (int n0 = 0; n0 < np; n0 += S::BN) {
+      const int wr_row = wr * S::BR * 16, wc_col = wc * S::BC * 16;  // within the chunk
+      const bool active = has_block && m0 + wr_row < np && n0 + wc_col < np;
+      dbl4 acc[S::TPW];
+      tile_gemm<S>(P, np, Q, np, np, np, np, m0, n0, L, active, wr_row, wc_col, acc);
+      if (kind == EK_STORE) {
         if (active) {
+          gdouble *dst = gptr(g_ep.dst);
+          int ld = g_ep.dst_ld;
+          const int nv = g_ep.dst_nvalid;
+          asm volatile("" : "+v"(ld));  // keep the store addresses out of the K loop
 #pragma unroll
-          for (int kk = 0; kk < kKP; kk += 4) {
-            double a[C::BR], b[C::BC];
+          for (int i = 0; i < S::BR; ++i)
 #pragma unroll
-            for (int i = 0; i < C::BR; ++i) a[i] = g_sm.pan.p[aoff[i] + kk];
+            for (int j = 0; j < S::BC; ++j) {
+              const int col = n0 + wc_col + j * 16 + lr;
 #pragma unroll
-            for (int j = 0; j < C::BC; ++j) b[j] = g_sm.pan.q[boff[j] + kk * LDQ];
-#pragma unroll
-            for (int i = 0; i < C::BR; ++i)
-#pragma unroll
-              for (int j = 0; j < C::BC; ++j)
-                acc[i * C::BC + j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i * C::BC + j], 0, 0, 0);
-          }
+              for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wr_row + i * 16 + 4 * r + lk;
+                if (row < nv && col < nv) dst[row * ld + col] = acc[i * S::BC + j][r];
+              }
+            }
         }
+        __syncthreads();  // the next chunk's loads reuse the stage ring
+        continue;
       }
-      __syncthreads();  // panels consumed: the chunk copy of C reuses their storage
+      __syncthreads();  // stage ring retired: it becomes the chunk copy of C
+      double *cbuf = lds_pool<NW>();
       if (active) {
+        int lrow = lk;
+        asm volatile("" : "+v"(lrow));
 #pragma unroll
-        for (int i = 0; i < C::BR; ++i)
+        for (int i = 0; i < S::BR; ++i)
 #pragma unroll
-          for (int j = 0; j < C::BC; ++j)
+          for (int j = 0; j < S::BC; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-              g_sm.c[((br0 - cr0 + i) * 16 + 4 * r + lk) * LDC + (bc0 - cc0 + j) * 16 + lr] = acc[i * C::BC + j][r];
+              cbuf[(wr_row + i * 16 + 4 * r + lrow) * LDC + wc_col + j * 16 + lr] = acc[i * S::BC + j][r];
       }
       __syncthreads();
-      const int rows = ((T - cr0) < CR ? (T - cr0) : CR) * 16;
-      const int cols = ((T - cc0) < CC ? (T - cc0) : CC) * 16;
-      run_epilogue(cr0 * 16, cc0 * 16, rows, cols, LDC);
+      const int rows = (np - m0) < S::BM ? (np - m0) : S::BM;
+      const int cols = (np - n0) < S::BN ? (np - n0) : S::BN;
+      run_epilogue<NW>(m0, n0, rows, cols, LDC);
+      __syncthreads();  // chunk copy consumed before the next chunk's loads
     }
   }
-  __syncthreads();  // outputs visible to the whole workgroup before the next step
 }
 
-// C = P * Q with the epilogue described by g_ep (np = g_ep.np, a multiple of 16, <= 256).
+// C = P * Q with the epilogue described by g_ep (np = g_ep.np).  NW = 4 serves np <= 64,
+// NW = 8 serves np in 80..256.
+template <int NW>
 __device__ inline void gemm_block() {
-  switch (g_ep.np >> 4) {
-    case 1: gemm_t<1>(); break;
-    case 2: gemm_t<2>(); break;
-    case 3: gemm_t<3>(); break;
-    case 4: gemm_t<4>(); break;
-    case 5: gemm_t<5>(); break;
-    case 6: gemm_t<6>(); break;
-    case 7: gemm_t<7>(); break;
-    case 8: gemm_t<8>(); break;
-    case 9: gemm_t<9>(); break;
-    case 10: gemm_t<10>(); break;
-    case 11: gemm_t<11>(); break;
-    case 12: gemm_t<12>(); break;
-    case 13: gemm_t<13>(); break;
-    case 14: gemm_t<14>(); break;
-    case 15: gemm_t<15>(); break;
-    default: gemm_t<16>(); break;
+  const int t = g_ep.np >> 4;
+  if constexpr (NW == 4) {
+    switch (t) {
+      case 1: gemm_t<4, 1>(); break;
+      case 2: gemm_t<4, 2>(); break;
+      case 3: gemm_t<4, 3>(); break;
+      default: gemm_t<4, 4>(); break;
+    }
+  } else {
+    switch (t) {
+      case 5: gemm_t<8, 5>(); break;
+      case 6: gemm_t<8, 6>(); break;
+      case 7: gemm_t<8, 7>(); break;
+      case 8: gemm_t<8, 8>(); break;
+      case 9: gemm_t<8, 9>(); break;
+      case 10: gemm_t<8, 10>(); break;
+      case 11: gemm_t<8, 11>(); break;
+      case 12: gemm_t<8, 12>(); break;
+      case 13: gemm_t<8, 13>(); break;
+      case 14: gemm_t<8, 14>(); break;
+      case 15: gemm_t<8, 15>(); break;
+      default: gemm_t<8, 16>(); break;
+    }
   }
 }
 

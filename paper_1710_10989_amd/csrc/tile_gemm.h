@@ -1,0 +1,173 @@
+// Workgroup FP64 MFMA tile engine: acc(BM x BN) = P[m0 : m0+BM, 0:K] * Q[0:K, n0 : n0+BN]
+// for row-major operands in device memory.
+//
+// Pipeline.  K is walked in panels of KP = 16.  Panels travel from global memory straight
+// into LDS with global_load_lds_dwordx4 (gfx950: each lane moves 16 bytes to
+// LDS base + 16 * lane, no registers involved), into a ring of three LDS stages.  Panel
+// kp + 2 is in flight while panel kp is multiplied, and one workgroup barrier per panel both
+// publishes panel kp and retires the stage that panel kp + 2 overwrites.  The ring is unrolled
+// by three so every stage is a distinct __shared__ array: the compiler then sees that the
+// fragment reads of one stage never alias the in-flight writes of another.
+//
+// LDS layouts (16-byte chunks):
+//   P stage: BM rows x 8 chunks (128 B per row).  Chunk c of row r sits in slot
+//            c ^ ((r >> 1) & 7): an A fragment reads 16 rows of one column, and the swizzle
+//            puts those 16 reads in 16 distinct bank groups.
+//   Q stage: 16 rows x BN/2 chunks.  When BN/2 is a multiple of 16, odd rows swap 128-byte
+//            halves (slot c ^ 8), so the four 16-lane groups of a B fragment use both bank
+//            halves.
+//
+// MFMA operand layout (gfx950, 16x16x4 f64): lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; accumulator register r of lane l holds D[4 r + l / 16][l % 16].
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace expm {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) double gdouble;
+typedef __attribute__((address_space(1))) const double cgdouble;
+typedef __attribute__((address_space(1))) const void *gvoidp;
+typedef __attribute__((address_space(3))) void *lvoidp;
+__device__ inline gdouble *gptr(double *p) { return (gdouble *)p; }
+__device__ inline cgdouble *gptr(const double *p) { return (cgdouble *)p; }
+
+constexpr int kKP = 16;
+
+// NW waves; chunk BM x BN; waves in a WR x WC grid, each owning BR x BC 16x16 tiles.
+template <int NW_, int BM_, int BN_, int WR_, int WC_, int BR_, int BC_>
+struct TileShape {
+  static constexpr int NW = NW_, BM = BM_, BN = BN_, WR = WR_, WC = WC_, BR = BR_, BC = BC_;
+  static constexpr int TPW = BR * BC;
+  static constexpr int P_STAGE = BM * kKP;          // doubles
+  static constexpr int Q_STAGE = kKP * BN;          // doubles
+  static constexpr int P_INSTR = BM * kKP / 128;    // wave instructions (64 x 16 B) per panel
+  static constexpr int Q_INSTR = kKP * BN / 128;
+  static constexpr int INSTR = P_INSTR + Q_INSTR;
+  static constexpr int MIN_INSTR_PER_WAVE = INSTR / NW;  // waves issue floor or ceil of this
+  static constexpr bool Q_SWZ = ((BN / 2) % 16) == 0;
+  static_assert(BM % 16 == 0 && BN % 16 == 0, "tile multiple of 16");
+  static_assert(WR * WC <= NW, "wave grid");
+  static_assert(P_INSTR * 128 == BM * kKP && Q_INSTR * 128 == kKP * BN, "whole wave loads");
+};
+
+template <class S>
+struct TileLds {
+  double p[3][S::P_STAGE];
+  double q[3][S::Q_STAGE];
+};
+
+// Workgroup barrier for the panel ring.  __syncthreads() (and even an LDS-scoped fence)
+// makes the compiler wait for every outstanding vector-memory operation, including the
+// in-flight LDS-DMA panels.  Here the caller waits for exactly the panel it needs
+// (wait_vmcnt), this wave's LDS reads are drained (lgkmcnt(0)), and s_barrier publishes both;
+// the memory clobber keeps the compiler from moving LDS accesses across it.
+__device__ inline void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// s_waitcnt with vmcnt <= n and the other counters unconstrained (gfx9 encoding).
+template <int n>
+__device__ inline void wait_vmcnt() {
+  static_assert(n >= 0 && n < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// Issues the direct-to-LDS loads of panel kp (columns k0 .. k0+15 of P's rows m0.., rows
+// k0 .. k0+15 of Q's columns n0..) into stage buffers lp, lq.  Rows of P at or beyond M,
+// columns of Q at or beyond N and k at or beyond K are clamped to valid addresses: those LDS
+// entries only feed accumulators that are never stored, or are skipped (k tail).
+template <class S>
+__device__ inline void issue_panel(cgdouble *P, int ldp, cgdouble *Q, int ldq, int M, int N, int K,
+                                   int m0, int n0, int k0, double *lp, double *lq) {
+  int lane = threadIdx.x & 63;
+  asm volatile("" : "+v"(lane));  // opaque: addresses are rebuilt per panel, not held live
+  const int wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < (S::INSTR + S::NW - 1) / S::NW; ++i) {
+    const int ins = i * S::NW + wave;  // wave-uniform instruction index
+    if (ins < S::P_INSTR) {
+      const int j = ins * 64 + lane;   // chunk index in the P stage
+      const int r = j >> 3, slot = j & 7;
+      const int c = slot ^ ((r >> 1) & 7);
+      int k = k0 + 2 * c;
+      if (k >= K) k = 0;
+      const int row = (m0 + r < M) ? m0 + r : 0;
+      __builtin_amdgcn_global_load_lds((gvoidp)(P + (size_t)row * ldp + k),
+                                       (lvoidp)(lp + ins * 128), 16, 0, 0);
+    } else if (ins < S::INSTR) {
+      const int qi = ins - S::P_INSTR;
+      const int j = qi * 64 + lane;    // chunk index in the Q stage
+      const int r = j / (S::BN / 2), slot = j % (S::BN / 2);
+      const int c = S::Q_SWZ ? (slot ^ ((r & 1) << 3)) : slot;
+      int k = k0 + r;
+      if (k >= K) k = 0;
+      const int col = (n0 + 2 * c < N) ? n0 + 2 * c : 0;
+      __builtin_amdgcn_global_load_lds((gvoidp)(Q + (size_t)k * ldq + col),
+                                       (lvoidp)(lq + qi * 128), 16, 0, 0);
+    }
+  }
+}
+
+// Multiplies the panel held in (lp, lq) into acc: kend = 16, or fewer for a K tail.
+template <class S>
+__device__ inline void mma_panel(const double *lp, const double *lq, int wr_row, int wc_col, int kend,
+                                 dbl4 (&acc)[S::TPW]) {
+  int lane = threadIdx.x & 63;
+  asm volatile("" : "+v"(lane));
+  const int lr = lane & 15, lk = lane >> 4;
+  // Blocks of 9+ tiles keep only two k steps of fragments in flight (register budget).
+#pragma unroll (S::TPW >= 9 ? 2 : 4)
+  for (int kk = 0; kk < kKP; kk += 4) {
+    if (kk < kend) {
+      const int k = kk + lk;
+      double a[S::BR], b[S::BC];
+#pragma unroll
+      for (int i = 0; i < S::BR; ++i) {
+        const int r = wr_row + i * 16 + lr;  // row within the chunk
+        const int slot = (k >> 1) ^ ((r >> 1) & 7);
+        a[i] = lp[r * kKP + 2 * slot + (k & 1)];
+      }
+#pragma unroll
+      for (int j = 0; j < S::BC; ++j) {
+        const int col = wc_col + j * 16 + lr;  // column within the chunk
+        const int slot = S::Q_SWZ ? ((col >> 1) ^ ((k & 1) << 3)) : (col >> 1);
+        b[j] = lq[k * S::BN + 2 * slot + (col & 1)];
+      }
+#pragma unroll
+      for (int i = 0; i < S::BR; ++i)
+#pragma unroll
+        for (int j = 0; j < S::BC; ++j)
+          acc[i * S::BC + j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i * S::BC + j], 0, 0, 0);
+    }
+  }
+}
+
+// Full K loop for one chunk.  `active`: this wave owns a block inside the matrix.  The caller
+// must have passed a workgroup barrier since the stages were last read.  On return every
+// panel load has completed, but other waves may still be reading the last stage.
+template <class S>
+__device__ inline void tile_gemm(cgdouble *P, int ldp, cgdouble *Q, int ldq, int M, int N, int K,
+                                 int m0, int n0, TileLds<S> &L, bool active, int wr_row, int wc_col,
+                                 dbl4 (&acc)[S::TPW]) {
+#pragma unroll
+  for (int i = 0; i < S::TPW; ++i) acc[i] = dbl4{0.0, 0.0, 0.0, 0.0};
+  const int npan = (K + kKP - 1) / kKP;
+  issue_panel<S>(P, ldp, Q, ldq, M, N, K, m0, n0, 0, L.p[0], L.q[0]);
+  if (npan > 1) issue_panel<S>(P, ldp, Q, ldq, M, N, K, m0, n0, kKP, L.p[1], L.q[1]);
+  // One step: wait for panel kp, publish it, refill the stage freed by panel kp - 1, multiply.
+  auto step = [&](int kp, double *lp, double *lq, double *np_p, double *np_q) {
+    if (kp + 1 < npan) wait_vmcnt<S::MIN_INSTR_PER_WAVE>(); else wait_vmcnt<0>();
+    lds_barrier();
+    if (kp + 2 < npan) issue_panel<S>(P, ldp, Q, ldq, M, N, K, m0, n0, (kp + 2) * kKP, np_p, np_q);
+    const int kend = (K - kp * kKP) < kKP ? (K - kp * kKP) : kKP;
+    if (active) mma_panel<S>(lp, lq, wr_row, wc_col, kend, acc);
+  };
+  for (int kp = 0; kp < npan; kp += 3) {
+    step(kp, L.p[0], L.q[0], L.p[2], L.q[2]);
+    if (kp + 1 < npan) step(kp + 1, L.p[1], L.q[1], L.p[0], L.q[0]);
+    if (kp + 2 < npan) step(kp + 2, L.p[2], L.q[2], L.p[1], L.q[1]);
+  }
+}
+
+}  // namespace expm
