@@ -50,7 +50,10 @@ typedef enum {
   EXPM_E_UNSUPPORTED = 5
 } expm_status_t;
 
-/* Element type of A and e^A. */
+/* Element type of A and e^A.  EXPM_C128 runs the method on the real form [[X, -Y], [Y, X]] of
+ * A = X + iY (of order 2n): the map is an algebra homomorphism, so the real exponential of
+ * the real form is the real form of e^A.  (m, s) are chosen from the 1-norm of the real form,
+ * which lies between ||A||_1 and sqrt(2) ||A||_1. */
 typedef enum { EXPM_F64 = 0, EXPM_C128 = 1 } expm_dtype_t;
 
 /* Arithmetic of the polynomial products (the powers and the product stage of T_m).  The
@@ -105,22 +108,32 @@ EXPM_API expm_status_t expm_select(const void *A_dev, int64_t n, const expm_opts
 
 /* e^A for one n x n matrix: E_dev <- e^{A_dev}; the chosen (m, s) and the status go to
  * m_dev, s_dev, status_dev (one int32 each, device; status_dev may be NULL).
- * n <= 256: one persistent fused launch, no host synchronisation (graph-capturable).
- * n > 256: tiled multi-workgroup kernels; the host reads (m, s) back once (8 bytes) to size
- * the launch sequence, so the call synchronises `stream` after the selection step. */
+ * Real order n <= 256 (complex n <= 128): one persistent fused launch, no host
+ * synchronisation (graph-capturable).  Larger orders: tiled multi-workgroup kernels; the host
+ * reads (m, s) back once (8 bytes) to size the launch sequence, so the call synchronises
+ * `stream` and is not graph-capturable. */
 EXPM_API expm_status_t expm_taylor(const void *A_dev, void *E_dev, int64_t n, const expm_opts_t *opts,
                           int32_t *m_dev, int32_t *s_dev, int32_t *status_dev, void *ws_dev,
                           size_t ws_bytes, void *stream);
 
-/* e^A for `batch` independent matrices of uneven order n_b <= n_max <= 256, packed:
- * matrix b occupies elements [offsets_dev[b], offsets_dev[b] + n_b^2) of A_dev and E_dev
- * (elements of the dtype, not bytes).  n_dev[b] = n_b (int32).  Outputs per matrix: m_dev[b],
- * s_dev[b], status_dev[b].  One persistent launch walks a device work queue, largest matrices
- * first; no host synchronisation (graph-capturable). */
+/* e^A for `batch` independent matrices of uneven order n_b <= n_max, real order <= 256
+ * (complex <= 128), packed: matrix b occupies elements [offsets_dev[b], offsets_dev[b] + n_b^2)
+ * of A_dev and E_dev (elements of the dtype, not bytes).  n_dev[b] = n_b (int32).  Outputs per
+ * matrix: m_dev[b], s_dev[b], status_dev[b].  A device kernel sorts the batch largest order
+ * first; persistent launches walk that work queue; no host synchronisation
+ * (graph-capturable).  Larger orders: EXPM_E_UNSUPPORTED (use expm_batched_uniform). */
 EXPM_API expm_status_t expm_batched(const void *A_dev, void *E_dev, const int64_t *offsets_dev,
                            const int32_t *n_dev, int64_t batch, int64_t n_max,
                            const expm_opts_t *opts, int32_t *m_dev, int32_t *s_dev,
                            int32_t *status_dev, void *ws_dev, size_t ws_bytes, void *stream);
+
+/* e^A for `batch` matrices of the same order n stored back to back (matrix b at element
+ * b * n^2).  Any order: real order <= 256 (complex <= 128) runs on the fused kernels with
+ * static assignment (graph-capturable); larger orders run the tiled path in groups of matrices
+ * (about 2048 output tiles per launch), synchronising once per group to read (m, s) back. */
+EXPM_API expm_status_t expm_batched_uniform(const void *A_dev, void *E_dev, int64_t n, int64_t batch,
+                                   const expm_opts_t *opts, int32_t *m_dev, int32_t *s_dev,
+                                   int32_t *status_dev, void *ws_dev, size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libexpm.so")
-SOURCES = ["expm_api.cpp", "theta.cpp", "expm_fused.hip"]
+SOURCES = ["expm_api.cpp", "theta.cpp", "expm_fused.hip", "expm_large.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -19,17 +19,21 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
 
 
 def build(verbose=False):
-    objs = []
+    from concurrent.futures import ThreadPoolExecutor
+    jobs = []
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(CSRC, "_build", src + ".o")
         os.makedirs(os.path.dirname(obj), exist_ok=True)
-        lang = ["-x", "hip"]
-        cmd = [HIPCC] + FLAGS + lang + ["-c", path, "-o", obj]
+        cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
-        objs.append(obj)
+        jobs.append((cmd, obj))
+    with ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
+        for rc in ex.map(lambda j: subprocess.call(j[0]), jobs):
+            if rc != 0:
+                raise RuntimeError("hipcc failed")
+    objs = [o for _, o in jobs]
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs
     if verbose:

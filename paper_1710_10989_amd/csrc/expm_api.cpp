@@ -7,6 +7,7 @@
 
 #include "expm_fused.h"
 #include "expm_internal.h"
+#include "expm_large.h"
 
 using namespace expm;
 
@@ -121,12 +122,16 @@ expm_status_t expm_select_rule(const double *norms, int32_t sel, double u, int32
   return EXPM_OK;
 }
 
+// Order of the real matrix the method runs on: complex inputs use their real form.
+static int64_t real_order(const expm_opts_t *o, int64_t n) { return o->dtype == EXPM_C128 ? 2 * n : n; }
+
 size_t expm_workspace_bytes(int64_t n_max, int64_t batch, const expm_opts_t *opts) {
   double u;
   if (n_max < 1 || batch < 1 || check_opts(opts, &u) != EXPM_OK) return 0;
-  if (n_max <= kFusedNMax && opts->dtype == EXPM_F64 && opts->prec == EXPM_PREC_FP64)
-    return fused_layout(n_max, batch).total;
-  return 0;
+  if (opts->prec != EXPM_PREC_FP64) return 0;
+  const int64_t nr = real_order(opts, n_max);
+  if (nr <= kFusedNMax) return fused_layout(nr, batch).total;
+  return large_layout(nr, batch).total;
 }
 
 static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, const int32_t *ns,
@@ -134,7 +139,10 @@ static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, cons
                                const expm_opts_t *opts, double u, int32_t *m_dev, int32_t *s_dev,
                                int32_t *status_dev, void *ws, size_t ws_bytes, void *stream,
                                int select_only) {
-  FusedLayout L = fused_layout(n_max, batch);
+  // n_uniform and n_max are input orders; the kernels pad the real order
+  const int cplx = opts->dtype == EXPM_C128;
+  const int64_t nr_max = real_order(opts, n_max), nr_uni = real_order(opts, n_uniform);
+  FusedLayout L = fused_layout(nr_max, batch);
   if (!ws || ws_bytes < L.total) return EXPM_E_WORKSPACE;
   if (((uintptr_t)ws) % kAlign) return EXPM_E_INVALID_ARG;
   FusedArgs a;
@@ -152,24 +160,47 @@ static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, cons
   a.slot_doubles = L.slot_doubles;
   a.batch = batch;
   a.n_uniform = (int)n_uniform;
-  a.np_max = (int)pad16(n_max);
+  a.np_max = (int)pad16(nr_max);
+  a.cplx = cplx;
   a.sel = opts->sel == EXPM_SEL_LEARNED ? EXPM_SEL_ALPHA : opts->sel;
   a.select_only = select_only;
   hipStream_t st = (hipStream_t)stream;
   if (ns) {
     a.order = (const int32_t *)(base + L.order_off);
     a.queue = (unsigned long long *)(base + L.queue_off);
-    if (launch_order(ns, batch, (int32_t *)a.order, a.queue, st) != hipSuccess) return EXPM_E_HIP;
+    if (launch_order(ns, batch, cplx, (int32_t *)a.order, a.queue, st) != hipSuccess) return EXPM_E_HIP;
     // largest orders first: the 8-wave kernel drains the front of the queue, then the 4-wave
     // kernel the rest (either range may be empty)
-    if (np_max_t(n_max) >= kSplitT && launch_fused(a, 8, grid_for(8, batch), st) != hipSuccess) return EXPM_E_HIP;
+    if (np_max_t(nr_max) >= kSplitT && launch_fused(a, 8, grid_for(8, batch), st) != hipSuccess) return EXPM_E_HIP;
     if (launch_fused(a, 4, grid_for(4, batch), st) != hipSuccess) return EXPM_E_HIP;
   } else {
-    const bool big = np_max_t(n_uniform) >= kSplitT;
+    const bool big = np_max_t(nr_uni) >= kSplitT;
     a.split = big ? batch : 0;
     if (launch_fused(a, big ? 8 : 4, grid_for(big ? 8 : 4, batch), st) != hipSuccess) return EXPM_E_HIP;
   }
   return EXPM_OK;
+}
+
+static expm_status_t run_large_call(const void *A, void *E, int64_t n, int64_t batch, const expm_opts_t *opts,
+                                    double u, int32_t *m_dev, int32_t *s_dev, int32_t *status_dev, void *ws,
+                                    size_t ws_bytes, void *stream, int select_only) {
+  if (((uintptr_t)ws) % kAlign) return EXPM_E_INVALID_ARG;
+  LargeCall c;
+  memset(&c, 0, sizeof(c));
+  if (!make_consts(u, &c.k)) return EXPM_E_INVALID_ARG;
+  c.A = (const double *)A;
+  c.E = (double *)E;
+  c.nin = n;
+  c.cplx = opts->dtype == EXPM_C128;
+  c.batch = batch;
+  c.sel = opts->sel == EXPM_SEL_LEARNED ? EXPM_SEL_ALPHA : opts->sel;
+  c.select_only = select_only;
+  c.m_out = m_dev;
+  c.s_out = s_dev;
+  c.status = status_dev;
+  c.ws = ws;
+  c.ws_bytes = ws_bytes;
+  return run_large(c, (hipStream_t)stream);
 }
 
 expm_status_t expm_select(const void *A_dev, int64_t n, const expm_opts_t *opts, int32_t *m_dev,
@@ -178,7 +209,9 @@ expm_status_t expm_select(const void *A_dev, int64_t n, const expm_opts_t *opts,
   expm_status_t st = check_opts(opts, &u);
   if (st != EXPM_OK) return st;
   if (!A_dev || !m_dev || !s_dev || n < 1) return EXPM_E_INVALID_ARG;
-  if (n > kFusedNMax || opts->dtype != EXPM_F64 || opts->prec != EXPM_PREC_FP64) return EXPM_E_UNSUPPORTED;
+  if (opts->prec != EXPM_PREC_FP64) return EXPM_E_UNSUPPORTED;
+  if (real_order(opts, n) > kFusedNMax)
+    return run_large_call(A_dev, nullptr, n, 1, opts, u, m_dev, s_dev, nullptr, ws_dev, ws_bytes, stream, 1);
   return run_fused(A_dev, nullptr, nullptr, nullptr, 1, n, n, opts, u, m_dev, s_dev, nullptr,
                    ws_dev, ws_bytes, stream, 1);
 }
@@ -190,7 +223,9 @@ expm_status_t expm_taylor(const void *A_dev, void *E_dev, int64_t n, const expm_
   expm_status_t st = check_opts(opts, &u);
   if (st != EXPM_OK) return st;
   if (!A_dev || !E_dev || !m_dev || !s_dev || n < 1 || A_dev == E_dev) return EXPM_E_INVALID_ARG;
-  if (n > kFusedNMax || opts->dtype != EXPM_F64 || opts->prec != EXPM_PREC_FP64) return EXPM_E_UNSUPPORTED;
+  if (opts->prec != EXPM_PREC_FP64) return EXPM_E_UNSUPPORTED;
+  if (real_order(opts, n) > kFusedNMax)
+    return run_large_call(A_dev, E_dev, n, 1, opts, u, m_dev, s_dev, status_dev, ws_dev, ws_bytes, stream, 0);
   return run_fused(A_dev, E_dev, nullptr, nullptr, 1, n, n, opts, u, m_dev, s_dev, status_dev,
                    ws_dev, ws_bytes, stream, 0);
 }
@@ -205,9 +240,23 @@ expm_status_t expm_batched(const void *A_dev, void *E_dev, const int64_t *offset
   if (!A_dev || !E_dev || !offsets_dev || !n_dev || !m_dev || !s_dev || batch < 1 || n_max < 1 ||
       A_dev == E_dev)
     return EXPM_E_INVALID_ARG;
-  if (n_max > kFusedNMax || opts->dtype != EXPM_F64 || opts->prec != EXPM_PREC_FP64) return EXPM_E_UNSUPPORTED;
+  if (real_order(opts, n_max) > kFusedNMax || opts->prec != EXPM_PREC_FP64) return EXPM_E_UNSUPPORTED;
   return run_fused(A_dev, E_dev, offsets_dev, n_dev, batch, 0, n_max, opts, u, m_dev, s_dev,
                    status_dev, ws_dev, ws_bytes, stream, 0);
+}
+
+expm_status_t expm_batched_uniform(const void *A_dev, void *E_dev, int64_t n, int64_t batch,
+                                   const expm_opts_t *opts, int32_t *m_dev, int32_t *s_dev,
+                                   int32_t *status_dev, void *ws_dev, size_t ws_bytes, void *stream) {
+  double u;
+  expm_status_t st = check_opts(opts, &u);
+  if (st != EXPM_OK) return st;
+  if (!A_dev || !E_dev || !m_dev || !s_dev || batch < 1 || n < 1 || A_dev == E_dev) return EXPM_E_INVALID_ARG;
+  if (opts->prec != EXPM_PREC_FP64) return EXPM_E_UNSUPPORTED;
+  if (real_order(opts, n) > kFusedNMax)
+    return run_large_call(A_dev, E_dev, n, batch, opts, u, m_dev, s_dev, status_dev, ws_dev, ws_bytes, stream, 0);
+  return run_fused(A_dev, E_dev, nullptr, nullptr, batch, n, n, opts, u, m_dev, s_dev, status_dev,
+                   ws_dev, ws_bytes, stream, 0);
 }
 
 }  // extern "C"

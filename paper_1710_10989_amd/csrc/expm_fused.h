@@ -26,13 +26,15 @@ struct FusedArgs {
   int np_max;             // largest padded order the slots can hold
   int sel;                // expm_sel_t
   int select_only;
+  int cplx;               // inputs / outputs are interleaved complex (run on the real form)
   Consts k;
 };
+
 
 constexpr int kFusedBufs = 8;
 int fused_max_blocks_per_cu(int nw);
 hipError_t launch_fused(const FusedArgs &a, int nw, int grid, hipStream_t st);
-hipError_t launch_order(const int32_t *ns, int64_t batch, int32_t *order,
+hipError_t launch_order(const int32_t *ns, int64_t batch, int cplx, int32_t *order,
                         unsigned long long *queue, hipStream_t st);
 
 }  // namespace expm

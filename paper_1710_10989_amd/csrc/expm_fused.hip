@@ -20,6 +20,7 @@
 
 #include "expm_fused.h"
 #include "expm_internal.h"
+#include "coefs.h"
 #include "gemm_block.h"
 
 namespace expm {
@@ -84,47 +85,6 @@ __device__ void for_each_elem(int np, const double *const (&inp)[NIN], const F &
   __syncthreads();
 }
 
-// Scaled coefficients for degree m and scaling s, written to g_ep.c: a coefficient of X^k
-// becomes coef * 2^(-s k) on the stored power A^k.
-__device__ void make_coefs(const Consts &k, int m, int s) {
-  const double h1 = ldexp(1.0, -s), h2 = ldexp(1.0, -2 * s), h3 = ldexp(1.0, -3 * s),
-               h6 = ldexp(1.0, -6 * s);
-  double *c = g_ep.c;
-  switch (m) {
-    case 1: c[0] = h1; break;
-    case 2: c[0] = h1; c[1] = 0.5 * h2; break;
-    case 4:
-      c[0] = h1; c[1] = h2;                            // T = I + h1 A + h2 (A^2 W)
-      c[2] = 0.5; c[3] = h1 / 6.0; c[4] = h2 / 24.0;   // W = I/2 + X/6 + X^2/24
-      break;
-    case 8:
-      c[0] = k.t8[0] * h1; c[1] = k.t8[1] * h2;       // W1 = x1 X + x2 X^2
-      c[2] = h2;                                        // A_4 = h2 (A^2 W1)
-      c[3] = k.t8[2] * h2;                              // L = x3 X^2 + A_4
-      c[4] = k.t8[3]; c[5] = k.t8[4] * h1; c[6] = k.t8[5] * h2; c[7] = k.t8[6];  // R
-      c[8] = k.t8[7]; c[9] = k.t8[8] * h1; c[10] = k.t8[9] * h2;  // y0 I + y1 X + y2 X^2
-      break;
-    case 12:
-      for (int j = 0; j < 4; ++j) {
-        c[4 * j + 0] = k.t12[j][0];
-        c[4 * j + 1] = k.t12[j][1] * h1;
-        c[4 * j + 2] = k.t12[j][2] * h2;
-        c[4 * j + 3] = k.t12[j][3] * h3;
-      }
-      break;
-    case 18:
-      c[0] = k.t18a[0]; c[1] = k.t18a[1] * h1; c[2] = k.t18a[2] * h2; c[3] = k.t18a[3] * h3;
-      for (int j = 0; j < 4; ++j) {
-        c[4 + 5 * j + 0] = k.t18b[j][0];
-        c[4 + 5 * j + 1] = k.t18b[j][1] * h1;
-        c[4 + 5 * j + 2] = k.t18b[j][2] * h2;
-        c[4 + 5 * j + 3] = k.t18b[j][3] * h3;
-        c[4 + 5 * j + 4] = k.t18b[j][4] * h6;
-      }
-      break;
-  }
-}
-
 __shared__ int sh_ms[2];
 
 // One GEMM step: thread 0 fills the LDS descriptor through `set`, then all threads run it.
@@ -136,18 +96,16 @@ __device__ void gemm_step(const S &set) {
   __syncthreads();
 }
 
-__device__ void put_out(double *p, int ld, int nvalid, int r, int cc, double v) {
-  if (r < nvalid && cc < nvalid) p[r * ld + cc] = v;
-}
-
 // Runs the method on one matrix.
 template <int NW>
 __device__ void run_one(const FusedArgs &a, int64_t b, double *slot, double *red) {
   constexpr int NT = 64 * NW;
   const int tid = threadIdx.x;
-  const int n = a.ns ? a.ns[b] : a.n_uniform;
-  const int64_t off = a.offs ? a.offs[b] : b * (int64_t)n * n;
-  if (n < 1 || n > a.np_max) {
+  const int nin = a.ns ? a.ns[b] : a.n_uniform;  // order of the input (complex or real)
+  const int cx = a.cplx;
+  const int n = cx ? 2 * nin : nin;              // order of the real matrix the method runs on
+  const int64_t off = (a.offs ? a.offs[b] : b * (int64_t)nin * nin) * (cx ? 2 : 1);  // in doubles
+  if (nin < 1 || n > a.np_max) {
     if (tid == 0) {
       a.m_out[b] = -1; a.s_out[b] = -1;
       if (a.status) a.status[b] = EXPM_E_INVALID_ARG;
@@ -155,13 +113,22 @@ __device__ void run_one(const FusedArgs &a, int64_t b, double *slot, double *red
     return;
   }
   const int np = (n + 15) & ~15;
+  if ((NW == 4) != ((np >> 4) < kSplitT)) {  // matrix routed to the wrong variant
+    if (tid == 0) {
+      a.m_out[b] = -1; a.s_out[b] = -1;
+      if (a.status) a.status[b] = EXPM_E_UNSUPPORTED;
+    }
+    return;
+  }
   const size_t nn = (size_t)np * np;
   double *buf[kBufs];
   for (int i = 0; i < kBufs; ++i) buf[i] = slot + i * nn;
   const double *A = a.A + off;
   double *E = a.E ? a.E + off : nullptr;
 
-  // ---- load A into buf0 (zero padded) and take ||A||_1 (thread j owns column j) ----
+  // ---- load A into buf0 (zero padded) and take ||A||_1 (thread j owns column j).  A complex
+  // input Z = X + iY is loaded as its real form [[X, -Y], [Y, X]] (an algebra homomorphism,
+  // so the real exponential of that matrix is the real form of e^Z). ----
   double colsum = 0.0;
   int bad = 0;
   if (tid < np) {
@@ -170,7 +137,21 @@ __device__ void run_one(const FusedArgs &a, int64_t b, double *slot, double *red
     for (int i = 0; i < np; i += 16) {  // 16 loads in flight, then 16 stores
       double v[16];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) v[u] = (i + u < n && tid < n) ? Ag[(size_t)(i + u) * n + tid] : 0.0;
+      for (int u = 0; u < 16; ++u) {
+        const int r = i + u;
+        double x = 0.0;
+        if (r < n && tid < n) {
+          if (!cx) {
+            x = Ag[(size_t)r * n + tid];
+          } else {
+            const int ri = r < nin ? r : r - nin, ci = tid < nin ? tid : tid - nin;
+            const bool im = (r < nin) != (tid < nin);
+            x = Ag[2 * ((size_t)ri * nin + ci) + (im ? 1 : 0)];
+            if (im && r < nin) x = -x;
+          }
+        }
+        v[u] = x;
+      }
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         bad |= !isfinite(v[u]);
@@ -190,7 +171,7 @@ __device__ void run_one(const FusedArgs &a, int64_t b, double *slot, double *red
   __syncthreads();
 
   if (bad) {
-    if (E) for (int e = tid; e < n * n; e += NT) E[e] = __builtin_nan("");
+    if (E) for (int e = tid; e < nin * nin * (cx ? 2 : 1); e += NT) E[e] = __builtin_nan("");
     if (tid == 0) {
       a.m_out[b] = -1; a.s_out[b] = -1;
       if (a.status) a.status[b] = EXPM_E_NONFINITE;
@@ -209,14 +190,14 @@ __device__ void run_one(const FusedArgs &a, int64_t b, double *slot, double *red
   if (m_plain >= 2) {
     gemm_step<NW>([&](EpiDesc &d) {
       d.P = buf[0]; d.Q = buf[0]; d.kind = EK_STORE; d.np = np;
-      d.dst = buf[1]; d.dst_ld = np; d.dst_nvalid = np;
+      d.dst = buf[1]; d.dst_ld = np; d.dst_nvalid = np; d.cplx = 0;
     });
     if (want_alpha) n2 = block_norm1<NT>(buf[1], np, red);
   }
   if (m_plain >= 12) {
     gemm_step<NW>([&](EpiDesc &d) {
       d.P = buf[1]; d.Q = buf[0]; d.kind = EK_STORE; d.np = np;
-      d.dst = buf[2]; d.dst_ld = np; d.dst_nvalid = np;
+      d.dst = buf[2]; d.dst_ld = np; d.dst_nvalid = np; d.cplx = 0;
     });
     if (want_alpha) n3 = block_norm1<NT>(buf[2], np, red);
   }
@@ -226,7 +207,7 @@ __device__ void run_one(const FusedArgs &a, int64_t b, double *slot, double *red
   }
   const int m = sh_ms[0], s = sh_ms[1];
   if (tid == 0) {
-    make_coefs(a.k, m, s);
+    make_coefs(a.k, m, s, g_ep.c);
     a.m_out[b] = m; a.s_out[b] = s;
     if (a.status) a.status[b] = EXPM_OK;
   }
@@ -235,25 +216,27 @@ __device__ void run_one(const FusedArgs &a, int64_t b, double *slot, double *red
 
   const double *c = g_ep.c;
   const int tb = (m >= 8) ? 2 : 3;  // buffer holding T when s > 0
+  // destination of T: e^A itself when there is no squaring, else a workspace buffer
   double *Tp = (s == 0) ? E : buf[tb];
-  const int Tld = (s == 0) ? n : np, Tnv = (s == 0) ? n : np;
+  const int Tld = (s == 0) ? n : np, Tnv = (s == 0) ? nin : np, Tcx = (s == 0) ? cx : 0;
   double *B0 = buf[0], *B1 = buf[1], *B2 = buf[2];
   auto base = [&](EpiDesc &d) {
     d.np = np; d.b0 = B0; d.b1 = B1; d.b2 = B2;
-    d.dst = Tp; d.dst_ld = Tld; d.dst_nvalid = Tnv;
+    d.dst = Tp; d.dst_ld = Tld; d.dst_nvalid = Tnv; d.cplx = Tcx;
   };
+  gdouble *Tg = gptr(Tp);
 
   if (m == 1) {
     const double c0 = c[0];
     const double *in[1] = {B0};
     for_each_elem<NT, 1>(np, in, [&](int r, int cc, int, const double *x) {
-      put_out(Tp, Tld, Tnv, r, cc, (r == cc ? 1.0 : 0.0) + c0 * x[0]);
+      put_dst(Tg, Tld, Tnv, Tcx, r, cc, (r == cc ? 1.0 : 0.0) + c0 * x[0]);
     });
   } else if (m == 2) {
     const double c0 = c[0], c1 = c[1];
     const double *in[2] = {B0, B1};
     for_each_elem<NT, 2>(np, in, [&](int r, int cc, int, const double *x) {
-      put_out(Tp, Tld, Tnv, r, cc, (r == cc ? 1.0 : 0.0) + c0 * x[0] + c1 * x[1]);
+      put_dst(Tg, Tld, Tnv, Tcx, r, cc, (r == cc ? 1.0 : 0.0) + c0 * x[0] + c1 * x[1]);
     });
   } else if (m == 4) {
     double *W = buf[2];
@@ -313,7 +296,8 @@ __device__ void run_one(const FusedArgs &a, int64_t b, double *slot, double *red
     const bool last = (rsq == s);
     gemm_step<NW>([&](EpiDesc &d) {
       d.np = np; d.P = buf[cur]; d.Q = buf[cur]; d.kind = EK_STORE;
-      d.dst = last ? E : buf[nxt]; d.dst_ld = last ? n : np; d.dst_nvalid = last ? n : np;
+      d.dst = last ? E : buf[nxt]; d.dst_ld = last ? n : np; d.dst_nvalid = last ? nin : np;
+      d.cplx = last ? cx : 0;
     });
     cur = nxt;
   }
@@ -347,14 +331,14 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 2 : 1) void expm_fused_kernel(Fu
 
 // Counting sort of the batch by padded order, largest first (the work-queue order); resets
 // both queue counters and records the split between the two kernels.  One workgroup.
-__global__ void expm_order_kernel(const int32_t *ns, int64_t batch, int32_t *order,
+__global__ void expm_order_kernel(const int32_t *ns, int64_t batch, int cplx, int32_t *order,
                                   unsigned long long *queue) {
   __shared__ int hist[18], start[18];
   const int tid = threadIdx.x;
   if (tid < 18) hist[tid] = 0;
   __syncthreads();
   auto key = [&](int64_t b) {
-    const int n = ns[b];
+    const int n = cplx ? 2 * ns[b] : ns[b];  // order of the real matrix the method runs on
     if (n < 1 || n > kNpMax) return 17;
     return 16 - ((n + 15) >> 4);  // 0 for np = 256 ... 15 for np = 16
   };
@@ -389,9 +373,9 @@ hipError_t launch_fused(const FusedArgs &a, int nw, int grid, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_order(const int32_t *ns, int64_t batch, int32_t *order,
+hipError_t launch_order(const int32_t *ns, int64_t batch, int cplx, int32_t *order,
                         unsigned long long *queue, hipStream_t st) {
-  hipLaunchKernelGGL(expm_order_kernel, dim3(1), dim3(1024), 0, st, ns, batch, order, queue);
+  hipLaunchKernelGGL(expm_order_kernel, dim3(1), dim3(1024), 0, st, ns, batch, cplx, order, queue);
   return hipGetLastError();
 }
 

@@ -1,0 +1,42 @@
+// Tiled multi-workgroup path for real orders above 256 (complex orders above 128).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "expm_internal.h"
+
+namespace expm {
+
+constexpr int kLargeTile = 128;   // output tile of one workgroup
+constexpr int kLargeBufs = 8;     // n x n work buffers per matrix
+constexpr int kLargeRB = 64;      // rows per workgroup in the norm passes
+
+struct LargeLayout {
+  int64_t n;        // order of the real matrix the method runs on (2 * input order if complex)
+  int64_t np;       // n rounded up to kLargeTile
+  int64_t group;    // matrices processed together
+  int64_t nrb;      // row blocks of the norm passes
+  size_t bufs_off, partial_off, norms_off, flags_off, coef_off, list_off, total;
+};
+
+LargeLayout large_layout(int64_t n_real, int64_t batch);
+
+struct LargeCall {
+  const double *A;    // first input; matrix b at A + b * in_stride doubles
+  double *E;          // first output, same layout
+  int64_t nin;        // input order (complex or real)
+  int cplx;           // interleaved complex input / output, run on the real form
+  int64_t batch;
+  int sel;            // EXPM_SEL_PLAIN or EXPM_SEL_ALPHA
+  int select_only;
+  int32_t *m_out, *s_out, *status;  // device, one per matrix
+  void *ws;
+  size_t ws_bytes;
+  Consts k;
+};
+
+// Runs the method on a uniform batch of large matrices.  Synchronises the stream once per
+// group to read the chosen (m, s) back.
+expm_status_t run_large(const LargeCall &c, hipStream_t st);
+
+}  // namespace expm

@@ -1,0 +1,472 @@
+// Tiled multi-workgroup path for large orders: every GEMM is one launch over
+// (output tiles) x (matrices of the group), each workgroup computing one 128 x 128 tile with
+// the 8-wave direct-to-LDS tile engine and applying the fused epilogue of that step.
+//
+// Steps per group of matrices (all of order n, zero padded to np = multiple of 128):
+//   load: copy A into buffer 0 (real form for complex input), partial column sums;
+//   norm: column sums reduced in a fixed order, maximum by an integer atomic on the bit
+//         pattern of the non-negative doubles (deterministic);
+//   select: (m, s) per matrix on the device, scaled coefficients per matrix;
+//   read (m, s) back once; group the matrices by degree and squaring count;
+//   powers, product stage (the same epilogue kinds as the fused path), s squarings.
+// Zero padding is exact for the same reason as in the fused path (block-diagonal powers).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "coefs.h"
+#include "expm_large.h"
+#include "gemm_block.h"
+
+namespace expm {
+
+namespace {
+
+typedef TileShape<8, 128, 128, 4, 2, 2, 4> LS;
+constexpr int LDC_L = 129;
+static_assert(kLargeTile * LDC_L <= kPool8, "tile copy exceeds the LDS pool");
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Buffer selectors resolved per matrix inside the kernels.
+enum BufSel {
+  SEL_T = 100,       // buffer holding T: 2 for m >= 8, else 3
+  SEL_TDST = 101,    // destination of T: e^A when s == 0, else SEL_T
+  SEL_SQSRC = 200,   // squaring source in round r: SEL_T ^ ((r - 1) & 1)
+  SEL_SQDST = 201,   // squaring destination in round r: e^A when r == s, else source ^ 1
+  SEL_NONE = -1
+};
+
+struct MatCtx {
+  double *buf0;      // first work buffer of the matrix
+  size_t bstride;    // doubles between buffers
+  int m, s;
+};
+
+struct LargeArgs {
+  double *ws;              // group work buffers
+  size_t mstride, bstride; // doubles per matrix / per buffer
+  int np, n, nin, cplx;
+  const double *A;
+  double *E;
+  int64_t io_stride;       // doubles between consecutive inputs / outputs
+  int64_t g0;              // global index of the group's first matrix
+  const int32_t *m_arr, *s_arr;  // global arrays
+  const double *coef;      // group coefficients, 64 per matrix
+  const int32_t *list;     // matrices (group-relative) of this launch
+  int round;               // squaring round (1-based) for SEL_SQ*
+  // step description
+  int kind;                // epilogue kind (GEMM) or elementwise kind
+  int p, q, b0, b1, b2, in0, in1, o[5], dst;
+};
+
+__device__ inline int resolve_t(int m) { return m >= 8 ? 2 : 3; }
+
+// Pointer of a selector for matrix (group-relative) mi; returns nullptr for e^A (the caller
+// then writes the output matrix).
+__device__ inline double *sel_ptr(const LargeArgs &a, int mi, int sel, int m, int s) {
+  double *base = a.ws + (size_t)mi * a.mstride;
+  int k = sel;
+  if (sel == SEL_T) k = resolve_t(m);
+  else if (sel == SEL_TDST) { if (s == 0) return nullptr; k = resolve_t(m); }
+  else if (sel == SEL_SQSRC) k = resolve_t(m) ^ ((a.round - 1) & 1);
+  else if (sel == SEL_SQDST) { if (a.round == s) return nullptr; k = resolve_t(m) ^ ((a.round - 1) & 1) ^ 1; }
+  if (k < 0) return nullptr;
+  return base + (size_t)k * a.bstride;
+}
+
+__global__ void lg_zero_kernel(unsigned long long *norms, int64_t nnorms, int *flags, int64_t nflags) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < nnorms) norms[i] = 0ull;
+  if (i < nflags) flags[i] = 0;
+}
+
+// Copy of the group's inputs into buffer 0 (zero padded, real form for complex input) and
+// partial column sums of |A| over kLargeRB rows.  Grid (np / 256, np / kLargeRB, count).
+__global__ __launch_bounds__(256) void lg_load_kernel(LargeArgs a, double *partial, int nrb, int *flags) {
+  const int col = blockIdx.x * 256 + threadIdx.x;
+  if (col >= a.np) return;
+  const int rb = blockIdx.y;
+  const int mi = blockIdx.z;
+  const int n = a.n, nin = a.nin, np = a.np, cx = a.cplx;
+  cgdouble *A = gptr(a.A + (a.g0 + mi) * a.io_stride);
+  gdouble *B0 = gptr(a.ws + (size_t)mi * a.mstride);
+  double acc = 0.0;
+  int bad = 0;
+  for (int r0 = rb * kLargeRB; r0 < (rb + 1) * kLargeRB; r0 += 16) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int r = r0 + u;
+      double x = 0.0;
+      if (r < n && col < n) {
+        if (!cx) {
+          x = A[(size_t)r * n + col];
+        } else {
+          const int ri = r < nin ? r : r - nin, ci = col < nin ? col : col - nin;
+          const bool im = (r < nin) != (col < nin);
+          x = A[2 * ((size_t)ri * nin + ci) + (im ? 1 : 0)];
+          if (im && r < nin) x = -x;
+        }
+      }
+      v[u] = x;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      bad |= !isfinite(v[u]);
+      acc += fabs(v[u]);
+      B0[(size_t)(r0 + u) * np + col] = v[u];
+    }
+  }
+  partial[((size_t)mi * nrb + rb) * np + col] = acc;
+  if (bad) atomicOr(&flags[mi], 1);
+}
+
+// Partial column sums of |buffer sel| for the listed matrices.  Grid (np / 256, nrb, count).
+__global__ __launch_bounds__(256) void lg_colsum_kernel(LargeArgs a, int sel, double *partial, int nrb) {
+  const int col = blockIdx.x * 256 + threadIdx.x;
+  if (col >= a.np) return;
+  const int rb = blockIdx.y;
+  const int mi = a.list[blockIdx.z];
+  cgdouble *B = gptr(a.ws + (size_t)mi * a.mstride + (size_t)sel * a.bstride);
+  double acc = 0.0;
+  for (int r0 = rb * kLargeRB; r0 < (rb + 1) * kLargeRB; r0 += 16) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = B[(size_t)(r0 + u) * a.np + col];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc += fabs(v[u]);
+  }
+  partial[((size_t)mi * nrb + rb) * a.np + col] = acc;
+}
+
+// Column sums in row-block order, then the maximum over columns into norms[mi] (bit pattern
+// of a non-negative double, monotone as an unsigned integer).  Grid (np / 256, count).
+__global__ __launch_bounds__(256) void lg_colmax_kernel(LargeArgs a, const double *partial, int nrb,
+                                                        unsigned long long *norms, int use_list) {
+  const int col = blockIdx.x * 256 + threadIdx.x;
+  const int mi = use_list ? a.list[blockIdx.y] : blockIdx.y;
+  double s = 0.0;
+  if (col < a.np)
+    for (int rb = 0; rb < nrb; ++rb) s += partial[((size_t)mi * nrb + rb) * a.np + col];
+  __shared__ double red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(&norms[mi], (unsigned long long)__double_as_longlong(red[0]));
+}
+
+// (m, s) and coefficients per matrix.  alpha: use ||A^2||, ||A^3|| where formed (norm bits
+// zero and m_plain below the degree that forms them mean "not formed").
+__global__ void lg_select_kernel(LargeArgs a, int count, int stride, const unsigned long long *norms,
+                                 const int *flags, int alpha, Consts k, int32_t *status, double *coef) {
+  const int mi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (mi >= count) return;
+  const int64_t gb = a.g0 + mi;
+  int32_t *m_arr = const_cast<int32_t *>(a.m_arr), *s_arr = const_cast<int32_t *>(a.s_arr);
+  if (flags[mi]) {
+    m_arr[gb] = -1; s_arr[gb] = -1;
+    if (status) status[gb] = EXPM_E_NONFINITE;
+    return;
+  }
+  const double eta = __longlong_as_double((long long)norms[mi]);
+  int m, s;
+  select_ms(k.theta, 0, eta, -1.0, -1.0, &m, &s);
+  if (alpha && m >= 2) {
+    const double n2 = __longlong_as_double((long long)norms[stride + mi]);
+    const double n3 = m >= 12 ? __longlong_as_double((long long)norms[2 * stride + mi]) : -1.0;
+    select_ms(k.theta, 1, eta, n2, n3, &m, &s);
+  }
+  m_arr[gb] = m; s_arr[gb] = s;
+  if (status) status[gb] = EXPM_OK;
+  make_coefs(k, m, s, coef + (size_t)mi * 64);
+}
+
+// One 128 x 128 output tile of a GEMM step for matrix list[blockIdx.y].
+__global__ __launch_bounds__(512, 1) void lg_gemm_kernel(LargeArgs a) {
+  const int mi = a.list[blockIdx.y];
+  const int64_t gb = a.g0 + mi;
+  const int m = a.m_arr[gb], s = a.s_arr[gb];
+  const int tiles = a.np / kLargeTile;
+  const int tm = blockIdx.x / tiles, tn = blockIdx.x - tm * tiles;
+  if (threadIdx.x == 0) {
+    EpiDesc &d = g_ep;
+    d.P = sel_ptr(a, mi, a.p, m, s);
+    d.Q = sel_ptr(a, mi, a.q, m, s);
+    d.b0 = sel_ptr(a, mi, 0, m, s); d.b1 = sel_ptr(a, mi, 1, m, s); d.b2 = sel_ptr(a, mi, 2, m, s);
+    d.in0 = a.in0 >= 0 ? sel_ptr(a, mi, a.in0, m, s) : nullptr;
+    d.in1 = a.in1 >= 0 ? sel_ptr(a, mi, a.in1, m, s) : nullptr;
+    for (int j = 0; j < 5; ++j) d.o[j] = a.o[j] >= 0 ? sel_ptr(a, mi, a.o[j], m, s) : nullptr;
+    double *dst = sel_ptr(a, mi, a.dst, m, s);
+    if (dst) {
+      d.dst = dst; d.dst_ld = a.np; d.dst_nvalid = a.np; d.cplx = 0;
+    } else {
+      d.dst = a.E + gb * a.io_stride; d.dst_ld = a.n; d.dst_nvalid = a.nin; d.cplx = a.cplx;
+    }
+    d.kind = a.kind;
+    d.np = a.np;
+    for (int i = 0; i < 64; ++i) d.c[i] = a.coef[(size_t)mi * 64 + i];
+  }
+  __syncthreads();
+  TileLds<LS> &L = *reinterpret_cast<TileLds<LS> *>(lds_pool<8>());
+  const int wave = threadIdx.x >> 6;
+  const int wr = wave / LS::WC, wc = wave % LS::WC;
+  const int wr_row = wr * LS::BR * 16, wc_col = wc * LS::BC * 16;
+  const int m0 = tm * kLargeTile, n0 = tn * kLargeTile;
+  dbl4 acc[LS::TPW];
+  tile_gemm<LS>(gptr(g_ep.P), a.np, gptr(g_ep.Q), a.np, a.np, a.np, a.np, m0, n0, L, true, wr_row, wc_col, acc);
+  if (a.kind == EK_STORE) {
+    store_acc<LS>(acc, m0 + wr_row, n0 + wc_col);
+    return;
+  }
+  __syncthreads();
+  double *cbuf = lds_pool<8>();
+  stage_acc<LS, LDC_L>(cbuf, acc, wr_row, wc_col);
+  __syncthreads();
+  run_epilogue<8>(m0, n0, kLargeTile, kLargeTile, LDC_L);
+}
+
+// Elementwise steps (no product), kinds LC1, LC2 (T = I + c0 A [+ c1 A^2]), LC4W, LC8W,
+// LC12.  Grid (np * np / (256 * 4), count).
+enum ElemKind { LC1 = 0, LC2 = 1, LC4W = 2, LC8W = 3, LC12 = 4, LCNAN = 5 };
+
+__global__ __launch_bounds__(256) void lg_elem_kernel(LargeArgs a) {
+  const int mi = a.list[blockIdx.y];
+  const int64_t gb = a.g0 + mi;
+  const int m = a.m_arr[gb], s = a.s_arr[gb];
+  const double *c = a.coef + (size_t)mi * 64;
+  cgdouble *B0 = gptr(sel_ptr(a, mi, 0, m, s));
+  cgdouble *B1 = gptr(sel_ptr(a, mi, 1, m, s));
+  cgdouble *B2 = gptr(sel_ptr(a, mi, 2, m, s));
+  double *dstp = a.kind == LCNAN ? nullptr : sel_ptr(a, mi, a.dst, m, s);
+  gdouble *dst = dstp ? gptr(dstp) : gptr(a.E + gb * a.io_stride);
+  const int dld = dstp ? a.np : a.n, dnv = dstp ? a.np : a.nin, dcx = dstp ? 0 : a.cplx;
+  const int np = a.np;
+  const int64_t total = (int64_t)np * np;
+  for (int u = 0; u < 4; ++u) {
+    const int64_t e = ((int64_t)blockIdx.x * 4 + u) * 256 + threadIdx.x;
+    if (e >= total) break;
+    const int r = (int)(e / np), cc = (int)(e - (int64_t)r * np);
+    const double id = (r == cc) ? 1.0 : 0.0;
+    switch (a.kind) {
+      case LC1: put_dst(dst, dld, dnv, dcx, r, cc, id + c[0] * B0[e]); break;
+      case LC2: put_dst(dst, dld, dnv, dcx, r, cc, id + c[0] * B0[e] + c[1] * B1[e]); break;
+      case LC4W: gptr(sel_ptr(a, mi, 2, m, s))[e] = c[2] * id + c[3] * B0[e] + c[4] * B1[e]; break;
+      case LC8W: gptr(sel_ptr(a, mi, 2, m, s))[e] = c[0] * B0[e] + c[1] * B1[e]; break;
+      case LCNAN: put_dst(dst, dld, dnv, dcx, r, cc, __builtin_nan("")); break;
+      case LC12: {
+        const double x1 = B0[e], x2 = B1[e], x3 = B2[e];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          gptr(sel_ptr(a, mi, 3 + j, m, s))[e] = c[4 * j] * id + c[4 * j + 1] * x1 + c[4 * j + 2] * x2 + c[4 * j + 3] * x3;
+      } break;
+    }
+  }
+}
+
+}  // namespace
+
+LargeLayout large_layout(int64_t n_real, int64_t batch) {
+  LargeLayout L;
+  L.n = n_real;
+  L.np = (n_real + kLargeTile - 1) / kLargeTile * kLargeTile;
+  const int64_t tiles = (L.np / kLargeTile) * (L.np / kLargeTile);
+  int64_t g = (2048 + tiles - 1) / tiles;   // about 2048 output tiles per launch
+  if (g < 1) g = 1;
+  if (g > batch) g = batch;
+  L.group = g;
+  L.nrb = L.np / kLargeRB;
+  const size_t nn = (size_t)L.np * L.np;
+  L.bufs_off = 0;
+  L.partial_off = align_up(L.bufs_off + (size_t)g * kLargeBufs * nn * sizeof(double));
+  L.norms_off = align_up(L.partial_off + (size_t)g * L.nrb * L.np * sizeof(double));
+  L.flags_off = align_up(L.norms_off + (size_t)3 * g * sizeof(unsigned long long));
+  L.coef_off = align_up(L.flags_off + (size_t)g * sizeof(int));
+  L.list_off = align_up(L.coef_off + (size_t)g * 64 * sizeof(double));
+  L.total = align_up(L.list_off + (size_t)g * 64 * sizeof(int32_t));
+  return L;
+}
+
+namespace {
+
+struct Launcher {
+  const LargeCall &c;
+  const LargeLayout &L;
+  LargeArgs base;
+  hipStream_t st;
+  int32_t *list_dev;
+  bool ok = true;
+
+  std::vector<std::vector<int32_t>> keep;  // host copies stay alive until the group's sync
+
+  // Uploads `idx` as the launch list and returns the device pointer (slots are reused in
+  // stream order: a later copy into a slot runs after the kernels that read it).
+  const int32_t *upload(const std::vector<int32_t> &idx, int slot) {
+    int32_t *d = list_dev + (size_t)(slot % 64) * L.group;
+    keep.push_back(idx);
+    if (hipMemcpyAsync(d, keep.back().data(), idx.size() * sizeof(int32_t), hipMemcpyHostToDevice, st) != hipSuccess)
+      ok = false;
+    return d;
+  }
+
+  void gemm(const std::vector<int32_t> &idx, int slot, int kind, int p, int q, int dst,
+            int in0 = SEL_NONE, int in1 = SEL_NONE, std::vector<int> o = {}, int round = 0) {
+    if (idx.empty() || !ok) return;
+    LargeArgs a = base;
+    a.list = upload(idx, slot);
+    a.kind = kind; a.p = p; a.q = q; a.dst = dst; a.in0 = in0; a.in1 = in1; a.round = round;
+    for (int j = 0; j < 5; ++j) a.o[j] = j < (int)o.size() ? o[j] : SEL_NONE;
+    const int tiles = (int)((L.np / kLargeTile) * (L.np / kLargeTile));
+    hipLaunchKernelGGL(lg_gemm_kernel, dim3(tiles, (unsigned)idx.size()), dim3(512), 0, st, a);
+    if (hipGetLastError() != hipSuccess) ok = false;
+  }
+
+  void elem(const std::vector<int32_t> &idx, int slot, int kind, int dst) {
+    if (idx.empty() || !ok) return;
+    LargeArgs a = base;
+    a.list = upload(idx, slot);
+    a.kind = kind; a.dst = dst;
+    const int64_t blocks = (L.np * L.np + 1023) / 1024;
+    hipLaunchKernelGGL(lg_elem_kernel, dim3((unsigned)blocks, (unsigned)idx.size()), dim3(256), 0, st, a);
+    if (hipGetLastError() != hipSuccess) ok = false;
+  }
+};
+
+}  // namespace
+
+expm_status_t run_large(const LargeCall &c, hipStream_t st) {
+  const int64_t n = c.cplx ? 2 * c.nin : c.nin;
+  LargeLayout L = large_layout(n, c.batch);
+  if (!c.ws || c.ws_bytes < L.total) return EXPM_E_WORKSPACE;
+  char *base = (char *)c.ws;
+  double *bufs = (double *)(base + L.bufs_off);
+  double *partial = (double *)(base + L.partial_off);
+  unsigned long long *norms = (unsigned long long *)(base + L.norms_off);
+  int *flags = (int *)(base + L.flags_off);
+  double *coef = (double *)(base + L.coef_off);
+  int32_t *lists = (int32_t *)(base + L.list_off);
+
+  LargeArgs a;
+  memset(&a, 0, sizeof(a));
+  a.ws = bufs;
+  a.bstride = (size_t)L.np * L.np;
+  a.mstride = kLargeBufs * a.bstride;
+  a.np = (int)L.np; a.n = (int)n; a.nin = (int)c.nin; a.cplx = c.cplx;
+  a.A = c.A; a.E = c.E;
+  a.io_stride = c.nin * c.nin * (c.cplx ? 2 : 1);
+  a.m_arr = c.m_out; a.s_arr = c.s_out;
+  a.coef = coef;
+  for (int j = 0; j < 5; ++j) a.o[j] = SEL_NONE;
+
+  std::vector<int32_t> mh, sh;
+  for (int64_t g0 = 0; g0 < c.batch; g0 += L.group) {
+    const int cnt = (int)std::min<int64_t>(L.group, c.batch - g0);
+    a.g0 = g0;
+    Launcher run{c, L, a, st, lists};
+    std::vector<int32_t> all(cnt);
+    for (int i = 0; i < cnt; ++i) all[i] = i;
+    // norms (3 per matrix) and non-finite flags start at zero
+    hipLaunchKernelGGL(lg_zero_kernel, dim3((unsigned)((3 * L.group + 255) / 256)), dim3(256), 0, st, norms,
+                       3 * L.group, flags, L.group);
+    hipLaunchKernelGGL(lg_load_kernel, dim3((unsigned)((L.np + 255) / 256), (unsigned)L.nrb, cnt),
+                       dim3(256), 0, st, a, partial, (int)L.nrb, flags);
+    hipLaunchKernelGGL(lg_colmax_kernel, dim3((unsigned)((L.np + 255) / 256), cnt), dim3(256), 0, st, a, partial, (int)L.nrb,
+                       norms, 0);
+    if (hipGetLastError() != hipSuccess) return EXPM_E_HIP;
+    if (c.sel == EXPM_SEL_ALPHA) {
+      // plain choice first: it says which powers the method forms anyway
+      hipLaunchKernelGGL(lg_select_kernel, dim3((cnt + 63) / 64), dim3(64), 0, st, a, cnt, (int)L.group, norms,
+                         flags, 0, c.k, c.status, coef);
+      mh.assign(cnt, 0);
+      if (hipMemcpyAsync(mh.data(), c.m_out + g0, cnt * sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return EXPM_E_HIP;
+      std::vector<int32_t> l2, l3;
+      for (int i = 0; i < cnt; ++i) {
+        if (mh[i] >= 2) l2.push_back(i);
+        if (mh[i] >= 12) l3.push_back(i);
+      }
+      run.gemm(l2, 0, EK_STORE, 0, 0, 1);
+      run.gemm(l3, 1, EK_STORE, 1, 0, 2);
+      LargeArgs b2 = a;
+      if (!l2.empty()) {
+        b2.list = run.upload(l2, 2);
+        hipLaunchKernelGGL(lg_colsum_kernel, dim3((unsigned)((L.np + 255) / 256), (unsigned)L.nrb, (unsigned)l2.size()),
+                           dim3(256), 0, st, b2, 1, partial, (int)L.nrb);
+        hipLaunchKernelGGL(lg_colmax_kernel, dim3((unsigned)((L.np + 255) / 256), (unsigned)l2.size()), dim3(256), 0, st, b2,
+                           partial, (int)L.nrb, norms + L.group, 1);
+      }
+      if (!l3.empty()) {
+        b2.list = run.upload(l3, 3);
+        hipLaunchKernelGGL(lg_colsum_kernel, dim3((unsigned)((L.np + 255) / 256), (unsigned)L.nrb, (unsigned)l3.size()),
+                           dim3(256), 0, st, b2, 2, partial, (int)L.nrb);
+        hipLaunchKernelGGL(lg_colmax_kernel, dim3((unsigned)((L.np + 255) / 256), (unsigned)l3.size()), dim3(256), 0, st, b2,
+                           partial, (int)L.nrb, norms + 2 * L.group, 1);
+      }
+      // the alpha selection reads norms[group + i] and norms[2 group + i]
+      hipLaunchKernelGGL(lg_select_kernel, dim3((cnt + 63) / 64), dim3(64), 0, st, a, cnt, (int)L.group, norms,
+                         flags, 1, c.k, c.status, coef);
+    } else {
+      hipLaunchKernelGGL(lg_select_kernel, dim3((cnt + 63) / 64), dim3(64), 0, st, a, cnt, (int)L.group, norms,
+                         flags, 0, c.k, c.status, coef);
+    }
+    if (hipGetLastError() != hipSuccess || !run.ok) return EXPM_E_HIP;
+    mh.assign(cnt, 0);
+    sh.assign(cnt, 0);
+    if (hipMemcpyAsync(mh.data(), c.m_out + g0, cnt * sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(sh.data(), c.s_out + g0, cnt * sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return EXPM_E_HIP;
+    if (c.select_only) continue;
+
+    // ---- powers (the alpha path formed them already) ----
+    std::vector<int32_t> l2, l3, lm[19], lnan;
+    int smax = 0;
+    for (int i = 0; i < cnt; ++i) {
+      const int m = mh[i];
+      if (m < 1) { lnan.push_back(i); continue; }  // non-finite input
+      if (m >= 2) l2.push_back(i);
+      if (m >= 12) l3.push_back(i);
+      lm[m].push_back(i);
+      smax = std::max(smax, (int)sh[i]);
+    }
+    if (c.sel != EXPM_SEL_ALPHA) {
+      run.gemm(l2, 0, EK_STORE, 0, 0, 1);
+      run.gemm(l3, 1, EK_STORE, 1, 0, 2);
+    }
+    run.elem(lnan, 1, LCNAN, SEL_NONE);
+    // ---- product stage per degree ----
+    run.elem(lm[1], 2, LC1, SEL_TDST);
+    run.elem(lm[2], 3, LC2, SEL_TDST);
+    run.elem(lm[4], 4, LC4W, 2);
+    run.gemm(lm[4], 4, EK_M4, 1, 2, SEL_TDST);
+    run.elem(lm[8], 5, LC8W, 2);
+    run.gemm(lm[8], 5, EK_M8A, 1, 2, SEL_NONE, SEL_NONE, SEL_NONE, {3, 4});
+    run.gemm(lm[8], 5, EK_M8B, 3, 4, SEL_TDST);
+    run.elem(lm[12], 6, LC12, SEL_NONE);
+    run.gemm(lm[12], 6, EK_SPLIT2, 6, 6, SEL_NONE, 5, 4, {0, 1});
+    run.gemm(lm[12], 6, EK_ADD1, 1, 0, SEL_TDST, 3);
+    run.gemm(lm[18], 7, EK_M18A, 2, 2, SEL_NONE, SEL_NONE, SEL_NONE, {3, 4, 5, 6, 7});
+    run.gemm(lm[18], 7, EK_SPLIT2, 3, 7, SEL_NONE, 6, 5, {0, 1});
+    run.gemm(lm[18], 7, EK_ADD1, 1, 0, SEL_TDST, 4);
+    // ---- squarings: round r covers the matrices with s >= r ----
+    for (int r = 1; r <= smax; ++r) {
+      std::vector<int32_t> lr;
+      for (int i = 0; i < cnt; ++i)
+        if (mh[i] >= 1 && sh[i] >= r) lr.push_back(i);
+      run.gemm(lr, 8 + (r & 1) * 8, EK_STORE, SEL_SQSRC, SEL_SQSRC, SEL_SQDST, SEL_NONE, SEL_NONE, {}, r);
+    }
+    if (!run.ok) return EXPM_E_HIP;
+    // lists are uploaded asynchronously from host vectors that die here: finish the group
+    if (hipStreamSynchronize(st) != hipSuccess) return EXPM_E_HIP;
+  }
+  return EXPM_OK;
+}
+
+}  // namespace expm

@@ -41,8 +41,22 @@ struct EpiDesc {
   double *o[5];
   double *dst;
   int kind, np, dst_ld, dst_nvalid;
+  int cplx;  // dst is an interleaved complex n x n matrix (n = dst_nvalid) holding the
+             // realified result: rows 0..n-1 carry the real part, rows n..2n-1 the imaginary
   double c[64];
 };
+
+// Store of one element of a result to the destination described by (dst, ld, nv, cplx).
+// Real: element (r, c) of the leading nv x nv block.  Complex (realified 2nv x 2nv matrix
+// [[Re, -Im], [Im, Re]]): column c < nv of the upper half is Re, of the lower half Im.
+__device__ inline void put_dst(gdouble *dst, int ld, int nv, int cplx, int r, int c, double v) {
+  if (!cplx) {
+    if (r < nv && c < nv) dst[r * ld + c] = v;
+  } else if (c < nv) {
+    if (r < nv) dst[2 * (r * nv + c)] = v;
+    else if (r < 2 * nv) dst[2 * ((r - nv) * nv + c) + 1] = v;
+  }
+}
 
 __shared__ EpiDesc g_ep;
 
@@ -61,7 +75,10 @@ constexpr int kPool4 = 3 * (64 * 16 + 16 * 64);  // 3 stages of 64 x 16 + 16 x 6
 constexpr int kPool8 = 128 * 129;   // >= 3 stages of 128 x 16 + 16 x 128, >= 128 x (128 + 1)
 __shared__ double g_pool4[kPool4];
 __shared__ double g_pool8[kPool8];
-template <int NW> __device__ inline double *lds_pool() { return NW == 4 ? g_pool4 : g_pool8; }
+template <int NW> __device__ inline double *lds_pool() {
+  if constexpr (NW == 4) return g_pool4;
+  else return g_pool8;
+}
 
 // Walks the LDS copy of a chunk (ld ldc) with consecutive threads on consecutive columns.
 // Each thread gathers the NIN global inputs of kEpiU elements before computing.
@@ -103,12 +120,12 @@ __device__ inline void run_epilogue(int row0, int col0, int rows, int cols, int 
   switch (g_ep.kind) {
     case EK_M4: {
       gdouble *dst = gptr(g_ep.dst);
-      const int ld = g_ep.dst_ld, nv = g_ep.dst_nvalid;
+      const int ld = g_ep.dst_ld, nv = g_ep.dst_nvalid, cx = g_ep.cplx;
       const double c0 = c[0], c1 = c[1];
       cgdouble *const in[1] = {gptr(g_ep.b0)};
       for_chunk<NW, 1>(cbuf, row0, col0, rows, cols, ldc, np, in, [&](int r, int cc, int, double v, const double *x) {
         const double t = (r == cc ? 1.0 : 0.0) + c0 * x[0] + c1 * v;
-        if (r < nv && cc < nv) dst[r * ld + cc] = t;
+        put_dst(dst, ld, nv, cx, r, cc, t);
       });
     } break;
     case EK_M8A: {
@@ -123,21 +140,21 @@ __device__ inline void run_epilogue(int row0, int col0, int rows, int cols, int 
     } break;
     case EK_M8B: {
       gdouble *dst = gptr(g_ep.dst);
-      const int ld = g_ep.dst_ld, nv = g_ep.dst_nvalid;
+      const int ld = g_ep.dst_ld, nv = g_ep.dst_nvalid, cx = g_ep.cplx;
       const double c8 = c[8], c9 = c[9], c10 = c[10];
       cgdouble *const in[2] = {gptr(g_ep.b0), gptr(g_ep.b1)};
       for_chunk<NW, 2>(cbuf, row0, col0, rows, cols, ldc, np, in, [&](int r, int cc, int, double v, const double *x) {
         const double t = v + (r == cc ? c8 : 0.0) + c9 * x[0] + c10 * x[1];
-        if (r < nv && cc < nv) dst[r * ld + cc] = t;
+        put_dst(dst, ld, nv, cx, r, cc, t);
       });
     } break;
     case EK_ADD1: {
       gdouble *dst = gptr(g_ep.dst);
-      const int ld = g_ep.dst_ld, nv = g_ep.dst_nvalid;
+      const int ld = g_ep.dst_ld, nv = g_ep.dst_nvalid, cx = g_ep.cplx;
       cgdouble *const in[1] = {gptr(g_ep.in0)};
       for_chunk<NW, 1>(cbuf, row0, col0, rows, cols, ldc, np, in, [&](int r, int cc, int, double v, const double *x) {
         const double t = v + x[0];
-        if (r < nv && cc < nv) dst[r * ld + cc] = t;
+        put_dst(dst, ld, nv, cx, r, cc, t);
       });
     } break;
     case EK_SPLIT2: {
@@ -170,6 +187,42 @@ __device__ inline void run_epilogue(int row0, int col0, int rows, int cols, int 
   }
 }
 
+// Plain product: each lane stores its accumulators to the g_ep destination (lanes 0..15 of
+// a register cover 16 consecutive columns of one row).  (row0, col0): the wave's block.
+template <class S>
+__device__ inline void store_acc(const dbl4 (&acc)[S::TPW], int row0, int col0) {
+  gdouble *dst = gptr(g_ep.dst);
+  int ld = g_ep.dst_ld;
+  const int nv = g_ep.dst_nvalid, cx = g_ep.cplx;
+  asm volatile("" : "+v"(ld));  // keep the store addresses out of the K loop
+  const int lane = threadIdx.x & 63;
+  const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int i = 0; i < S::BR; ++i)
+#pragma unroll
+    for (int j = 0; j < S::BC; ++j) {
+      const int col = col0 + j * 16 + lr;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) put_dst(dst, ld, nv, cx, row0 + i * 16 + 4 * r + lk, col, acc[i * S::BC + j][r]);
+    }
+}
+
+// Stages the wave's accumulators into the chunk copy (ld LDC) at chunk-relative (r0, c0).
+template <class S, int LDC>
+__device__ inline void stage_acc(double *cbuf, const dbl4 (&acc)[S::TPW], int r0, int c0) {
+  const int lane = threadIdx.x & 63;
+  int lrow = lane >> 4;
+  asm volatile("" : "+v"(lrow));
+  const int lr = lane & 15;
+#pragma unroll
+  for (int i = 0; i < S::BR; ++i)
+#pragma unroll
+    for (int j = 0; j < S::BC; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        cbuf[(r0 + i * 16 + 4 * r + lrow) * LDC + c0 + j * 16 + lr] = acc[i * S::BC + j][r];
+}
+
 template <int NW, int T>
 __device__ __noinline__ void gemm_t() {
   typedef typename TileFor<NW, T>::S S;
@@ -180,9 +233,7 @@ __device__ __noinline__ void gemm_t() {
   TileLds<S> &L = *reinterpret_cast<TileLds<S> *>(lds_pool<NW>());
   cgdouble *P = gptr(g_ep.P);
   cgdouble *Q = gptr(g_ep.Q);
-  const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int lr = lane & 15, lk = lane >> 4;
   const bool has_block = wave < S::WR * S::WC;
   const int wr = wave / S::WC, wc = wave % S::WC;
   const int kind = g_ep.kind;
@@ -196,39 +247,13 @@ __device__ __noinline__ void gemm_t() {
       dbl4 acc[S::TPW];
       tile_gemm<S>(P, np, Q, np, np, np, np, m0, n0, L, active, wr_row, wc_col, acc);
       if (kind == EK_STORE) {
-        if (active) {
-          gdouble *dst = gptr(g_ep.dst);
-          int ld = g_ep.dst_ld;
-          const int nv = g_ep.dst_nvalid;
-          asm volatile("" : "+v"(ld));  // keep the store addresses out of the K loop
-#pragma unroll
-          for (int i = 0; i < S::BR; ++i)
-#pragma unroll
-            for (int j = 0; j < S::BC; ++j) {
-              const int col = n0 + wc_col + j * 16 + lr;
-#pragma unroll
-              for (int r = 0; r < 4; ++r) {
-                const int row = m0 + wr_row + i * 16 + 4 * r + lk;
-                if (row < nv && col < nv) dst[row * ld + col] = acc[i * S::BC + j][r];
-              }
-            }
-        }
+        if (active) store_acc<S>(acc, m0 + wr_row, n0 + wc_col);
         __syncthreads();  // the next chunk's loads reuse the stage ring
         continue;
       }
       __syncthreads();  // stage ring retired: it becomes the chunk copy of C
       double *cbuf = lds_pool<NW>();
-      if (active) {
-        int lrow = lk;
-        asm volatile("" : "+v"(lrow));
-#pragma unroll
-        for (int i = 0; i < S::BR; ++i)
-#pragma unroll
-          for (int j = 0; j < S::BC; ++j)
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-              cbuf[(wr_row + i * 16 + 4 * r + lrow) * LDC + wc_col + j * 16 + lr] = acc[i * S::BC + j][r];
-      }
+      if (active) stage_acc<S, LDC>(cbuf, acc, wr_row, wc_col);
       __syncthreads();
       const int rows = (np - m0) < S::BM ? (np - m0) : S::BM;
       const int cols = (np - n0) < S::BN ? (np - n0) : S::BN;

@@ -117,7 +117,8 @@ __device__ inline void mma_panel(const double *lp, const double *lq, int wr_row,
   asm volatile("" : "+v"(lane));
   const int lr = lane & 15, lk = lane >> 4;
   // Blocks of 9+ tiles keep only two k steps of fragments in flight (register budget).
-#pragma unroll (S::TPW >= 9 ? 2 : 4)
+  constexpr int KU = S::TPW >= 9 ? 2 : 4;
+#pragma unroll KU
   for (int kk = 0; kk < kKP; kk += 4) {
     if (kk < kend) {
       const int k = kk + lk;

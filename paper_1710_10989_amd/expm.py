@@ -133,3 +133,25 @@ def batched(batch, u=None, prec="fp64", selector="plain", workspace=None, out=No
                               ws.numel(), _stream())
     N.check(st, "expm_batched")
     return E, m, s, status
+
+
+def batched_uniform(A, u=None, prec="fp64", selector="plain", workspace=None, out=None):
+    """e^A for a stack A of shape (batch, n, n) of same-order matrices (float64 or complex128).
+    Returns (E, m, s, status) device tensors."""
+    if A.dim() != 3 or A.shape[1] != A.shape[2]:
+        raise ValueError("A must have shape (batch, n, n)")
+    if not A.is_cuda or A.dtype not in (torch.float64, torch.complex128):
+        raise ValueError("A must be a float64 or complex128 device tensor")
+    A = A.contiguous()
+    nb, n = A.shape[0], A.shape[1]
+    o = _opts(A.dtype, prec, selector, u)
+    ws = workspace if workspace is not None else _workspace(
+        N.lib().expm_workspace_bytes(n, nb, ctypes.byref(o)), A.device)
+    E = out if out is not None else torch.empty_like(A)
+    m = torch.empty(nb, dtype=torch.int32, device=A.device)
+    s = torch.empty_like(m)
+    status = torch.empty_like(m)
+    st = N.lib().expm_batched_uniform(_ptr(A), _ptr(E), n, nb, ctypes.byref(o), _ptr(m), _ptr(s), _ptr(status),
+                                      _ptr(ws), ws.numel(), _stream())
+    N.check(st, "expm_batched_uniform")
+    return E, m, s, status

@@ -1,0 +1,159 @@
+"""GPU parity for the tiled path (real orders above 256, complex orders above 128) and for
+complex inputs on both paths.
+
+Tolerance as for the fused path: relative 1-norm error <= 1e-12 against the oracle's direct
+Taylor result (FP64 target).  At full size (n = 8192) the oracle cannot run: the input is
+A = H D H with H = I - 2 v v^T a Householder reflector and D diagonal, a dense matrix whose
+exponential H e^D H has a closed form computable in O(n^2).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1710_10989_amd as P
+    assert torch.cuda.is_available()
+    return P
+
+
+def dev(A):
+    return torch.from_numpy(np.ascontiguousarray(A)).cuda()
+
+
+def test_large_ragged_order(P, orc):
+    g = np.random.default_rng(300)
+    n = 300
+    A = g.standard_normal((n, n))
+    A *= 2.0 / np.abs(A).sum(0).max()
+    say("case large n=300")
+    E, m, s, st = P.taylor(dev(A))
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    assert (int(m.item()), int(s.item())) == orc.select_plain(orc.norm1(A)) == (18, 1)
+    ref, _ = orc.expm_taylor(A, prec="d")
+    assert orc.rel_err_1(E.cpu().numpy(), ref) <= TOL
+
+
+def test_large_batch_every_degree(P, orc):
+    g = np.random.default_rng(512)
+    n = 384
+    targets = [1e-17, 1e-9, 1e-4, 0.03, 0.25, 1.0, 6.0, 40.0]
+    mats = []
+    for t in targets:
+        A = g.standard_normal((n, n))
+        mats.append(A * (t / np.abs(A).sum(0).max()))
+    stack = np.stack(mats)
+    say("case large batch n=384 x %d" % len(mats))
+    E, m, s, st = P.batched_uniform(dev(stack))
+    torch.cuda.synchronize()
+    E, m, s, st = E.cpu().numpy(), m.cpu().numpy(), s.cpu().numpy(), st.cpu().numpy()
+    assert np.all(st == 0)
+    refs, _ = orc.expm_taylor_batch(mats, prec="d")
+    for i, A in enumerate(mats):
+        assert (m[i], s[i]) == orc.select_plain(orc.norm1(A)), i
+        assert orc.rel_err_1(E[i], refs[i]) <= TOL, (i, targets[i])
+
+
+@pytest.mark.parametrize("kind", ["dense", "nilpotent"])
+def test_large_alpha(P, orc, kind):
+    from paper_1710_10989_amd import workloads as W
+    g = np.random.default_rng(77)
+    n = 320
+    A = W.rescale(W.structured(g, n, kind), 30.0)
+    say("case large alpha", kind)
+    E, m, s, st = P.taylor(dev(A), selector="alpha")
+    torch.cuda.synchronize()
+    m, s = int(m.item()), int(s.item())
+    nk = orc.powers_norms(A, 3)
+    mp, _ = orc.select_plain(nk[0])
+    assert (m, s) == P.select_rule([nk[0], nk[1] if mp >= 2 else -1, nk[2] if mp >= 12 else -1], "alpha")
+    ref, _ = orc.expm_taylor(A, prec="d")
+    assert orc.rel_err_1(E.cpu().numpy(), ref) <= TOL
+
+
+def test_large_select_and_nonfinite(P, orc):
+    g = np.random.default_rng(9)
+    A = g.standard_normal((260, 260))
+    A *= 9.0 / np.abs(A).sum(0).max()
+    m, s = P.select(dev(A))
+    assert (int(m.item()), int(s.item())) == orc.select_plain(orc.norm1(A))
+    A[5, 7] = np.inf
+    E, m, s, st = P.taylor(dev(A))
+    torch.cuda.synchronize()
+    assert int(st.item()) == 2 and int(m.item()) == -1
+    assert torch.isnan(E).all()
+
+
+def _hermitian(g, n, t):
+    G = g.standard_normal((n, n)) + 1j * g.standard_normal((n, n))
+    H = (G + G.conj().T) / 2
+    H /= np.max(np.abs(np.linalg.eigvalsh(H)))
+    return -1j * H * t
+
+
+@pytest.mark.parametrize("n,t", [(24, 0.3), (64, 5.0), (128, 40.0), (160, 3.0), (256, 20.0)])
+def test_complex_unitary(P, orc, n, t):
+    g = np.random.default_rng(n)
+    A = _hermitian(g, n, t)
+    say("case complex n=%d t=%g" % (n, t))
+    E, m, s, st = P.taylor(dev(A))
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    Eh = E.cpu().numpy()
+    assert np.abs(Eh.conj().T @ Eh - np.eye(n)).sum(0).max() <= 1e-12 * (1 << max(int(s.item()), 0))
+    # selection uses the 1-norm of the real form [[X, -Y], [Y, X]]
+    R = np.block([[A.real, -A.imag], [A.imag, A.real]])
+    assert (int(m.item()), int(s.item())) == orc.select_plain(orc.norm1(R))
+    if n <= 160:
+        ref, _ = orc.expm_taylor(A)
+        assert orc.rel_err_1(Eh, ref) <= TOL
+
+
+def test_complex_ragged_batch(P, orc):
+    g = np.random.default_rng(5)
+    mats = [_hermitian(g, n, t) for n, t in ((17, 0.1), (40, 2.0), (96, 12.0), (128, 0.5))]
+    from paper_1710_10989_amd.expm import Batch
+    B = Batch.from_host(mats, dtype=torch.complex128)
+    say("case complex ragged batch")
+    E, m, s, st = P.batched(B)
+    torch.cuda.synchronize()
+    assert np.all(st.cpu().numpy() == 0)
+    for A, X in zip(mats, B.unpack(E)):
+        ref, _ = orc.expm_taylor(A)
+        assert orc.rel_err_1(X, ref) <= TOL
+
+
+def test_full_size_n8192_householder(P):
+    # Dense A = H D H (H = I - 2 v v^T), ||A||_1 = 20: e^A = H e^D H in closed form.
+    n = 8192
+    g = np.random.default_rng(8192)
+    d = g.uniform(-1.0, 1.0, n)
+    v = g.standard_normal(n)
+    v /= np.linalg.norm(v)
+    A = np.diag(d) - 2 * np.outer(v, v * d) - 2 * np.outer(v * d, v) + 4 * (v @ (d * v)) * np.outer(v, v)
+    scale = 20.0 / np.abs(A).sum(0).max()
+    A *= scale
+    d *= scale
+    ed = np.exp(d)
+    R = np.diag(ed) - 2 * np.outer(v, v * ed) - 2 * np.outer(v * ed, v) + 4 * (v @ (ed * v)) * np.outer(v, v)
+    say("case full size n=8192")
+    E, m, s, st = P.taylor(dev(A))
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    assert (int(m.item()), int(s.item())) == (18, 5)
+    X = E.cpu().numpy()
+    err = np.abs(X - R).sum(0).max() / np.abs(R).sum(0).max()
+    say("n=8192 rel err", err)
+    assert err <= TOL
