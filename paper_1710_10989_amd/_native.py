@@ -16,7 +16,7 @@ EXPM_PREC_FP64, EXPM_PREC_FP32, EXPM_PREC_BF16X3 = 0, 1, 2
 EXPM_SEL_PLAIN, EXPM_SEL_ALPHA, EXPM_SEL_LEARNED = 0, 1, 2
 
 EXPORTED = ("expm_status_string", "expm_theta", "expm_select_rule", "expm_workspace_bytes",
-            "expm_select", "expm_taylor", "expm_batched", "expm_batched_uniform")
+            "expm_select", "expm_taylor", "expm_batched", "expm_batched_stage", "expm_batched_uniform")
 
 
 class ExpmOpts(ctypes.Structure):
@@ -51,6 +51,8 @@ def lib():
         L.expm_taylor.argtypes = [vp, vp, i64, op, vp, vp, vp, vp, sz, vp]; L.expm_taylor.restype = i32
         L.expm_batched.argtypes = [vp, vp, vp, vp, i64, i64, op, vp, vp, vp, vp, sz, vp]
         L.expm_batched.restype = i32
+        L.expm_batched_stage.argtypes = [vp, vp, vp, vp, i64, i64, op, vp, vp, vp, vp, sz, vp, i32]
+        L.expm_batched_stage.restype = i32
         L.expm_batched_uniform.argtypes = [vp, vp, i64, i64, op, vp, vp, vp, vp, sz, vp]
         L.expm_batched_uniform.restype = i32
         _lib = L

@@ -3,6 +3,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 
 #include "expm_fused.h"
@@ -69,21 +70,26 @@ int grid_for(int nw, int64_t batch) {
 }
 
 struct FusedLayout {
-  size_t queue_off, order_off, slots_off, total;
-  size_t slot_doubles;
-  int slots;
+  size_t queue_off, order_off, slots8_off, slots4_off, total;
+  size_t slot8_doubles, slot4_doubles;
+  int slots8, slots4;
 };
 
+// Separate slot arrays for the two kernels, so their sweeps may also run concurrently.  The
+// 4-wave kernel only sees padded orders up to 16 (kSplitT - 1).
 FusedLayout fused_layout(int64_t n_max, int64_t batch) {
   FusedLayout L;
   const int64_t np = pad16(n_max);
-  const int g4 = grid_for(4, batch), g8 = grid_for(8, batch);
-  L.slots = g4 > g8 ? g4 : g8;
-  L.slot_doubles = (size_t)kFusedBufs * np * np;
+  const int64_t np4 = std::min<int64_t>(np, 16 * (kSplitT - 1));
+  L.slots4 = grid_for(4, batch);
+  L.slots8 = np_max_t(n_max) >= kSplitT ? grid_for(8, batch) : 0;
+  L.slot8_doubles = (size_t)kFusedBufs * np * np;
+  L.slot4_doubles = (size_t)kFusedBufs * np4 * np4;
   L.queue_off = 0;
   L.order_off = kAlign;
-  L.slots_off = L.order_off + align_up(sizeof(int32_t) * (size_t)batch);
-  L.total = L.slots_off + (size_t)L.slots * L.slot_doubles * sizeof(double);
+  L.slots8_off = L.order_off + align_up(sizeof(int32_t) * (size_t)batch);
+  L.slots4_off = L.slots8_off + align_up((size_t)L.slots8 * L.slot8_doubles * sizeof(double));
+  L.total = L.slots4_off + (size_t)L.slots4 * L.slot4_doubles * sizeof(double);
   return L;
 }
 
@@ -134,11 +140,13 @@ size_t expm_workspace_bytes(int64_t n_max, int64_t batch, const expm_opts_t *opt
   return large_layout(nr, batch).total;
 }
 
+// stage: -1 all phases; 0 sort the batch into the work queue; 1 sweep of the 8-wave kernel;
+// 2 sweep of the 4-wave kernel (stages 1 and 2 need stage 0 first, and are independent).
 static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, const int32_t *ns,
                                int64_t batch, int64_t n_uniform, int64_t n_max,
                                const expm_opts_t *opts, double u, int32_t *m_dev, int32_t *s_dev,
                                int32_t *status_dev, void *ws, size_t ws_bytes, void *stream,
-                               int select_only) {
+                               int select_only, int stage = -1) {
   // n_uniform and n_max are input orders; the kernels pad the real order
   const int cplx = opts->dtype == EXPM_C128;
   const int64_t nr_max = real_order(opts, n_max), nr_uni = real_order(opts, n_uniform);
@@ -156,8 +164,6 @@ static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, cons
   a.s_out = s_dev;
   a.status = status_dev;
   char *base = (char *)ws;
-  a.slots = (double *)(base + L.slots_off);
-  a.slot_doubles = L.slot_doubles;
   a.batch = batch;
   a.n_uniform = (int)n_uniform;
   a.np_max = (int)pad16(nr_max);
@@ -165,18 +171,27 @@ static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, cons
   a.sel = opts->sel == EXPM_SEL_LEARNED ? EXPM_SEL_ALPHA : opts->sel;
   a.select_only = select_only;
   hipStream_t st = (hipStream_t)stream;
+  FusedArgs a8 = a, a4 = a;
+  a8.slots = (double *)(base + L.slots8_off);
+  a8.slot_doubles = L.slot8_doubles;
+  a4.slots = (double *)(base + L.slots4_off);
+  a4.slot_doubles = L.slot4_doubles;
   if (ns) {
-    a.order = (const int32_t *)(base + L.order_off);
-    a.queue = (unsigned long long *)(base + L.queue_off);
-    if (launch_order(ns, batch, cplx, (int32_t *)a.order, a.queue, st) != hipSuccess) return EXPM_E_HIP;
+    a8.order = a4.order = (const int32_t *)(base + L.order_off);
+    a8.queue = a4.queue = (unsigned long long *)(base + L.queue_off);
+    if ((stage == -1 || stage == 0) &&
+        launch_order(ns, batch, cplx, (int32_t *)a8.order, a8.queue, st) != hipSuccess)
+      return EXPM_E_HIP;
     // largest orders first: the 8-wave kernel drains the front of the queue, then the 4-wave
     // kernel the rest (either range may be empty)
-    if (np_max_t(nr_max) >= kSplitT && launch_fused(a, 8, grid_for(8, batch), st) != hipSuccess) return EXPM_E_HIP;
-    if (launch_fused(a, 4, grid_for(4, batch), st) != hipSuccess) return EXPM_E_HIP;
+    if ((stage == -1 || stage == 1) && L.slots8 > 0 && launch_fused(a8, 8, L.slots8, st) != hipSuccess)
+      return EXPM_E_HIP;
+    if ((stage == -1 || stage == 2) && launch_fused(a4, 4, L.slots4, st) != hipSuccess) return EXPM_E_HIP;
   } else {
     const bool big = np_max_t(nr_uni) >= kSplitT;
-    a.split = big ? batch : 0;
-    if (launch_fused(a, big ? 8 : 4, grid_for(big ? 8 : 4, batch), st) != hipSuccess) return EXPM_E_HIP;
+    a8.split = a4.split = big ? batch : 0;
+    if (big ? launch_fused(a8, 8, L.slots8, st) != hipSuccess : launch_fused(a4, 4, L.slots4, st) != hipSuccess)
+      return EXPM_E_HIP;
   }
   return EXPM_OK;
 }
@@ -243,6 +258,22 @@ expm_status_t expm_batched(const void *A_dev, void *E_dev, const int64_t *offset
   if (real_order(opts, n_max) > kFusedNMax || opts->prec != EXPM_PREC_FP64) return EXPM_E_UNSUPPORTED;
   return run_fused(A_dev, E_dev, offsets_dev, n_dev, batch, 0, n_max, opts, u, m_dev, s_dev,
                    status_dev, ws_dev, ws_bytes, stream, 0);
+}
+
+expm_status_t expm_batched_stage(const void *A_dev, void *E_dev, const int64_t *offsets_dev,
+                                 const int32_t *n_dev, int64_t batch, int64_t n_max,
+                                 const expm_opts_t *opts, int32_t *m_dev, int32_t *s_dev,
+                                 int32_t *status_dev, void *ws_dev, size_t ws_bytes, void *stream,
+                                 int32_t stage) {
+  double u;
+  expm_status_t st = check_opts(opts, &u);
+  if (st != EXPM_OK) return st;
+  if (!A_dev || !E_dev || !offsets_dev || !n_dev || !m_dev || !s_dev || batch < 1 || n_max < 1 ||
+      A_dev == E_dev || stage < 0 || stage > 2)
+    return EXPM_E_INVALID_ARG;
+  if (real_order(opts, n_max) > kFusedNMax || opts->prec != EXPM_PREC_FP64) return EXPM_E_UNSUPPORTED;
+  return run_fused(A_dev, E_dev, offsets_dev, n_dev, batch, 0, n_max, opts, u, m_dev, s_dev,
+                   status_dev, ws_dev, ws_bytes, stream, 0, stage);
 }
 
 expm_status_t expm_batched_uniform(const void *A_dev, void *E_dev, int64_t n, int64_t batch,

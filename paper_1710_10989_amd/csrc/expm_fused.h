@@ -18,7 +18,7 @@ struct FusedArgs {
   const int32_t *order;   // work-queue order (nullptr: identity)
   unsigned long long *queue;  // [counter 8-wave, counter 4-wave, split]; nullptr: static
   int32_t *m_out, *s_out, *status;
-  double *slots;          // gridDim.x slots of slot_doubles doubles
+  double *slots;          // gridDim.x slots of slot_doubles doubles (per kernel variant)
   size_t slot_doubles;
   int64_t batch;
   int64_t split;          // used when queue == nullptr

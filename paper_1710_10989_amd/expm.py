@@ -118,20 +118,26 @@ class Batch:
         return [host[o:o + n * n].reshape(n, n) for o, n in zip(offs, ns)]
 
 
-def batched(batch, u=None, prec="fp64", selector="plain", workspace=None, out=None):
-    """e^A for every matrix of a Batch.  Returns (E_packed, m, s, status) device tensors."""
+def batched(batch, u=None, prec="fp64", selector="plain", workspace=None, out=None, stage=None, outs=None):
+    """e^A for every matrix of a Batch.  Returns (E_packed, m, s, status) device tensors.
+    stage: None (all phases) or 0 / 1 / 2 (expm_batched_stage); outs: reuse (E, m, s, status)."""
     nb = batch.ns.numel()
     o = _opts(batch.packed.dtype, prec, selector, u)
     ws = workspace if workspace is not None else _workspace(
         N.lib().expm_workspace_bytes(batch.n_max, nb, ctypes.byref(o)), batch.packed.device)
-    E = out if out is not None else torch.empty_like(batch.packed)
-    m = torch.empty(nb, dtype=torch.int32, device=batch.packed.device)
-    s = torch.empty_like(m)
-    status = torch.empty_like(m)
-    st = N.lib().expm_batched(_ptr(batch.packed), _ptr(E), _ptr(batch.offsets), _ptr(batch.ns), nb,
-                              batch.n_max, ctypes.byref(o), _ptr(m), _ptr(s), _ptr(status), _ptr(ws),
-                              ws.numel(), _stream())
-    N.check(st, "expm_batched")
+    if outs is not None:
+        E, m, s, status = outs
+    else:
+        E = out if out is not None else torch.empty_like(batch.packed)
+        m = torch.empty(nb, dtype=torch.int32, device=batch.packed.device)
+        s = torch.empty_like(m)
+        status = torch.empty_like(m)
+    args = (_ptr(batch.packed), _ptr(E), _ptr(batch.offsets), _ptr(batch.ns), nb, batch.n_max, ctypes.byref(o),
+            _ptr(m), _ptr(s), _ptr(status), _ptr(ws), ws.numel(), _stream())
+    if stage is None:
+        N.check(N.lib().expm_batched(*args), "expm_batched")
+    else:
+        N.check(N.lib().expm_batched_stage(*args, int(stage)), "expm_batched_stage")
     return E, m, s, status
 
 

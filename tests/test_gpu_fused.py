@@ -225,3 +225,32 @@ def test_batched_deterministic_and_graph_replay(P):
         torch.cuda.synchronize()
         assert torch.equal(out, E1), rep
         _ = (B.packed * 2).sum().item()  # eager work between replays
+
+
+def test_staged_calls_match_and_may_overlap(P):
+    mats, _ = _batch(500, 3)
+    from paper_1710_10989_amd.expm import Batch
+    B = Batch.from_host(mats)
+    say("case staged")
+    E0, m0, s0, _ = P.batched(B)
+    ws = torch.empty(P.workspace_bytes(B.n_max, len(mats)), dtype=torch.uint8, device="cuda")
+    nb = len(mats)
+    outs = (torch.empty_like(B.packed), torch.empty(nb, dtype=torch.int32, device="cuda"),
+            torch.empty(nb, dtype=torch.int32, device="cuda"), torch.empty(nb, dtype=torch.int32, device="cuda"))
+    for stg in (0, 1, 2):
+        P.batched(B, workspace=ws, outs=outs, stage=stg)
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], E0) and torch.equal(outs[1], m0) and torch.equal(outs[2], s0)
+    # stages 1 and 2 on two streams after stage 0
+    outs[0].zero_()
+    P.batched(B, workspace=ws, outs=outs, stage=0)
+    done0 = torch.cuda.Event()
+    done0.record()
+    side = torch.cuda.Stream()
+    side.wait_event(done0)
+    with torch.cuda.stream(side):
+        P.batched(B, workspace=ws, outs=outs, stage=2)
+    P.batched(B, workspace=ws, outs=outs, stage=1)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], E0)
