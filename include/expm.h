@@ -56,12 +56,14 @@ typedef enum {
  * which lies between ||A||_1 and sqrt(2) ||A||_1. */
 typedef enum { EXPM_F64 = 0, EXPM_C128 = 1 } expm_dtype_t;
 
-/* Arithmetic of the polynomial products (the powers and the product stage of T_m).  The
- * norms, the theta comparison, the linear combinations and the s squarings are FP64 in
- * every form.  EXPM_PREC_FP32: FP32 operands and FP32 accumulation.  EXPM_PREC_BF16X3: each
- * FP64 operand is split into three bfloat16 terms (hi + mid + lo), six of the nine cross
- * products are accumulated in FP32 (lo*lo, mid*lo and lo*mid are dropped).  Reduced forms
- * select (m, s) with the u = 2^-24 thresholds unless opts.u says otherwise. */
+/* Arithmetic of the polynomial products.  In the reduced forms the powers A^2, A^3 (A^6) and
+ * the first product of the product stage use it; the last product of the stage (which carries
+ * the O(1) identity part of T_m), the s squarings (error growth 2^s), the norms, the theta
+ * comparison and the linear combinations stay FP64.  EXPM_PREC_FP32: operands rounded to
+ * FP32, FP32 accumulation.  EXPM_PREC_BF16X3: each FP64 operand is split into three bfloat16
+ * terms (hi + mid + lo), six of the nine cross products (lo*lo, mid*lo, lo*mid dropped) are
+ * accumulated in FP32.  Default u: 2^-24 for FP32, 2^-53 for FP64 and BF16X3.  Reduced forms
+ * always run the tiled path (any order). */
 typedef enum { EXPM_PREC_FP64 = 0, EXPM_PREC_FP32 = 1, EXPM_PREC_BF16X3 = 2 } expm_prec_t;
 
 /* How (m, s) is chosen.

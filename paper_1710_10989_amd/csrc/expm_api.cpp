@@ -23,7 +23,9 @@ size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 int64_t pad16(int64_t n) { return (n + 15) & ~int64_t(15); }
 int np_max_t(int64_t n) { return (int)(pad16(n) >> 4); }
 
-double default_u(int prec) { return prec == EXPM_PREC_FP64 ? 0x1p-53 : 0x1p-24; }
+// FP64 and BF16X3 target the double row of the thresholds (truncation below 1e-15, so the
+// split's FP32 accumulation dominates the error); FP32 uses the single row.
+double default_u(int prec) { return prec == EXPM_PREC_FP32 ? 0x1p-24 : 0x1p-53; }
 
 expm_status_t check_opts(const expm_opts_t *o, double *u) {
   if (!o) return EXPM_E_INVALID_ARG;
@@ -134,9 +136,8 @@ static int64_t real_order(const expm_opts_t *o, int64_t n) { return o->dtype == 
 size_t expm_workspace_bytes(int64_t n_max, int64_t batch, const expm_opts_t *opts) {
   double u;
   if (n_max < 1 || batch < 1 || check_opts(opts, &u) != EXPM_OK) return 0;
-  if (opts->prec != EXPM_PREC_FP64) return 0;
   const int64_t nr = real_order(opts, n_max);
-  if (nr <= kFusedNMax) return fused_layout(nr, batch).total;
+  if (nr <= kFusedNMax && opts->prec == EXPM_PREC_FP64) return fused_layout(nr, batch).total;
   return large_layout(nr, batch).total;
 }
 
@@ -209,6 +210,7 @@ static expm_status_t run_large_call(const void *A, void *E, int64_t n, int64_t b
   c.cplx = opts->dtype == EXPM_C128;
   c.batch = batch;
   c.sel = opts->sel == EXPM_SEL_LEARNED ? EXPM_SEL_ALPHA : opts->sel;
+  c.prec = opts->prec;  // expm_prec_t values match PREC_F64 / PREC_F32 / PREC_BF16X3
   c.select_only = select_only;
   c.m_out = m_dev;
   c.s_out = s_dev;
@@ -224,8 +226,7 @@ expm_status_t expm_select(const void *A_dev, int64_t n, const expm_opts_t *opts,
   expm_status_t st = check_opts(opts, &u);
   if (st != EXPM_OK) return st;
   if (!A_dev || !m_dev || !s_dev || n < 1) return EXPM_E_INVALID_ARG;
-  if (opts->prec != EXPM_PREC_FP64) return EXPM_E_UNSUPPORTED;
-  if (real_order(opts, n) > kFusedNMax)
+  if (real_order(opts, n) > kFusedNMax || opts->prec != EXPM_PREC_FP64)
     return run_large_call(A_dev, nullptr, n, 1, opts, u, m_dev, s_dev, nullptr, ws_dev, ws_bytes, stream, 1);
   return run_fused(A_dev, nullptr, nullptr, nullptr, 1, n, n, opts, u, m_dev, s_dev, nullptr,
                    ws_dev, ws_bytes, stream, 1);
@@ -238,8 +239,7 @@ expm_status_t expm_taylor(const void *A_dev, void *E_dev, int64_t n, const expm_
   expm_status_t st = check_opts(opts, &u);
   if (st != EXPM_OK) return st;
   if (!A_dev || !E_dev || !m_dev || !s_dev || n < 1 || A_dev == E_dev) return EXPM_E_INVALID_ARG;
-  if (opts->prec != EXPM_PREC_FP64) return EXPM_E_UNSUPPORTED;
-  if (real_order(opts, n) > kFusedNMax)
+  if (real_order(opts, n) > kFusedNMax || opts->prec != EXPM_PREC_FP64)
     return run_large_call(A_dev, E_dev, n, 1, opts, u, m_dev, s_dev, status_dev, ws_dev, ws_bytes, stream, 0);
   return run_fused(A_dev, E_dev, nullptr, nullptr, 1, n, n, opts, u, m_dev, s_dev, status_dev,
                    ws_dev, ws_bytes, stream, 0);
@@ -283,8 +283,7 @@ expm_status_t expm_batched_uniform(const void *A_dev, void *E_dev, int64_t n, in
   expm_status_t st = check_opts(opts, &u);
   if (st != EXPM_OK) return st;
   if (!A_dev || !E_dev || !m_dev || !s_dev || batch < 1 || n < 1 || A_dev == E_dev) return EXPM_E_INVALID_ARG;
-  if (opts->prec != EXPM_PREC_FP64) return EXPM_E_UNSUPPORTED;
-  if (real_order(opts, n) > kFusedNMax)
+  if (real_order(opts, n) > kFusedNMax || opts->prec != EXPM_PREC_FP64)
     return run_large_call(A_dev, E_dev, n, batch, opts, u, m_dev, s_dev, status_dev, ws_dev, ws_bytes, stream, 0);
   return run_fused(A_dev, E_dev, nullptr, nullptr, batch, n, n, opts, u, m_dev, s_dev, status_dev,
                    ws_dev, ws_bytes, stream, 0);

@@ -28,6 +28,7 @@ struct LargeCall {
   int cplx;           // interleaved complex input / output, run on the real form
   int64_t batch;
   int sel;            // EXPM_SEL_PLAIN or EXPM_SEL_ALPHA
+  int prec;           // PREC_F64 / PREC_F32 / PREC_BF16X3 for the reduced steps
   int select_only;
   int32_t *m_out, *s_out, *status;  // device, one per matrix
   void *ws;

@@ -10,6 +10,11 @@
 //   read (m, s) back once; group the matrices by degree and squaring count;
 //   powers, product stage (the same epilogue kinds as the fused path), s squarings.
 // Zero padding is exact for the same reason as in the fused path (block-diagonal powers).
+//
+// Reduced-precision forms: the powers and the first GEMM of the product stage run in FP32 or
+// BF16x3 (FP32 accumulation); the last product of the stage, which carries the O(1) identity
+// part of T_m (for T_18: (B_3 + A_9) A_9 with constant term about (-11.06)(-0.090) = 1), and
+// the s squarings, whose error grows 2^s-fold, stay FP64, as do the norms and the selection.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <string.h>
@@ -188,7 +193,8 @@ __global__ void lg_select_kernel(LargeArgs a, int count, int stride, const unsig
   make_coefs(k, m, s, coef + (size_t)mi * 64);
 }
 
-// One 128 x 128 output tile of a GEMM step for matrix list[blockIdx.y].
+// One 128 x 128 output tile of a GEMM step for matrix list[blockIdx.y], products in PREC.
+template <int PREC>
 __global__ __launch_bounds__(512, 1) void lg_gemm_kernel(LargeArgs a) {
   const int mi = a.list[blockIdx.y];
   const int64_t gb = a.g0 + mi;
@@ -219,15 +225,16 @@ __global__ __launch_bounds__(512, 1) void lg_gemm_kernel(LargeArgs a) {
   const int wr = wave / LS::WC, wc = wave % LS::WC;
   const int wr_row = wr * LS::BR * 16, wc_col = wc * LS::BC * 16;
   const int m0 = tm * kLargeTile, n0 = tn * kLargeTile;
-  dbl4 acc[LS::TPW];
-  tile_gemm<LS>(gptr(g_ep.P), a.np, gptr(g_ep.Q), a.np, a.np, a.np, a.np, m0, n0, L, true, wr_row, wc_col, acc);
+  typename AccOf<PREC>::T acc[LS::TPW];
+  tile_gemm<LS, PREC>(gptr(g_ep.P), a.np, gptr(g_ep.Q), a.np, a.np, a.np, a.np, m0, n0, L, true, wr_row, wc_col,
+                      acc);
   if (a.kind == EK_STORE) {
-    store_acc<LS>(acc, m0 + wr_row, n0 + wc_col);
+    store_acc<LS, PREC>(acc, m0 + wr_row, n0 + wc_col);
     return;
   }
   __syncthreads();
   double *cbuf = lds_pool<8>();
-  stage_acc<LS, LDC_L>(cbuf, acc, wr_row, wc_col);
+  stage_acc<LS, LDC_L, PREC>(cbuf, acc, wr_row, wc_col);
   __syncthreads();
   run_epilogue<8>(m0, n0, kLargeTile, kLargeTile, LDC_L);
 }
@@ -315,15 +322,22 @@ struct Launcher {
     return d;
   }
 
+  int prec = PREC_F64;  // arithmetic of the polynomial products (set per call by run_large)
+
   void gemm(const std::vector<int32_t> &idx, int slot, int kind, int p, int q, int dst,
-            int in0 = SEL_NONE, int in1 = SEL_NONE, std::vector<int> o = {}, int round = 0) {
+            int in0 = SEL_NONE, int in1 = SEL_NONE, std::vector<int> o = {}, int round = 0,
+            bool reduced = false) {
     if (idx.empty() || !ok) return;
     LargeArgs a = base;
     a.list = upload(idx, slot);
     a.kind = kind; a.p = p; a.q = q; a.dst = dst; a.in0 = in0; a.in1 = in1; a.round = round;
     for (int j = 0; j < 5; ++j) a.o[j] = j < (int)o.size() ? o[j] : SEL_NONE;
     const int tiles = (int)((L.np / kLargeTile) * (L.np / kLargeTile));
-    hipLaunchKernelGGL(lg_gemm_kernel, dim3(tiles, (unsigned)idx.size()), dim3(512), 0, st, a);
+    const int pr = reduced ? prec : PREC_F64;
+    if (pr == PREC_F32) hipLaunchKernelGGL(lg_gemm_kernel<PREC_F32>, dim3(tiles, (unsigned)idx.size()), dim3(512), 0, st, a);
+    else if (pr == PREC_BF16X3)
+      hipLaunchKernelGGL(lg_gemm_kernel<PREC_BF16X3>, dim3(tiles, (unsigned)idx.size()), dim3(512), 0, st, a);
+    else hipLaunchKernelGGL(lg_gemm_kernel<PREC_F64>, dim3(tiles, (unsigned)idx.size()), dim3(512), 0, st, a);
     if (hipGetLastError() != hipSuccess) ok = false;
   }
 
@@ -369,6 +383,7 @@ expm_status_t run_large(const LargeCall &c, hipStream_t st) {
     const int cnt = (int)std::min<int64_t>(L.group, c.batch - g0);
     a.g0 = g0;
     Launcher run{c, L, a, st, lists};
+    run.prec = c.prec;
     std::vector<int32_t> all(cnt);
     for (int i = 0; i < cnt; ++i) all[i] = i;
     // norms (3 per matrix) and non-finite flags start at zero
@@ -392,8 +407,8 @@ expm_status_t run_large(const LargeCall &c, hipStream_t st) {
         if (mh[i] >= 2) l2.push_back(i);
         if (mh[i] >= 12) l3.push_back(i);
       }
-      run.gemm(l2, 0, EK_STORE, 0, 0, 1);
-      run.gemm(l3, 1, EK_STORE, 1, 0, 2);
+      run.gemm(l2, 0, EK_STORE, 0, 0, 1, SEL_NONE, SEL_NONE, {}, 0, true);
+      run.gemm(l3, 1, EK_STORE, 1, 0, 2, SEL_NONE, SEL_NONE, {}, 0, true);
       LargeArgs b2 = a;
       if (!l2.empty()) {
         b2.list = run.upload(l2, 2);
@@ -437,8 +452,8 @@ expm_status_t run_large(const LargeCall &c, hipStream_t st) {
       smax = std::max(smax, (int)sh[i]);
     }
     if (c.sel != EXPM_SEL_ALPHA) {
-      run.gemm(l2, 0, EK_STORE, 0, 0, 1);
-      run.gemm(l3, 1, EK_STORE, 1, 0, 2);
+      run.gemm(l2, 0, EK_STORE, 0, 0, 1, SEL_NONE, SEL_NONE, {}, 0, true);
+      run.gemm(l3, 1, EK_STORE, 1, 0, 2, SEL_NONE, SEL_NONE, {}, 0, true);
     }
     run.elem(lnan, 1, LCNAN, SEL_NONE);
     // ---- product stage per degree ----
@@ -447,13 +462,13 @@ expm_status_t run_large(const LargeCall &c, hipStream_t st) {
     run.elem(lm[4], 4, LC4W, 2);
     run.gemm(lm[4], 4, EK_M4, 1, 2, SEL_TDST);
     run.elem(lm[8], 5, LC8W, 2);
-    run.gemm(lm[8], 5, EK_M8A, 1, 2, SEL_NONE, SEL_NONE, SEL_NONE, {3, 4});
+    run.gemm(lm[8], 5, EK_M8A, 1, 2, SEL_NONE, SEL_NONE, SEL_NONE, {3, 4}, 0, true);
     run.gemm(lm[8], 5, EK_M8B, 3, 4, SEL_TDST);
     run.elem(lm[12], 6, LC12, SEL_NONE);
-    run.gemm(lm[12], 6, EK_SPLIT2, 6, 6, SEL_NONE, 5, 4, {0, 1});
+    run.gemm(lm[12], 6, EK_SPLIT2, 6, 6, SEL_NONE, 5, 4, {0, 1}, 0, true);
     run.gemm(lm[12], 6, EK_ADD1, 1, 0, SEL_TDST, 3);
-    run.gemm(lm[18], 7, EK_M18A, 2, 2, SEL_NONE, SEL_NONE, SEL_NONE, {3, 4, 5, 6, 7});
-    run.gemm(lm[18], 7, EK_SPLIT2, 3, 7, SEL_NONE, 6, 5, {0, 1});
+    run.gemm(lm[18], 7, EK_M18A, 2, 2, SEL_NONE, SEL_NONE, SEL_NONE, {3, 4, 5, 6, 7}, 0, true);
+    run.gemm(lm[18], 7, EK_SPLIT2, 3, 7, SEL_NONE, 6, 5, {0, 1}, 0, true);
     run.gemm(lm[18], 7, EK_ADD1, 1, 0, SEL_TDST, 4);
     // ---- squarings: round r covers the matrices with s >= r ----
     for (int r = 1; r <= smax; ++r) {

@@ -189,8 +189,8 @@ __device__ inline void run_epilogue(int row0, int col0, int rows, int cols, int 
 
 // Plain product: each lane stores its accumulators to the g_ep destination (lanes 0..15 of
 // a register cover 16 consecutive columns of one row).  (row0, col0): the wave's block.
-template <class S>
-__device__ inline void store_acc(const dbl4 (&acc)[S::TPW], int row0, int col0) {
+template <class S, int PREC = PREC_F64>
+__device__ inline void store_acc(const typename AccOf<PREC>::T (&acc)[S::TPW], int row0, int col0) {
   gdouble *dst = gptr(g_ep.dst);
   int ld = g_ep.dst_ld;
   const int nv = g_ep.dst_nvalid, cx = g_ep.cplx;
@@ -203,13 +203,16 @@ __device__ inline void store_acc(const dbl4 (&acc)[S::TPW], int row0, int col0) 
     for (int j = 0; j < S::BC; ++j) {
       const int col = col0 + j * 16 + lr;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) put_dst(dst, ld, nv, cx, row0 + i * 16 + 4 * r + lk, col, acc[i * S::BC + j][r]);
+      for (int r = 0; r < 4; ++r) {
+        const int row = row0 + i * 16 + (PREC == PREC_F64 ? 4 * r + lk : 4 * lk + r);
+        put_dst(dst, ld, nv, cx, row, col, (double)acc[i * S::BC + j][r]);
+      }
     }
 }
 
 // Stages the wave's accumulators into the chunk copy (ld LDC) at chunk-relative (r0, c0).
-template <class S, int LDC>
-__device__ inline void stage_acc(double *cbuf, const dbl4 (&acc)[S::TPW], int r0, int c0) {
+template <class S, int LDC, int PREC = PREC_F64>
+__device__ inline void stage_acc(double *cbuf, const typename AccOf<PREC>::T (&acc)[S::TPW], int r0, int c0) {
   const int lane = threadIdx.x & 63;
   int lrow = lane >> 4;
   asm volatile("" : "+v"(lrow));
@@ -220,7 +223,8 @@ __device__ inline void stage_acc(double *cbuf, const dbl4 (&acc)[S::TPW], int r0
     for (int j = 0; j < S::BC; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        cbuf[(r0 + i * 16 + 4 * r + lrow) * LDC + c0 + j * 16 + lr] = acc[i * S::BC + j][r];
+        cbuf[(r0 + i * 16 + (PREC == PREC_F64 ? 4 * r + lrow : 4 * lrow + r)) * LDC + c0 + j * 16 + lr] =
+            (double)acc[i * S::BC + j][r];
 }
 
 template <int NW, int T>

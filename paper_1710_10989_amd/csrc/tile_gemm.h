@@ -17,14 +17,43 @@
 //            halves (slot c ^ 8), so the four 16-lane groups of a B fragment use both bank
 //            halves.
 //
-// MFMA operand layout (gfx950, 16x16x4 f64): lane l supplies A[l % 16][l / 16] and
-// B[l / 16][l % 16]; accumulator register r of lane l holds D[4 r + l / 16][l % 16].
+// MFMA operand layouts (gfx950): 16x16x4 f64 and f32: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; 16x16x16 bf16: lane l supplies A[l % 16][4 (l / 16) + i] and
+// B[4 (l / 16) + i][l % 16], i = 0..3.  Accumulator register r of lane l holds
+// D[4 r + l / 16][l % 16] for f64, D[4 (l / 16) + r][l % 16] for the f32-accumulating forms.
 #pragma once
 #include <hip/hip_runtime.h>
 
 namespace expm {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef short shr4 __attribute__((ext_vector_type(4)));
+
+// Arithmetic of the products: PREC_F64 (v_mfma_f64_16x16x4), PREC_F32 (operands rounded to
+// FP32, v_mfma_f32_16x16x4, FP32 accumulation), PREC_BF16X3 (each FP64 operand split into
+// three bfloat16 terms hi + mid + lo; the six products hi*hi, hi*mid, mid*hi, hi*lo, lo*hi,
+// mid*mid by v_mfma_f32_16x16x16_bf16, FP32 accumulation).  Operands always arrive as FP64.
+enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X3 = 2 };
+template <int PREC> struct AccOf { typedef dbl4 T; };
+template <> struct AccOf<PREC_F32> { typedef flt4 T; };
+template <> struct AccOf<PREC_BF16X3> { typedef flt4 T; };
+
+// Round-to-nearest-even bfloat16 of a float (the 16 high bits).
+__device__ inline short bf16_rne(float f) {
+  const unsigned u = __float_as_uint(f);
+  return (short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ inline double bf16_to_double(short h) { return (double)__uint_as_float(((unsigned)(unsigned short)h) << 16); }
+
+// x = hi + mid + lo + O(2^-24 |x|), each term a bfloat16; the remainders are exact in FP64.
+__device__ inline void split3(double x, short &hi, short &mid, short &lo) {
+  hi = bf16_rne((float)x);
+  const double r1 = x - bf16_to_double(hi);
+  mid = bf16_rne((float)r1);
+  const double r2 = r1 - bf16_to_double(mid);
+  lo = bf16_rne((float)r2);
+}
 typedef __attribute__((address_space(1))) double gdouble;
 typedef __attribute__((address_space(1))) const double cgdouble;
 typedef __attribute__((address_space(1))) const void *gvoidp;
@@ -109,37 +138,87 @@ __device__ inline void issue_panel(cgdouble *P, int ldp, cgdouble *Q, int ldq, i
   }
 }
 
-// Multiplies the panel held in (lp, lq) into acc: kend = 16, or fewer for a K tail.
-template <class S>
+// Multiplies the panel held in (lp, lq) into acc: kend = 16, or fewer for a K tail (a tail
+// only occurs with PREC_F64 on orders that are odd multiples of 16).
+template <class S, int PREC>
 __device__ inline void mma_panel(const double *lp, const double *lq, int wr_row, int wc_col, int kend,
-                                 dbl4 (&acc)[S::TPW]) {
+                                 typename AccOf<PREC>::T (&acc)[S::TPW]) {
   int lane = threadIdx.x & 63;
   asm volatile("" : "+v"(lane));
   const int lr = lane & 15, lk = lane >> 4;
-  // Blocks of 9+ tiles keep only two k steps of fragments in flight (register budget).
-  constexpr int KU = S::TPW >= 9 ? 2 : 4;
-#pragma unroll KU
-  for (int kk = 0; kk < kKP; kk += 4) {
-    if (kk < kend) {
-      const int k = kk + lk;
-      double a[S::BR], b[S::BC];
+  if constexpr (PREC == PREC_BF16X3) {
+    // one K = 16 step: lane supplies A[row][4 lk + i], B[4 lk + i][col], i = 0..3
+    (void)kend;
+    shr4 ah[S::BR], am[S::BR], al[S::BR];
+#pragma unroll
+    for (int i = 0; i < S::BR; ++i) {
+      const int r = wr_row + i * 16 + lr;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {  // chunks 2 lk and 2 lk + 1 hold k = 4 lk .. 4 lk + 3
+        const int slot = (2 * lk + h) ^ ((r >> 1) & 7);
+        const double x0 = lp[r * kKP + 2 * slot], x1 = lp[r * kKP + 2 * slot + 1];
+        short a0, b0, c0, a1, b1, c1;
+        split3(x0, a0, b0, c0);
+        split3(x1, a1, b1, c1);
+        ah[i][2 * h] = a0; am[i][2 * h] = b0; al[i][2 * h] = c0;
+        ah[i][2 * h + 1] = a1; am[i][2 * h + 1] = b1; al[i][2 * h + 1] = c1;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < S::BC; ++j) {
+      const int col = wc_col + j * 16 + lr;
+      shr4 bh, bm, bl;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int k = 4 * lk + t;
+        const int slot = S::Q_SWZ ? ((col >> 1) ^ ((k & 1) << 3)) : (col >> 1);
+        short x, y, z;
+        split3(lq[k * S::BN + 2 * slot + (col & 1)], x, y, z);
+        bh[t] = x; bm[t] = y; bl[t] = z;
+      }
 #pragma unroll
       for (int i = 0; i < S::BR; ++i) {
-        const int r = wr_row + i * 16 + lr;  // row within the chunk
-        const int slot = (k >> 1) ^ ((r >> 1) & 7);
-        a[i] = lp[r * kKP + 2 * slot + (k & 1)];
+        flt4 c = acc[i * S::BC + j];
+        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(am[i], bm, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bl, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bh, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bm, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(am[i], bh, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bh, c, 0, 0, 0);
+        acc[i * S::BC + j] = c;
       }
+    }
+  } else {
+    // Blocks of 9+ tiles keep only two k steps of fragments in flight (register budget).
+    constexpr int KU = S::TPW >= 9 ? 2 : 4;
+#pragma unroll KU
+    for (int kk = 0; kk < kKP; kk += 4) {
+      if (kk < kend) {
+        const int k = kk + lk;
+        double a[S::BR], b[S::BC];
 #pragma unroll
-      for (int j = 0; j < S::BC; ++j) {
-        const int col = wc_col + j * 16 + lr;  // column within the chunk
-        const int slot = S::Q_SWZ ? ((col >> 1) ^ ((k & 1) << 3)) : (col >> 1);
-        b[j] = lq[k * S::BN + 2 * slot + (col & 1)];
+        for (int i = 0; i < S::BR; ++i) {
+          const int r = wr_row + i * 16 + lr;  // row within the chunk
+          const int slot = (k >> 1) ^ ((r >> 1) & 7);
+          a[i] = lp[r * kKP + 2 * slot + (k & 1)];
+        }
+#pragma unroll
+        for (int j = 0; j < S::BC; ++j) {
+          const int col = wc_col + j * 16 + lr;  // column within the chunk
+          const int slot = S::Q_SWZ ? ((col >> 1) ^ ((k & 1) << 3)) : (col >> 1);
+          b[j] = lq[k * S::BN + 2 * slot + (col & 1)];
+        }
+#pragma unroll
+        for (int i = 0; i < S::BR; ++i)
+#pragma unroll
+          for (int j = 0; j < S::BC; ++j) {
+            if constexpr (PREC == PREC_F64)
+              acc[i * S::BC + j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i * S::BC + j], 0, 0, 0);
+            else
+              acc[i * S::BC + j] =
+                  __builtin_amdgcn_mfma_f32_16x16x4f32((float)a[i], (float)b[j], acc[i * S::BC + j], 0, 0, 0);
+          }
       }
-#pragma unroll
-      for (int i = 0; i < S::BR; ++i)
-#pragma unroll
-        for (int j = 0; j < S::BC; ++j)
-          acc[i * S::BC + j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i * S::BC + j], 0, 0, 0);
     }
   }
 }
@@ -147,12 +226,13 @@ __device__ inline void mma_panel(const double *lp, const double *lq, int wr_row,
 // Full K loop for one chunk.  `active`: this wave owns a block inside the matrix.  The caller
 // must have passed a workgroup barrier since the stages were last read.  On return every
 // panel load has completed, but other waves may still be reading the last stage.
-template <class S>
+template <class S, int PREC = PREC_F64>
 __device__ inline void tile_gemm(cgdouble *P, int ldp, cgdouble *Q, int ldq, int M, int N, int K,
                                  int m0, int n0, TileLds<S> &L, bool active, int wr_row, int wc_col,
-                                 dbl4 (&acc)[S::TPW]) {
+                                 typename AccOf<PREC>::T (&acc)[S::TPW]) {
+  typedef typename AccOf<PREC>::T AT;
 #pragma unroll
-  for (int i = 0; i < S::TPW; ++i) acc[i] = dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int i = 0; i < S::TPW; ++i) acc[i] = AT{0, 0, 0, 0};
   const int npan = (K + kKP - 1) / kKP;
   issue_panel<S>(P, ldp, Q, ldq, M, N, K, m0, n0, 0, L.p[0], L.q[0]);
   if (npan > 1) issue_panel<S>(P, ldp, Q, ldq, M, N, K, m0, n0, kKP, L.p[1], L.q[1]);
@@ -162,7 +242,7 @@ __device__ inline void tile_gemm(cgdouble *P, int ldp, cgdouble *Q, int ldq, int
     lds_barrier();
     if (kp + 2 < npan) issue_panel<S>(P, ldp, Q, ldq, M, N, K, m0, n0, (kp + 2) * kKP, np_p, np_q);
     const int kend = (K - kp * kKP) < kKP ? (K - kp * kKP) : kKP;
-    if (active) mma_panel<S>(lp, lq, wr_row, wc_col, kend, acc);
+    if (active) mma_panel<S, PREC>(lp, lq, wr_row, wc_col, kend, acc);
   };
   for (int kp = 0; kp < npan; kp += 3) {
     step(kp, L.p[0], L.q[0], L.p[2], L.q[2]);
