@@ -1,17 +1,24 @@
 """Throughput of the matrix-exponential hot path on one MI355X.
 
-Workload: 4096 FP64 matrices of uneven order n in {16, 32, 48, 64, 96, 128}, ||A||_1
-log-uniform in [1e-3, 1e2], structure mix 40 % dense Gaussian / 20 % skew-symmetric / 20 %
-strictly upper triangular / 20 % diagonal + rank 4 (seeded, synthetic).  One step = one
+Default workload (batched): 4096 FP64 matrices of uneven order n in {16, 32, 48, 64, 96, 128},
+||A||_1 log-uniform in [1e-3, 1e2], structure mix 40 % dense Gaussian / 20 % skew-symmetric /
+20 % strictly upper triangular / 20 % diagonal + rank 4 (seeded, synthetic).  One step = one
 expm_batched call on the whole batch (device work-queue ordering + the persistent fused
-kernel: norm, (m, s) selection, product-reduced Taylor polynomial, squarings), inputs already
-resident in HBM.
+kernels: norm, (m, s) selection, product-reduced Taylor polynomial, squarings), inputs
+already resident in HBM.
 
-Prints one JSON line: matrices/s, the roofline of the dominant kernel (the 8-wave fused
-kernel that handles the orders 80..128: executed FP64 flops of those matrices = sum of
-(products(m) + s) * 2 n^3, divided by its duration measured with HIP events around that
-phase on the launch stream, against the 78.6 TFLOP/s FP64 matrix peak) and the CPU oracle
-(FP64 direct Taylor) timed on a bounded sample of the same workload on the host cores.
+Other workloads (one JSON line each, selected with --workload):
+  single     one 64 x 64 FP64 matrix, ||A||_1 = 2 (latency-bound; repeated expm_taylor calls)
+  precision  256 matrices n = 1024 + 16 matrices n = 4096, N(0,1)/sqrt(n) entries scaled to
+             ||A||_1 uniform in [0.5, 50]; --prec fp64 / fp32 / bf16x3
+  complex    512 complex matrices -i H dt (H Hermitian, spectral radius 1, n = 256,
+             dt log-uniform in [1e-2, 1e2]) + one dense FP64 n = 8192 with ||A||_1 = 20
+
+The JSON line carries matrices/s, the roofline of the dominant kernel (executed flops =
+sum over matrices of (products(m) + s) * 2 n^3 for the real order n the kernels run on,
+divided by the kernel's duration measured with HIP events on the launch stream, against the
+MI355X dense FP64 MFMA peak, 78.6 TFLOP/s) and the CPU oracle (direct Taylor) timed on a
+bounded sample of the same workload on the host cores.
 """
 import argparse
 import json
@@ -25,33 +32,43 @@ PRODUCTS = {1: 0, 2: 1, 4: 2, 8: 3, 12: 4, 18: 5}
 PEAK_FP64 = 78.6e12
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--selector", default="plain", choices=["plain", "alpha"])
-    ap.add_argument("--count", type=int, default=4096)
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--no-cpu", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU: the method runs on a single MI355X (multi-GPU sharding "
-              "is a design note, not built); run with --gpus 1", file=sys.stderr)
-        sys.exit(2)
+def executed_flops(ms, ss, ns):
+    return float(sum((PRODUCTS[int(m)] + int(s)) * 2.0 * float(n) ** 3 for m, s, n in zip(ms, ss, ns) if m > 0))
 
-    import torch
-    import paper_1710_10989_amd as P
-    from paper_1710_10989_amd import workloads as W
+
+def cpu_oracle(mats, seconds, label):
+    """Whole passes of the FP64 direct-Taylor oracle over `mats` until about `seconds`."""
+    import oracle
+    threads = min(os.cpu_count() or 1, 16)
+    oracle.expm_taylor_batch(mats[:1], prec="d")
+    done, c0 = 0, time.perf_counter()
+    while True:
+        oracle.expm_taylor_batch(mats, prec="d")
+        done += 1
+        if time.perf_counter() - c0 >= seconds:
+            break
+    c1 = time.perf_counter()
+    return {"value": done * len(mats) / (c1 - c0), "unit": "matrices/s", "cores": threads, "kind": "oracle",
+            "sample": "%d pass(es) over %s, FP64 direct Taylor (own scaling ||X||_1 <= 1/2), OpenMP over "
+                      "matrices, %.1f s" % (done, label, c1 - c0)}
+
+
+def line(args, metric, value, ms_step, dtype, config, roofline, cpu):
+    return {"metric": metric, "value": value, "unit": "matrices/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config, "roofline": roofline,
+            "cpu_baseline": cpu}
+
+
+def run_batched(args, torch, P, W):
     from paper_1710_10989_amd.expm import Batch
-
     mats, kinds = W.mixed_batch(count=args.count)
     B = Batch.from_host(mats)
     ws = torch.empty(P.workspace_bytes(B.n_max, len(mats)), dtype=torch.uint8, device="cuda")
-    out = torch.empty_like(B.packed)
     nb = len(mats)
-    outs = (out, torch.empty(nb, dtype=torch.int32, device="cuda"), torch.empty(nb, dtype=torch.int32, device="cuda"),
-            torch.empty(nb, dtype=torch.int32, device="cuda"))
+    outs = (torch.empty_like(B.packed), torch.empty(nb, dtype=torch.int32, device="cuda"),
+            torch.empty(nb, dtype=torch.int32, device="cuda"), torch.empty(nb, dtype=torch.int32, device="cuda"))
+    stream = torch.cuda.current_stream()
 
     def step(ev=None):
         # one step = expm_batched in its three phases on the current stream; the events bracket
@@ -64,74 +81,176 @@ def main():
             ev[1].record(stream)
         P.batched(B, selector=args.selector, workspace=ws, outs=outs, stage=2)
 
-    stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     kev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0.record(stream)
     for i in range(args.steps):
         step(kev[i])
     t1.record(stream)
     torch.cuda.synchronize()
-    ms_total = t0.elapsed_time(t1)
-    ms_step = ms_total / args.steps
+    ms_step = t0.elapsed_time(t1) / args.steps
     ms_k8 = sum(a.elapsed_time(b) for a, b in kev) / args.steps
-    _, m, s, st = outs
-    m = m.cpu().numpy()
-    s = s.cpu().numpy()
-    st = st.cpu().numpy()
+    _, m, s, st = (x.cpu().numpy() for x in outs)
     assert np.all(st == 0), "non-ok status in the batch"
     ns = np.array([a.shape[0] for a in mats], dtype=np.float64)
-    fl = np.array([(PRODUCTS[int(mi)] + int(si)) * 2.0 * n ** 3 for mi, si, n in zip(m, s, ns)])
-    flops = float(fl.sum())
     big = ((ns + 15) // 16) >= 5  # real orders handled by the 8-wave kernel
-    flops_k8 = float(fl[big].sum())
+    flops = executed_flops(m, s, ns)
+    flops_k8 = executed_flops(m[big], s[big], ns[big])
     achieved = flops_k8 / (ms_k8 * 1e-3)
+    cpu = None if args.no_cpu else cpu_oracle(mats, args.cpu_seconds, "all %d matrices of the workload" % nb)
+    config = {"workload": "4096 FP64 matrices, n uniform in {16,32,48,64,96,128}, ||A||_1 log-uniform [1e-3,1e2], "
+                          "40/20/20/20 dense/skew/nilpotent/diag+rank4; one expm_batched call per step",
+              "selector": args.selector,
+              "mean_products_plus_squarings": float(np.mean([PRODUCTS[int(a)] + int(b) for a, b in zip(m, s)]))}
+    roof = {"bound": "mfma", "kernel": "expm_fused_kernel<8> (orders 80..128 of the batch)",
+            "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64,
+            "traffic": None, "kernel_ms": ms_k8, "step_tflops": flops / (ms_step * 1e-3) / 1e12}
+    return line(args, "expm matrices/s (rel err <= 1e-12, FP64)", nb / (ms_step * 1e-3), ms_step, "f64", config,
+                roof, cpu)
 
-    cpu = None
-    if not args.no_cpu:
-        import oracle
-        threads = min(os.cpu_count() or 1, 16)
-        os.environ.setdefault("OMP_NUM_THREADS", str(threads))
-        oracle.expm_taylor_batch(mats[:8], prec="d")  # load + warm
-        done, c0 = 0, time.perf_counter()
-        while True:  # whole passes over the batch until about --cpu-seconds of CPU work
-            oracle.expm_taylor_batch(mats, prec="d")
-            done += 1
-            if time.perf_counter() - c0 >= args.cpu_seconds:
-                break
-        c1 = time.perf_counter()
-        cpu = {"value": done * len(mats) / (c1 - c0), "unit": "matrices/s", "cores": threads, "kind": "oracle",
-               "sample": "%d pass(es) over all %d matrices of the workload, FP64 direct Taylor (own scaling "
-                         "||X||_1 <= 1/2), OpenMP over matrices, %.1f s" % (done, len(mats), c1 - c0)}
 
-    line = {
-        "metric": "expm matrices/s (rel err <= 1e-12, FP64)",
-        "value": len(mats) / (ms_step * 1e-3),
-        "unit": "matrices/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": "4096 FP64 matrices, n uniform in {16,32,48,64,96,128}, ||A||_1 log-uniform "
-                               "[1e-3,1e2], 40/20/20/20 dense/skew/nilpotent/diag+rank4; one expm_batched "
-                               "call per step", "selector": args.selector,
-                   "mean_products_plus_squarings": float(np.mean([PRODUCTS[int(a)] + int(b) for a, b in zip(m, s)]))},
-        "roofline": {"bound": "mfma", "kernel": "expm_fused_kernel<8> (orders 80..128 of the batch)",
-                     "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64, "traffic": None, "kernel_ms": ms_k8,
-                     "step_tflops": flops / (ms_step * 1e-3) / 1e12},
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(line), flush=True)
+def run_single(args, torch, P, W):
+    A = torch.from_numpy(W.single_dense(64, 2.0)).cuda()
+    ws = torch.empty(P.workspace_bytes(64, 1), dtype=torch.uint8, device="cuda")
+    for _ in range(args.warmup):
+        E, m, s, st = P.taylor(A, selector=args.selector, workspace=ws)
+    torch.cuda.synchronize()
+    reps = args.steps * 50
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        E, m, s, st = P.taylor(A, selector=args.selector, workspace=ws)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    fl = executed_flops([int(m.item())], [int(s.item())], [64])
+    cpu = None if args.no_cpu else cpu_oracle([A.cpu().numpy()] * 64, args.cpu_seconds, "64 copies of the matrix")
+    one_cu = PEAK_FP64 / 256
+    roof = {"bound": "mfma", "kernel": "expm_fused_kernel<4> (one workgroup, latency-bound)",
+            "achieved": fl / (ms * 1e-3) / 1e12, "peak": one_cu / 1e12, "unit": "TFLOP/s",
+            "frac": fl / (ms * 1e-3) / one_cu, "traffic": None, "note": "peak of the one CU a single matrix runs on"}
+    config = {"workload": "one 64x64 FP64 matrix, N(0,1) scaled to ||A||_1 = 2, one expm_taylor call per step "
+                          "(calls back to back, %d per timed step)" % 50, "selector": args.selector,
+              "m_s": [int(m.item()), int(s.item())], "us_per_matrix": ms * 1e3}
+    return line(args, "expm matrices/s (single 64x64, rel err <= 1e-12)", 1e3 / ms, ms * 50, "f64", config, roof, cpu)
+
+
+def run_precision(args, torch, P, W):
+    mats1 = W.large_dense(256, 1024, seed_stream=0)
+    mats4 = W.large_dense(16, 4096, seed_stream=1)
+    A1 = torch.from_numpy(np.stack(mats1)).cuda()
+    A4 = torch.from_numpy(np.stack(mats4)).cuda()
+    del mats4
+    ws1 = torch.empty(P.workspace_bytes(1024, 256, prec=args.prec), dtype=torch.uint8, device="cuda")
+    ws4 = torch.empty(P.workspace_bytes(4096, 16, prec=args.prec), dtype=torch.uint8, device="cuda")
+    E1, E4 = torch.empty_like(A1), torch.empty_like(A4)
+
+    def step():
+        r1 = P.batched_uniform(A1, prec=args.prec, selector=args.selector, workspace=ws1, out=E1)
+        r4 = P.batched_uniform(A4, prec=args.prec, selector=args.selector, workspace=ws4, out=E4)
+        return r1, r4
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(args.steps):
+        (_, m1, s1, st1), (_, m4, s4, st4) = step()
+    t1.record()
+    torch.cuda.synchronize()
+    ms_step = t0.elapsed_time(t1) / args.steps
+    m1, s1, m4, s4 = (x.cpu().numpy() for x in (m1, s1, m4, s4))
+    flops = executed_flops(m1, s1, [1024] * 256) + executed_flops(m4, s4, [4096] * 16)
+    err = None
+    if args.prec != "fp64":  # error of the form against the FP64 path (itself pinned to the oracle)
+        R1 = P.batched_uniform(A1, selector=args.selector)[0]
+        R4 = P.batched_uniform(A4, selector=args.selector)[0]
+        torch.cuda.synchronize()
+
+        def rel(X, R):
+            return float((X - R).abs().sum(dim=-2).amax(dim=-1).div(R.abs().sum(dim=-2).amax(dim=-1)).max())
+        err = max(rel(E1, R1), rel(E4, R4))
+    cpu = None if args.no_cpu else cpu_oracle(mats1[:1], args.cpu_seconds, "1 of the 256 n = 1024 matrices")
+    roof = {"bound": "mfma", "kernel": "lg_gemm_kernel (tiled 128x128, all GEMM steps of the step)",
+            "achieved": flops / (ms_step * 1e-3) / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+            "frac": flops / (ms_step * 1e-3) / PEAK_FP64, "traffic": None,
+            "note": "executed flops over the whole step against the FP64 peak (FP64-equivalent rate)"}
+    config = {"workload": "256 FP64 n=1024 + 16 FP64 n=4096, N(0,1)/sqrt(n) scaled to ||A||_1 ~ U[0.5,50]; two "
+                          "expm_batched_uniform calls per step", "selector": args.selector, "prec": args.prec,
+              "max_rel_err_vs_fp64_path": err,
+              "mean_products_plus_squarings": float(np.mean([PRODUCTS[int(a)] + int(b) for a, b in
+                                                             zip(np.r_[m1, m4], np.r_[s1, s4])]))}
+    return line(args, "expm matrices/s (precision workload, %s)" % args.prec, 272 / (ms_step * 1e-3), ms_step,
+                {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3+f32"}[args.prec], config, roof, cpu)
+
+
+def run_complex(args, torch, P, W):
+    mats, dts = W.hermitian_unitary_batch(count=512, n=256)
+    Z = torch.from_numpy(np.stack(mats)).cuda()
+    big = torch.from_numpy(W.single_dense(8192, 20.0, seed_stream=5)).cuda()
+    wsz = torch.empty(P.workspace_bytes(256, 512, dtype=torch.complex128), dtype=torch.uint8, device="cuda")
+    wsb = torch.empty(P.workspace_bytes(8192, 1), dtype=torch.uint8, device="cuda")
+    Ez, Eb = torch.empty_like(Z), torch.empty_like(big)
+    for _ in range(args.warmup):
+        P.batched_uniform(Z, selector=args.selector, workspace=wsz, out=Ez)
+        P.taylor(big, selector=args.selector, workspace=wsb)
+    torch.cuda.synchronize()
+    t0, t1, t2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    t0.record()
+    for _ in range(args.steps):
+        _, mz, sz, _ = P.batched_uniform(Z, selector=args.selector, workspace=wsz, out=Ez)
+    t1.record()
+    for _ in range(args.steps):
+        _, mb, sb, _ = P.taylor(big, selector=args.selector, workspace=wsb)
+    t2.record()
+    torch.cuda.synchronize()
+    ms_z = t0.elapsed_time(t1) / args.steps
+    ms_b = t1.elapsed_time(t2) / args.steps
+    mz, sz = mz.cpu().numpy(), sz.cpu().numpy()
+    # algorithmic flops: a complex product is 8 n^3 real flops (4 real products)
+    fl_z = 4 * executed_flops(mz, sz, [256] * 512)
+    fl_b = executed_flops([int(mb.item())], [int(sb.item())], [8192])
+    EzH = Ez.conj().transpose(-1, -2).contiguous()
+    unit = float((torch.matmul(EzH, Ez) - torch.eye(256, dtype=torch.complex128, device="cuda")).abs().sum(-2).amax())
+    cpu = None if args.no_cpu else cpu_oracle([np.block([[a.real, -a.imag], [a.imag, a.real]]) for a in mats[:4]],
+                                              args.cpu_seconds, "4 of the 512 complex matrices (real form)")
+    roof = {"bound": "mfma", "kernel": "lg_gemm_kernel (complex batch on the real form; n = 8192 matrix)",
+            "achieved": (fl_z + fl_b) / ((ms_z + ms_b) * 1e-3) / 1e12, "peak": PEAK_FP64 / 1e12,
+            "unit": "TFLOP/s", "frac": (fl_z + fl_b) / ((ms_z + ms_b) * 1e-3) / PEAK_FP64, "traffic": None,
+            "note": "algorithmic flops: 8 n^3 per complex product (the real form executes 16 n^3)"}
+    config = {"workload": "512 complex128 -iH dt (n=256, Hermitian, spectral radius 1, dt log-U[1e-2,1e2]) + 1 FP64 "
+                          "n=8192 ||A||_1=20", "selector": args.selector, "ms_complex_batch": ms_z,
+              "ms_n8192": ms_b, "n8192_m_s": [int(mb.item()), int(sb.item())], "max_unitarity_err": unit}
+    return line(args, "expm matrices/s (complex unitary + n=8192)", 513 / ((ms_z + ms_b) * 1e-3), ms_z + ms_b,
+                "c128/f64", config, roof, cpu)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="batched", choices=["batched", "single", "precision", "complex"])
+    ap.add_argument("--selector", default="plain", choices=["plain", "alpha"])
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--count", type=int, default=4096)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the method runs on a single MI355X (multi-GPU sharding "
+              "is a design note, not built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1710_10989_amd as P
+    from paper_1710_10989_amd import workloads as W
+    fn = {"batched": run_batched, "single": run_single, "precision": run_precision, "complex": run_complex}
+    print(json.dumps(fn[args.workload](args, torch, P, W)), flush=True)
 
 
 if __name__ == "__main__":

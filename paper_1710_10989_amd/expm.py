@@ -45,6 +45,7 @@ def select_rule(norms, selector="plain", u=2.0 ** -53):
 
 
 def workspace_bytes(n_max, batch=1, dtype=torch.float64, prec="fp64", selector="plain", u=None):
+    """Device workspace in bytes for matrices of order up to n_max (expm_workspace_bytes)."""
     o = _opts(dtype, prec, selector, u)
     return N.lib().expm_workspace_bytes(int(n_max), int(batch), ctypes.byref(o))
 
