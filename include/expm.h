@@ -150,6 +150,53 @@ EXPM_API expm_status_t expm_batched_uniform(const void *A_dev, void *E_dev, int6
                                    const expm_opts_t *opts, int32_t *m_dev, int32_t *s_dev,
                                    int32_t *status_dev, void *ws_dev, size_t ws_bytes, void *stream);
 
+/* ---------------------------------------------------------------------------------------
+ * Learned (m, s) selector (EXPM_SEL_LEARNED).  Not part of the paper: a small MLP proposes
+ * (m, s) from features that exist once A^2 is formed; the proposal is kept only when the
+ * alpha_p backward-error bound of eq. eq.theta holds for it (with ||A^3|| when the proposed
+ * degree forms A^3, else its submultiplicative bound), otherwise the plain ||A||_1 rule
+ * decides.  Classes: 0..4 = (1, 0), (2, 0), (4, 0), (8, 0), (12, 0); 5..15 = (18, 0..10).
+ * Features (8, in this order): log2 d_1 .. log2 d_5 with d_k = ||A^k||_1^(1/k) (d_3, d_4, d_5
+ * by submultiplicative bounds from ||A||, ||A^2||), log2 n, |tr A| / ||A||_1,
+ * ||A - A^T||_1 / (2 ||A||_1).
+ * MLP: 8 -> 64 (ReLU) -> 64 (ReLU) -> 16, FP32, parameters packed as W1[64][8], b1[64],
+ * W2[64][64], b2[64], W3[16][64], b3[16] (expm_mlp_param_count() floats).
+ * Used by the fused path (real order <= 256); the tiled path runs EXPM_SEL_ALPHA instead.
+ * --------------------------------------------------------------------------------------- */
+
+/* Feature rows and training labels for a packed batch (arguments as expm_batched; real FP64,
+ * order <= 256).  features_dev: 16 doubles per matrix: f0..f7, ||A||_1, ||A^2||_1,
+ * ||A^3||_1, label class, plain m, plain s, alpha m, alpha s.  The label is the cheapest
+ * (m, s) that passes the acceptance test above; it is also written to m_dev / s_dev.  Forms
+ * A^2 and A^3 in the workspace; no e^A. */
+EXPM_API expm_status_t expm_features(const void *A_dev, const int64_t *offsets_dev, const int32_t *n_dev,
+                                     int64_t batch, int64_t n_max, const expm_opts_t *opts, double *features_dev,
+                                     int32_t *m_dev, int32_t *s_dev, void *ws_dev, size_t ws_bytes, void *stream);
+
+/* MLP kernels (device pointers, FP32, row-major batches: x [batch][8], logits [batch][16]).
+ * scratch: expm_mlp_scratch_bytes(batch) bytes.  expm_mlp_grad writes the gradient of the
+ * mean softmax cross-entropy over the batch (labels y, int32 classes) to grads_dev
+ * (expm_mlp_param_count() floats) and the per-sample losses to loss_dev (batch floats).
+ * expm_mlp_adam applies one Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected,
+ * step >= 1) to params_dev with moment buffers m_dev, v_dev.  All deterministic. */
+EXPM_API size_t expm_mlp_scratch_bytes(int32_t batch);
+EXPM_API int32_t expm_mlp_param_count(void);
+EXPM_API expm_status_t expm_mlp_forward(const float *params_dev, const float *x_dev, int32_t batch,
+                                        float *logits_dev, void *scratch_dev, size_t scratch_bytes, void *stream);
+EXPM_API expm_status_t expm_mlp_grad(const float *params_dev, const float *x_dev, const int32_t *y_dev,
+                                     int32_t batch, float *grads_dev, float *loss_dev, void *scratch_dev,
+                                     size_t scratch_bytes, void *stream);
+EXPM_API expm_status_t expm_mlp_adam(float *params_dev, const float *grads_dev, float *m_dev, float *v_dev,
+                                     int32_t step, float lr, void *stream);
+
+/* Installs the selector's parameters (device, copied) and feature normalisation (host:
+ * mean[8] then std[8], std > 0; the MLP sees (f - mean) / std), and resets the counters.
+ * Process-wide state of the current device; synchronises `stream`. */
+EXPM_API expm_status_t expm_learned_set(const float *params_dev, const double *norm_host, void *stream);
+
+/* Proposals accepted / rejected by EXPM_SEL_LEARNED since the last expm_learned_set. */
+EXPM_API expm_status_t expm_learned_counts(int64_t *accepted, int64_t *rejected);
+
 #ifdef __cplusplus
 }
 #endif

@@ -46,6 +46,7 @@ def lib():
         L.or_select_plain.argtypes = [dbl, vp, ip, ip]; L.or_select_plain.restype = None
         L.or_select_alpha.argtypes = [vp, vp, ip, ip]; L.or_select_alpha.restype = None
         L.or_powers_norms.argtypes = [i64, vp, i32, vp]; L.or_powers_norms.restype = None
+        L.or_select_alpha_split.argtypes = [vp, vp, vp, ip, ip]; L.or_select_alpha_split.restype = None
         _lib = L
     return _lib
 
@@ -179,3 +180,38 @@ def rel_err_1(X, R):
     """Relative 1-norm error ||X - R||_1 / ||R||_1 (long double accumulation)."""
     D = np.asarray(X) - np.asarray(R)
     return norm1(D) / norm1(R)
+
+
+def alpha_bounds(n1, n2, n3=None):
+    """[d_1..d_5]: d_k = ||A^k||^(1/k) from ||A||, ||A^2|| and, when given, ||A^3||; the
+    missing ones by submultiplicativity (||A^3|| <= ||A|| ||A^2||, ||A^4|| <= min(||A^2||^2,
+    ||A^3|| ||A||), ||A^5|| <= min(||A^2|| ||A^3||, ||A^4|| ||A||))."""
+    if n3 is None:
+        n3 = min(n1 * n2, n1 ** 3)
+    n4 = min(n2 * n2, n3 * n1)
+    n5 = min(n2 * n3, n4 * n1)
+    return [n1, n2 ** 0.5, n3 ** (1.0 / 3.0), n4 ** 0.25, n5 ** 0.2]
+
+
+def learned_label(n1, n2, n3, u=2.0 ** -53):
+    """Cheapest (m, s) passing the alpha bound with ||A^3|| for m >= 12 and its bound for
+    m <= 8 (the information the learned selector has)."""
+    th = _theta_row(u)
+    lo = np.array(alpha_bounds(n1, n2), dtype=np.float64)
+    hi = np.array(alpha_bounds(n1, n2, n3), dtype=np.float64)
+    m, s = ctypes.c_int(0), ctypes.c_int(0)
+    lib().or_select_alpha_split(_p(lo), _p(hi), _p(th), ctypes.byref(m), ctypes.byref(s))
+    return m.value, s.value
+
+
+def learned_features(A):
+    """The selector's 8 features of a real matrix: log2 d_1..d_5 (bounds from ||A||, ||A^2||),
+    log2 n, |tr A| / ||A||_1, ||A - A^T||_1 / (2 ||A||_1)."""
+    A = _f64(A)
+    n1, n2 = powers_norms(A, 2)
+    d = alpha_bounds(n1, n2)
+    f = [np.log2(max(x, 1e-300)) for x in d]
+    f.append(np.log2(A.shape[0]))
+    f.append(abs(np.trace(A)) / n1 if n1 > 0 else 0.0)
+    f.append(norm1(A - A.T) / (2 * n1) if n1 > 0 else 0.0)
+    return np.array(f)

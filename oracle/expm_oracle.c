@@ -541,3 +541,25 @@ void or_select_alpha(const double *dk, const double *theta, int *m_out, int *s_o
   }
   select_from_eta(e, theta, m_out, s_out);
 }
+
+/*
+ * Label rule of the learned selector: degrees m >= 12 judge the alpha bound with dk_hi
+ * (exact d_3, because those degrees form A^3), degrees m <= 8 with dk_lo (d_3 only through
+ * its bound).  Otherwise as or_select_alpha.
+ */
+void or_select_alpha_split(const double *dk_lo, const double *dk_hi, const double *theta, int *m_out,
+                           int *s_out) {
+  ld e[6];
+  for (int i = 0; i < 6; ++i) {
+    const int m = SEL_M[i];
+    const double *dk = m >= 12 ? dk_hi : dk_lo;
+    ld best = -1.0L;
+    for (int p = 1; p <= 4; ++p) {
+      if (p * (p - 1) > m + 1) break;
+      ld a = dk[p - 1] > dk[p] ? dk[p - 1] : dk[p];
+      if (best < 0 || a < best) best = a;
+    }
+    e[i] = best;
+  }
+  select_from_eta(e, theta, m_out, s_out);
+}

@@ -16,7 +16,9 @@ EXPM_PREC_FP64, EXPM_PREC_FP32, EXPM_PREC_BF16X3 = 0, 1, 2
 EXPM_SEL_PLAIN, EXPM_SEL_ALPHA, EXPM_SEL_LEARNED = 0, 1, 2
 
 EXPORTED = ("expm_status_string", "expm_theta", "expm_select_rule", "expm_workspace_bytes",
-            "expm_select", "expm_taylor", "expm_batched", "expm_batched_stage", "expm_batched_uniform")
+            "expm_select", "expm_taylor", "expm_batched", "expm_batched_stage", "expm_batched_uniform",
+            "expm_features", "expm_mlp_scratch_bytes", "expm_mlp_param_count", "expm_mlp_forward",
+            "expm_mlp_grad", "expm_mlp_adam", "expm_learned_set", "expm_learned_counts")
 
 
 class ExpmOpts(ctypes.Structure):
@@ -55,6 +57,16 @@ def lib():
         L.expm_batched_stage.restype = i32
         L.expm_batched_uniform.argtypes = [vp, vp, i64, i64, op, vp, vp, vp, vp, sz, vp]
         L.expm_batched_uniform.restype = i32
+        L.expm_features.argtypes = [vp, vp, vp, i64, i64, op, vp, vp, vp, vp, sz, vp]
+        L.expm_features.restype = i32
+        L.expm_mlp_scratch_bytes.argtypes = [i32]; L.expm_mlp_scratch_bytes.restype = sz
+        L.expm_mlp_param_count.argtypes = []; L.expm_mlp_param_count.restype = i32
+        L.expm_mlp_forward.argtypes = [vp, vp, i32, vp, vp, sz, vp]; L.expm_mlp_forward.restype = i32
+        L.expm_mlp_grad.argtypes = [vp, vp, vp, i32, vp, vp, vp, sz, vp]; L.expm_mlp_grad.restype = i32
+        L.expm_mlp_adam.argtypes = [vp, vp, vp, vp, i32, ctypes.c_float, vp]; L.expm_mlp_adam.restype = i32
+        L.expm_learned_set.argtypes = [vp, vp, vp]; L.expm_learned_set.restype = i32
+        L.expm_learned_counts.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        L.expm_learned_counts.restype = i32
         _lib = L
     return _lib
 

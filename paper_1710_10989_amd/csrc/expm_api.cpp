@@ -9,6 +9,15 @@
 #include "expm_fused.h"
 #include "expm_internal.h"
 #include "expm_large.h"
+#include "mlp.h"
+
+namespace expm {
+size_t mlp_scratch_floats(int B);
+hipError_t mlp_forward(const float *params, const float *X, int B, float *scratch, float *logits, hipStream_t st);
+hipError_t mlp_grad(const float *params, const float *X, const int *y, int B, float *scratch, float *grads,
+                    float *loss, hipStream_t st);
+hipError_t mlp_adam_step(float *params, const float *grads, float *m, float *v, int step, float lr, hipStream_t st);
+}  // namespace expm
 
 using namespace expm;
 
@@ -147,7 +156,7 @@ static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, cons
                                int64_t batch, int64_t n_uniform, int64_t n_max,
                                const expm_opts_t *opts, double u, int32_t *m_dev, int32_t *s_dev,
                                int32_t *status_dev, void *ws, size_t ws_bytes, void *stream,
-                               int select_only, int stage = -1) {
+                               int select_only, int stage = -1, double *features = nullptr) {
   // n_uniform and n_max are input orders; the kernels pad the real order
   const int cplx = opts->dtype == EXPM_C128;
   const int64_t nr_max = real_order(opts, n_max), nr_uni = real_order(opts, n_uniform);
@@ -169,8 +178,9 @@ static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, cons
   a.n_uniform = (int)n_uniform;
   a.np_max = (int)pad16(nr_max);
   a.cplx = cplx;
-  a.sel = opts->sel == EXPM_SEL_LEARNED ? EXPM_SEL_ALPHA : opts->sel;
+  a.sel = opts->sel;  // the fused kernels run all three rules
   a.select_only = select_only;
+  a.features = features;
   hipStream_t st = (hipStream_t)stream;
   FusedArgs a8 = a, a4 = a;
   a8.slots = (double *)(base + L.slots8_off);
@@ -287,6 +297,65 @@ expm_status_t expm_batched_uniform(const void *A_dev, void *E_dev, int64_t n, in
     return run_large_call(A_dev, E_dev, n, batch, opts, u, m_dev, s_dev, status_dev, ws_dev, ws_bytes, stream, 0);
   return run_fused(A_dev, E_dev, nullptr, nullptr, batch, n, n, opts, u, m_dev, s_dev, status_dev,
                    ws_dev, ws_bytes, stream, 0);
+}
+
+expm_status_t expm_features(const void *A_dev, const int64_t *offsets_dev, const int32_t *n_dev, int64_t batch,
+                            int64_t n_max, const expm_opts_t *opts, double *features_dev, int32_t *m_dev,
+                            int32_t *s_dev, void *ws_dev, size_t ws_bytes, void *stream) {
+  double u;
+  expm_status_t st = check_opts(opts, &u);
+  if (st != EXPM_OK) return st;
+  if (!A_dev || !offsets_dev || !n_dev || !features_dev || !m_dev || !s_dev || batch < 1 || n_max < 1)
+    return EXPM_E_INVALID_ARG;
+  if (opts->dtype != EXPM_F64 || opts->prec != EXPM_PREC_FP64 || n_max > kFusedNMax) return EXPM_E_UNSUPPORTED;
+  return run_fused(A_dev, nullptr, offsets_dev, n_dev, batch, 0, n_max, opts, u, m_dev, s_dev, nullptr, ws_dev,
+                   ws_bytes, stream, 1, -1, features_dev);
+}
+
+size_t expm_mlp_scratch_bytes(int32_t batch) {
+  return batch < 1 ? 0 : mlp_scratch_floats(batch) * sizeof(float);
+}
+
+int32_t expm_mlp_param_count(void) { return kMlpParams; }
+
+expm_status_t expm_mlp_forward(const float *params_dev, const float *x_dev, int32_t batch, float *logits_dev,
+                               void *scratch_dev, size_t scratch_bytes, void *stream) {
+  if (!params_dev || !x_dev || !logits_dev || !scratch_dev || batch < 1) return EXPM_E_INVALID_ARG;
+  if (scratch_bytes < expm_mlp_scratch_bytes(batch)) return EXPM_E_WORKSPACE;
+  return mlp_forward(params_dev, x_dev, batch, (float *)scratch_dev, logits_dev, (hipStream_t)stream) == hipSuccess
+             ? EXPM_OK : EXPM_E_HIP;
+}
+
+expm_status_t expm_mlp_grad(const float *params_dev, const float *x_dev, const int32_t *y_dev, int32_t batch,
+                            float *grads_dev, float *loss_dev, void *scratch_dev, size_t scratch_bytes, void *stream) {
+  if (!params_dev || !x_dev || !y_dev || !grads_dev || !loss_dev || !scratch_dev || batch < 1)
+    return EXPM_E_INVALID_ARG;
+  if (scratch_bytes < expm_mlp_scratch_bytes(batch)) return EXPM_E_WORKSPACE;
+  return mlp_grad(params_dev, x_dev, y_dev, batch, (float *)scratch_dev, grads_dev, loss_dev, (hipStream_t)stream) ==
+                 hipSuccess ? EXPM_OK : EXPM_E_HIP;
+}
+
+expm_status_t expm_mlp_adam(float *params_dev, const float *grads_dev, float *m_dev, float *v_dev, int32_t step,
+                            float lr, void *stream) {
+  if (!params_dev || !grads_dev || !m_dev || !v_dev || step < 1 || !(lr > 0.0f)) return EXPM_E_INVALID_ARG;
+  return mlp_adam_step(params_dev, grads_dev, m_dev, v_dev, step, lr, (hipStream_t)stream) == hipSuccess ? EXPM_OK
+                                                                                                   : EXPM_E_HIP;
+}
+
+expm_status_t expm_learned_set(const float *params_dev, const double *norm_host, void *stream) {
+  if (!params_dev || !norm_host) return EXPM_E_INVALID_ARG;
+  for (int k = 0; k < kMlpIn; ++k)
+    if (!(norm_host[kMlpIn + k] > 0.0) || !isfinite(norm_host[k])) return EXPM_E_INVALID_ARG;
+  return learned_set(params_dev, norm_host, (hipStream_t)stream) == hipSuccess ? EXPM_OK : EXPM_E_HIP;
+}
+
+expm_status_t expm_learned_counts(int64_t *accepted, int64_t *rejected) {
+  if (!accepted || !rejected) return EXPM_E_INVALID_ARG;
+  unsigned long long c[2];
+  if (learned_counts(c) != hipSuccess) return EXPM_E_HIP;
+  *accepted = (int64_t)c[0];
+  *rejected = (int64_t)c[1];
+  return EXPM_OK;
 }
 
 }  // extern "C"

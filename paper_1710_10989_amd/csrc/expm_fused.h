@@ -27,8 +27,16 @@ struct FusedArgs {
   int sel;                // expm_sel_t
   int select_only;
   int cplx;               // inputs / outputs are interleaved complex (run on the real form)
+  double *features;       // feature rows of the learned selector (kFeatRow doubles per
+                          // matrix); when set no e^A is computed
   Consts k;
 };
+
+// Feature row: f0..f7 (raw features), ||A||, ||A^2||, ||A^3||, label class, plain m, plain s,
+// alpha m, alpha s.
+constexpr int kFeatRow = 16;
+hipError_t learned_set(const float *params_dev, const double *norm_host, hipStream_t st);
+hipError_t learned_counts(unsigned long long out[2]);
 
 
 constexpr int kFusedBufs = 8;

@@ -22,12 +22,21 @@
 #include "expm_internal.h"
 #include "coefs.h"
 #include "gemm_block.h"
+#include "mlp.h"
 
 namespace expm {
+
+// Learned selector state: MLP parameters, feature normalisation (mean[8], std[8]) and the
+// accepted / rejected proposal counters.
+__device__ float g_mlp_params[kMlpParams];
+__device__ double g_mlp_norm[2 * kMlpIn];
+__device__ unsigned long long g_learned_counts[2];
 
 namespace {
 
 constexpr int kBufs = kFusedBufs;
+__shared__ int sh_ms[2];
+__shared__ float sh_mlp[8 + 64 + 64 + 16];
 
 // Column sums of |B| over an np x np buffer (thread j owns column j), reduced to the maximum.
 template <int NT>
@@ -53,6 +62,93 @@ __device__ double block_norm1(const double *B, int np, double *red) {
   double r = red[0];
   __syncthreads();
   return r;
+}
+
+// Trace of an np x np buffer.
+template <int NT>
+__device__ double block_trace(const double *B, int np, double *red) {
+  const int tid = threadIdx.x;
+  red[tid] = tid < np ? B[tid * np + tid] : 0.0;
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// ||B - B^T||_1 of an np x np buffer (thread j owns column j).
+template <int NT>
+__device__ double block_asym1(const double *B, int np, double *red) {
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  if (tid < np)
+    for (int i = 0; i < np; ++i) s += fabs(B[i * np + tid] - B[tid * np + i]);
+  red[tid] = s;
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// The learned selector's 8 raw features from ||A||, ||A^2||, tr A, ||A - A^T||, n:
+// log2 d_1 .. log2 d_5 (d_3..d_5 by their submultiplicative bounds), log2 n,
+// |tr A| / ||A||_1, ||A - A^T||_1 / (2 ||A||_1).
+__device__ inline void learned_features(double n1, double n2, double tr, double asym, int n, double *f) {
+  double d[5];
+  alpha_d(n1, n2, -1.0, d);
+  for (int k = 0; k < 5; ++k) f[k] = log2(fmax(d[k], 1e-300));
+  f[5] = log2((double)n);
+  f[6] = n1 > 0.0 ? fabs(tr) / n1 : 0.0;
+  f[7] = n1 > 0.0 ? asym / (2.0 * n1) : 0.0;
+}
+
+// MLP inference (weights in g_mlp_params, feature normalisation in g_mlp_norm); returns the
+// proposed class.  Threads 0..63 evaluate the hidden units.
+template <int NT>
+__device__ int mlp_infer(double n1, double n2, double tr, double asym, int n) {
+  const int tid = threadIdx.x;
+  const float *W = g_mlp_params;
+  if (tid == 0) {
+    double f[8];
+    learned_features(n1, n2, tr, asym, n, f);
+    for (int k = 0; k < kMlpIn; ++k) sh_mlp[k] = (float)((f[k] - g_mlp_norm[k]) / g_mlp_norm[kMlpIn + k]);
+  }
+  __syncthreads();
+  if (tid < kMlpH) {
+    float acc = W[kMlpB1 + tid];
+    for (int k = 0; k < kMlpIn; ++k) acc += W[kMlpW1 + tid * kMlpIn + k] * sh_mlp[k];
+    sh_mlp[8 + tid] = fmaxf(acc, 0.0f);
+  }
+  __syncthreads();
+  if (tid < kMlpH) {
+    float acc = W[kMlpB2 + tid];
+    for (int k = 0; k < kMlpH; ++k) acc += W[kMlpW2 + tid * kMlpH + k] * sh_mlp[8 + k];
+    sh_mlp[72 + tid] = fmaxf(acc, 0.0f);
+  }
+  __syncthreads();
+  if (tid < kMlpOut) {
+    float acc = W[kMlpB3 + tid];
+    for (int k = 0; k < kMlpH; ++k) acc += W[kMlpW3 + tid * kMlpH + k] * sh_mlp[72 + k];
+    sh_mlp[136 + tid] = acc;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int best = 0;
+    for (int c = 1; c < kMlpOut; ++c)
+      if (sh_mlp[136 + c] > sh_mlp[136 + best]) best = c;
+    sh_ms[0] = best;
+  }
+  __syncthreads();
+  const int cls = sh_ms[0];
+  __syncthreads();
+  return cls;
 }
 
 // Elementwise pass over the np x np index space: each thread gathers the NIN inputs of
@@ -85,7 +181,7 @@ __device__ void for_each_elem(int np, const double *const (&inp)[NIN], const F &
   __syncthreads();
 }
 
-__shared__ int sh_ms[2];
+
 
 // One GEMM step: thread 0 fills the LDS descriptor through `set`, then all threads run it.
 template <int NW, class S>
@@ -182,30 +278,72 @@ __device__ void run_one(const FusedArgs &a, int64_t b, double *slot, double *red
 
   if (tid == 0) select_ms(a.k.theta, 0, eta, -1.0, -1.0, &sh_ms[0], &sh_ms[1]);
   __syncthreads();
-  const int m_plain = sh_ms[0];
+  const int m_plain = sh_ms[0], s_plain = sh_ms[1];
 
-  // ---- powers A^2 (m >= 2), A^3 (m >= 12) ----
-  const bool want_alpha = (a.sel == EXPM_SEL_ALPHA);
+  // ---- powers A^2 (buffer 1), A^3 (buffer 2) as the selection needs them ----
+  bool have2 = false, have3 = false;
   double n2 = -1.0, n3 = -1.0;
-  if (m_plain >= 2) {
+  auto form2 = [&]() {
+    if (have2) return;
     gemm_step<NW>([&](EpiDesc &d) {
       d.P = buf[0]; d.Q = buf[0]; d.kind = EK_STORE; d.np = np;
       d.dst = buf[1]; d.dst_ld = np; d.dst_nvalid = np; d.cplx = 0;
     });
-    if (want_alpha) n2 = block_norm1<NT>(buf[1], np, red);
-  }
-  if (m_plain >= 12) {
+    have2 = true;
+  };
+  auto form3 = [&]() {
+    form2();
+    if (have3) return;
     gemm_step<NW>([&](EpiDesc &d) {
       d.P = buf[1]; d.Q = buf[0]; d.kind = EK_STORE; d.np = np;
       d.dst = buf[2]; d.dst_ld = np; d.dst_nvalid = np; d.cplx = 0;
     });
-    if (want_alpha) n3 = block_norm1<NT>(buf[2], np, red);
-  }
-  if (want_alpha && m_plain >= 2) {
-    if (tid == 0) select_ms(a.k.theta, 1, eta, n2, n3, &sh_ms[0], &sh_ms[1]);
+    have3 = true;
+  };
+  int m = m_plain, s = s_plain;
+  if (a.features) {
+    // feature row and training label of the learned selector (no e^A)
+    form3();
+    n2 = block_norm1<NT>(buf[1], np, red);
+    n3 = block_norm1<NT>(buf[2], np, red);
+    const double tr = block_trace<NT>(buf[0], np, red), asym = block_asym1<NT>(buf[0], np, red);
+    if (tid == 0) {
+      double *row = a.features + b * kFeatRow;
+      learned_features(eta, n2, tr, asym, n, row);
+      int lm, ls, am, as;
+      learned_label(a.k.theta, eta, n2, n3, &lm, &ls);
+      select_ms(a.k.theta, 1, eta, m_plain >= 2 ? n2 : -1.0, m_plain >= 12 ? n3 : -1.0, &am, &as);
+      row[8] = eta; row[9] = n2; row[10] = n3; row[11] = mlp_ms_class(lm, ls);
+      row[12] = m_plain; row[13] = s_plain; row[14] = am; row[15] = as;
+      a.m_out[b] = lm; a.s_out[b] = ls;
+      if (a.status) a.status[b] = EXPM_OK;
+    }
     __syncthreads();
+    return;
+  } else if (a.sel == EXPM_SEL_ALPHA) {
+    if (m_plain >= 2) { form2(); n2 = block_norm1<NT>(buf[1], np, red); }
+    if (m_plain >= 12) { form3(); n3 = block_norm1<NT>(buf[2], np, red); }
+    if (m_plain >= 2) {
+      if (tid == 0) select_ms(a.k.theta, 1, eta, n2, n3, &sh_ms[0], &sh_ms[1]);
+      __syncthreads();
+      m = sh_ms[0]; s = sh_ms[1];
+    }
+  } else if (a.sel == EXPM_SEL_LEARNED && m_plain >= 2) {
+    // proposal from the MLP on features available once A^2 exists; kept only if the alpha
+    // bound holds for it (with ||A^3|| when the proposal forms A^3 anyway), else the plain rule
+    form2();
+    n2 = block_norm1<NT>(buf[1], np, red);
+    const double tr = block_trace<NT>(buf[0], np, red), asym = block_asym1<NT>(buf[0], np, red);
+    const int cls = mlp_infer<NT>(eta, n2, tr, asym, n);
+    int mq, sq;
+    mlp_class_ms(cls, &mq, &sq);
+    if (mq >= 12) { form3(); n3 = block_norm1<NT>(buf[2], np, red); }
+    const bool ok = proposal_ok(a.k.theta, eta, n2, mq >= 12 ? n3 : -1.0, mq, sq);
+    if (ok) { m = mq; s = sq; } else { m = m_plain; s = s_plain; }
+    if (tid == 0) atomicAdd(&g_learned_counts[ok ? 0 : 1], 1ull);
   }
-  const int m = sh_ms[0], s = sh_ms[1];
+  if (m >= 2) form2();
+  if (m >= 12) form3();
   if (tid == 0) {
     make_coefs(a.k, m, s, g_ep.c);
     a.m_out[b] = m; a.s_out[b] = s;
@@ -377,6 +515,27 @@ hipError_t launch_order(const int32_t *ns, int64_t batch, int cplx, int32_t *ord
                         unsigned long long *queue, hipStream_t st) {
   hipLaunchKernelGGL(expm_order_kernel, dim3(1), dim3(1024), 0, st, ns, batch, cplx, order, queue);
   return hipGetLastError();
+}
+
+}  // namespace expm
+
+namespace expm {
+
+hipError_t learned_set(const float *params_dev, const double *norm_host, hipStream_t st) {
+  hipError_t e = hipMemcpyToSymbolAsync(HIP_SYMBOL(g_mlp_params), params_dev, kMlpParams * sizeof(float), 0,
+                                        hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return e;
+  e = hipMemcpyToSymbolAsync(HIP_SYMBOL(g_mlp_norm), norm_host, 2 * kMlpIn * sizeof(double), 0,
+                             hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return e;
+  const unsigned long long z[2] = {0ull, 0ull};
+  e = hipMemcpyToSymbolAsync(HIP_SYMBOL(g_learned_counts), z, sizeof(z), 0, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(st);
+}
+
+hipError_t learned_counts(unsigned long long out[2]) {
+  return hipMemcpyFromSymbol(out, HIP_SYMBOL(g_learned_counts), 2 * sizeof(unsigned long long));
 }
 
 }  // namespace expm

@@ -57,33 +57,74 @@ __host__ __device__ inline void alpha_d(double n1, double n2, double n3, double 
   d[4] = pow(n5, 0.2);
 }
 
-// (m, s) selection: for each degree, eta_m is ||A||_1 (PLAIN) or the smallest admissible
-// alpha_p = max(d_p, d_{p+1}) with p (p - 1) <= m + 1 (ALPHA); s_m = scale_exp(eta_m, theta_m);
-// cost = products + s_m; cheapest wins, ties go to the smaller s.
+// Norm quantity for degree index i: ||A||_1 (PLAIN) or the smallest admissible
+// alpha_p = max(d_p, d_{p+1}) with p (p - 1) <= m + 1 (ALPHA), d from alpha_d.
+__host__ __device__ inline double eta_for_degree(int i, int alpha, double n1, const double d[5]) {
+  if (!alpha) return n1;
+  const int m = kDeg[i];
+  double eta = n1;  // p = 1: alpha_1 = max(d_1, d_2) = d_1
+  for (int p = 2; p <= 4; ++p) {
+    if (p * (p - 1) > m + 1) break;
+    const double a = fmax(d[p - 1], d[p]);
+    if (a < eta) eta = a;
+  }
+  return eta;
+}
+
+__host__ __device__ inline int degree_index(int m) {
+  for (int i = 0; i < kNumDeg; ++i)
+    if (kDeg[i] == m) return i;
+  return -1;
+}
+
+// (m, s) selection: for each degree, s_m = scale_exp(eta_m, theta_m) with eta_m from
+// eta_for_degree; cost = products + s_m; cheapest wins, ties go to the smaller s.
 __host__ __device__ inline void select_ms(const double *theta, int alpha, double n1, double n2,
                                           double n3, int *m_out, int *s_out) {
   double d[5];
   if (alpha) alpha_d(n1, n2, n3, d);
   int best = -1, best_cost = 0, best_s = 0;
   for (int i = 0; i < kNumDeg; ++i) {
-    double eta = n1;
-    if (alpha) {
-      const int m = kDeg[i];
-      eta = n1;  // p = 1: alpha_1 = max(d_1, d_2) = d_1
-      for (int p = 2; p <= 4; ++p) {
-        if (p * (p - 1) > m + 1) break;
-        double a = fmax(d[p - 1], d[p]);
-        if (a < eta) eta = a;
-      }
-    }
-    int s = scale_exp(eta, theta[i]);
-    int cost = kProducts[i] + s;
+    const int s = scale_exp(eta_for_degree(i, alpha, n1, d), theta[i]);
+    const int cost = kProducts[i] + s;
     if (best < 0 || cost < best_cost || (cost == best_cost && s < best_s)) {
       best = i; best_cost = cost; best_s = s;
     }
   }
   *m_out = kDeg[best];
   *s_out = best_s;
+}
+
+// Training label of the learned selector: the cheapest (m, s) that passes the alpha bound
+// with the information the selector has when it decides: ||A||, ||A^2|| always; ||A^3|| only
+// for m >= 12 (those degrees form A^3 anyway); smaller degrees use its submultiplicative
+// bound.  Ties go to the smaller s.
+__host__ __device__ inline void learned_label(const double *theta, double n1, double n2, double n3,
+                                              int *m_out, int *s_out) {
+  double dlo[5], dhi[5];
+  alpha_d(n1, n2, -1.0, dlo);
+  alpha_d(n1, n2, n3, dhi);
+  int best = -1, best_cost = 0, best_s = 0;
+  for (int i = 0; i < kNumDeg; ++i) {
+    const double *d = kDeg[i] >= 12 ? dhi : dlo;
+    const int s = scale_exp(eta_for_degree(i, 1, n1, d), theta[i]);
+    const int cost = kProducts[i] + s;
+    if (best < 0 || cost < best_cost || (cost == best_cost && s < best_s)) {
+      best = i; best_cost = cost; best_s = s;
+    }
+  }
+  *m_out = kDeg[best];
+  *s_out = best_s;
+}
+
+// Acceptance test of a proposed (m, s): the alpha bound with ||A^3|| when given (n3 >= 0),
+// else its bound.  True iff the backward error of T_m at X = A / 2^s stays below u.
+__host__ __device__ inline bool proposal_ok(const double *theta, double n1, double n2, double n3, int m, int s) {
+  const int i = degree_index(m);
+  if (i < 0 || s < 0) return false;
+  double d[5];
+  alpha_d(n1, n2, n3, d);
+  return scale_exp(eta_for_degree(i, 1, n1, d), theta[i]) <= s;
 }
 
 }  // namespace expm
