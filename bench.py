@@ -11,6 +11,10 @@ Other workloads (one JSON line each, selected with --workload):
   single     one 64 x 64 FP64 matrix, ||A||_1 = 2 (latency-bound; repeated expm_taylor calls)
   precision  256 matrices n = 1024 + 16 matrices n = 4096, N(0,1)/sqrt(n) entries scaled to
              ||A||_1 uniform in [0.5, 50]; --prec fp64 / fp32 / bf16x3
+  learned    20000 held-out FP64 matrices, n in {32, 64, 128, 256}, ||A||_1 log-uniform in
+             [1e-2, 1e3], the batched structure mix; plain vs alpha vs learned selector (the
+             network is trained on 200k matrices of the same distribution by
+             `python -m paper_1710_10989_amd.learned train`; its checkpoint is loaded if present)
   complex    512 complex matrices -i H dt (H Hermitian, spectral radius 1, n = 256,
              dt log-uniform in [1e-2, 1e2]) + one dense FP64 n = 8192 with ||A||_1 = 20
 
@@ -229,12 +233,88 @@ def run_complex(args, torch, P, W):
                 "c128/f64", config, roof, cpu)
 
 
+def run_learned(args, torch, P, W):
+    from paper_1710_10989_amd import learned as LS
+    from paper_1710_10989_amd.expm import Batch
+    if os.path.exists(LS.DEFAULT_CKPT):
+        net = LS.MLP()
+        net.load(LS.DEFAULT_CKPT)
+        trained = "checkpoint " + os.path.basename(LS.DEFAULT_CKPT)
+    else:
+        net = LS.train(LS.make_dataset(24576, seed=11), epochs=8)
+        trained = "24576 matrices, 8 epochs (no checkpoint found)"
+    LS.install(net)
+    gen = torch.Generator().manual_seed(20000)
+    stacks = [LS.device_batch(5000, n, gen) for n in LS.SIZES]
+    packed = torch.cat([a.reshape(-1) for a in stacks])
+    ns = torch.cat([torch.full((5000,), n, dtype=torch.int32) for n in LS.SIZES]).cuda()
+    sizes = torch.cat([torch.full((5000,), n * n, dtype=torch.int64) for n in LS.SIZES])
+    offs = torch.cat([torch.zeros(1, dtype=torch.int64), torch.cumsum(sizes, 0)[:-1]]).cuda()
+    B = Batch(packed, offs, ns, 256)
+    nb = 20000
+    ws = torch.empty(P.workspace_bytes(256, nb), dtype=torch.uint8, device="cuda")
+    outs = (torch.empty_like(packed), torch.empty(nb, dtype=torch.int32, device="cuda"),
+            torch.empty(nb, dtype=torch.int32, device="cuda"), torch.empty(nb, dtype=torch.int32, device="cuda"))
+    res = {}
+    for sel in ("plain", "alpha", "learned"):
+        for _ in range(args.warmup):
+            P.batched(B, selector=sel, workspace=ws, outs=outs)
+        torch.cuda.synchronize()
+        if sel == "learned":
+            LS.install(net)  # reset the counters
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(args.steps):
+            P.batched(B, selector=sel, workspace=ws, outs=outs)
+        t1.record()
+        torch.cuda.synchronize()
+        m, s, st = (x.cpu().numpy() for x in outs[1:])
+        assert np.all(st == 0)
+        nsh = ns.cpu().numpy()
+        res[sel] = {"ms": t0.elapsed_time(t1) / args.steps, "m": m, "s": s,
+                    "cost": float(np.mean([PRODUCTS[int(a)] + int(b) for a, b in zip(m, s)])),
+                    "tflops": executed_flops(m, s, nsh) / (t0.elapsed_time(t1) / args.steps * 1e-3) / 1e12}
+    acc, rej = LS.counts()
+    acc //= max(1, args.steps)
+    rej //= max(1, args.steps)
+    nsh = ns.cpu().numpy()
+    # dominant kernel of the learned run: time the 8-wave phase with events
+    kev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for i in range(args.steps):
+        P.batched(B, selector="learned", workspace=ws, outs=outs, stage=0)
+        kev[i][0].record()
+        P.batched(B, selector="learned", workspace=ws, outs=outs, stage=1)
+        kev[i][1].record()
+        P.batched(B, selector="learned", workspace=ws, outs=outs, stage=2)
+    torch.cuda.synchronize()
+    ms_k8 = sum(a.elapsed_time(b) for a, b in kev) / args.steps
+    big = ((nsh + 15) // 16) >= 5
+    ml, sl = res["learned"]["m"], res["learned"]["s"]
+    achieved = executed_flops(ml[big], sl[big], nsh[big]) / (ms_k8 * 1e-3)
+    cpu = None
+    if not args.no_cpu:
+        sample = [stacks[i % 4][i].cpu().numpy() for i in range(16)]
+        cpu = cpu_oracle(sample, args.cpu_seconds, "16 of the held-out matrices (4 per order)")
+    roof = {"bound": "mfma", "kernel": "expm_fused_kernel<8> (orders 80..256, learned selector)",
+            "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64,
+            "traffic": None, "kernel_ms": ms_k8}
+    config = {"workload": "20000 held-out FP64 matrices, n in {32,64,128,256} (5000 each), ||A||_1 log-U[1e-2,1e3], "
+                          "40/20/20/20 structure mix; one expm_batched call per step", "selector": "learned",
+              "trained": trained,
+              "matrices_per_s": {k: nb / (v["ms"] * 1e-3) for k, v in res.items()},
+              "mean_products_plus_squarings": {k: v["cost"] for k, v in res.items()},
+              "step_tflops": {k: v["tflops"] for k, v in res.items()},
+              "learned_accepted": int(acc), "learned_rejected": int(rej)}
+    return line(args, "expm matrices/s (learned selector, rel err <= 1e-12)", nb / (res["learned"]["ms"] * 1e-3),
+                res["learned"]["ms"], "f64", config, roof, cpu)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="batched", choices=["batched", "single", "precision", "complex"])
+    ap.add_argument("--workload", default="batched", choices=["batched", "single", "precision", "complex", "learned"])
     ap.add_argument("--selector", default="plain", choices=["plain", "alpha"])
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--count", type=int, default=4096)
@@ -249,7 +329,8 @@ def main():
     import torch
     import paper_1710_10989_amd as P
     from paper_1710_10989_amd import workloads as W
-    fn = {"batched": run_batched, "single": run_single, "precision": run_precision, "complex": run_complex}
+    fn = {"batched": run_batched, "single": run_single, "precision": run_precision, "complex": run_complex,
+          "learned": run_learned}
     print(json.dumps(fn[args.workload](args, torch, P, W)), flush=True)
 
 

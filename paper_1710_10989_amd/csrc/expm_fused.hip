@@ -79,13 +79,29 @@ __device__ double block_trace(const double *B, int np, double *red) {
   return r;
 }
 
-// ||B - B^T||_1 of an np x np buffer (thread j owns column j).
+// ||B - B^T||_1 of an np x np buffer (thread j owns column j).  Per block of 16 rows a thread
+// issues 16 coalesced column loads and reads the 16 mirror elements of its own row as eight
+// contiguous 16-byte loads, all before accumulating.
 template <int NT>
 __device__ double block_asym1(const double *B, int np, double *red) {
   const int tid = threadIdx.x;
   double s = 0.0;
-  if (tid < np)
-    for (int i = 0; i < np; ++i) s += fabs(B[i * np + tid] - B[tid * np + i]);
+  if (tid < np) {
+    cgdouble *Bg = gptr(B);
+    for (int i = 0; i < np; i += 16) {
+      double col[16];
+      dv2 row[8];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) col[u] = Bg[(i + u) * np + tid];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) row[u] = *reinterpret_cast<cgdv2 *>(Bg + tid * np + i + 2 * u);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        s += fabs(col[2 * u] - row[u].x);
+        s += fabs(col[2 * u + 1] - row[u].y);
+      }
+    }
+  }
   red[tid] = s;
   __syncthreads();
   for (int w = NT / 2; w > 0; w >>= 1) {
@@ -447,7 +463,7 @@ __device__ void run_one(const FusedArgs &a, int64_t b, double *slot, double *red
 // [split, batch); split = q[2] written by the order kernel (uniform batches: set by the host).
 template <int NW>
 __global__ __launch_bounds__(64 * NW, NW == 4 ? 2 : 1) void expm_fused_kernel(FusedArgs a) {
-  __shared__ double red[64 * NW];
+  __shared__ double red[64 * NW + 16];
   __shared__ int64_t sh_idx;
   const int64_t lo = NW == 8 ? 0 : (a.queue ? (int64_t)a.queue[2] : a.split);
   const int64_t hi = NW == 8 ? (a.queue ? (int64_t)a.queue[2] : a.split) : a.batch;

@@ -28,6 +28,8 @@ namespace expm {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef double dv2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) const dv2 cgdv2;
 typedef short shr4 __attribute__((ext_vector_type(4)));
 
 // Arithmetic of the products: PREC_F64 (v_mfma_f64_16x16x4), PREC_F32 (operands rounded to

@@ -190,8 +190,11 @@ def train(F, epochs=20, lr=2e-3, batch=1024, seed=0, mlp=None, log=None):
 
 def accuracy(mlp, F):
     x = inputs(F, mlp.norm)
-    pred = mlp.logits(x).argmax(dim=1)
-    return float((pred.cpu() == F[:, 11].round().long().cpu()).double().mean())
+    hits = 0
+    for b0 in range(0, x.shape[0], mlp.batch):
+        pred = mlp.logits(x[b0:b0 + mlp.batch].contiguous()).argmax(dim=1)
+        hits += int((pred.cpu() == F[b0:b0 + mlp.batch, 11].round().long().cpu()).sum())
+    return hits / x.shape[0]
 
 
 def install(mlp):
