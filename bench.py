@@ -17,6 +17,8 @@ Other workloads (one JSON line each, selected with --workload):
              `python -m paper_1710_10989_amd.learned train`; its checkpoint is loaded if present)
   complex    512 complex matrices -i H dt (H Hermitian, spectral radius 1, n = 256,
              dt log-uniform in [1e-2, 1e2]) + one dense FP64 n = 8192 with ||A||_1 = 20
+  copy       device-to-device copy of a 1 GiB buffer (the known-size calibration kernel
+             for HBM byte counters; not a matrix-exponential figure)
 
 The JSON line carries matrices/s, the roofline of the dominant kernel (executed flops =
 sum over matrices of (products(m) + s) * 2 n^3 for the real order n the kernels run on,
@@ -109,7 +111,7 @@ def run_batched(args, torch, P, W):
                           "40/20/20/20 dense/skew/nilpotent/diag+rank4; one expm_batched call per step",
               "selector": args.selector,
               "mean_products_plus_squarings": float(np.mean([PRODUCTS[int(a)] + int(b) for a, b in zip(m, s)]))}
-    roof = {"bound": "mfma", "kernel": "expm_fused_kernel<8> (orders 80..128 of the batch)",
+    roof = {"bound": "mfma", "kernel": "expm_resident_kernel<8> (orders 80..128 of the batch)",
             "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64,
             "traffic": None, "kernel_ms": ms_k8, "step_tflops": flops / (ms_step * 1e-3) / 1e12}
     return line(args, "expm matrices/s (rel err <= 1e-12, FP64)", nb / (ms_step * 1e-3), ms_step, "f64", config,
@@ -309,12 +311,33 @@ def run_learned(args, torch, P, W):
                 res["learned"]["ms"], "f64", config, roof, cpu)
 
 
+def run_copy(args, torch, P, W):
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(args.warmup):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(args.steps):
+        dst.copy_(src)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / args.steps
+    return {"metric": "device copy GB/s (calibration)", "value": 2 * nbytes / (ms * 1e-3) / 1e9, "unit": "GB/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "copy of %d bytes (read %d + write %d per launch)" % (nbytes, nbytes, nbytes)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="batched", choices=["batched", "single", "precision", "complex", "learned"])
+    ap.add_argument("--workload", default="batched", choices=["batched", "single", "precision", "complex", "learned",
+                                                             "copy"])
     ap.add_argument("--selector", default="plain", choices=["plain", "alpha"])
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--count", type=int, default=4096)
@@ -330,7 +353,7 @@ def main():
     import paper_1710_10989_amd as P
     from paper_1710_10989_amd import workloads as W
     fn = {"batched": run_batched, "single": run_single, "precision": run_precision, "complex": run_complex,
-          "learned": run_learned}
+          "learned": run_learned, "copy": run_copy}
     print(json.dumps(fn[args.workload](args, torch, P, W)), flush=True)
 
 

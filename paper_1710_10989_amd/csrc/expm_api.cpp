@@ -48,9 +48,9 @@ expm_status_t check_opts(const expm_opts_t *o, double *u) {
   return EXPM_OK;
 }
 
-// Resident workgroups of the two fused kernels on the current device (cached).
+// Resident workgroups per CU of the four sweep kernels on the current device (cached).
 struct FusedCaps {
-  int cus = 0, per4 = 1, per8 = 1;
+  int cus = 0, per4 = 1, per8 = 1, res4 = 1, res8 = 1;
 };
 
 FusedCaps fused_caps() {
@@ -65,6 +65,8 @@ FusedCaps fused_caps() {
       caps.cus = cus;
       caps.per4 = fused_max_blocks_per_cu(4);
       caps.per8 = fused_max_blocks_per_cu(8);
+      caps.res4 = resident_max_blocks_per_cu(4);
+      caps.res8 = resident_max_blocks_per_cu(8);
       init = true;
     } else {
       caps.cus = 0;  // no device visible: size for the largest launch, do not cache
@@ -73,34 +75,44 @@ FusedCaps fused_caps() {
   return caps;
 }
 
-int grid_for(int nw, int64_t batch) {
+enum Kern { K_FUSED4, K_FUSED8, K_RES4, K_RES8 };
+
+int grid_for(Kern k, int64_t batch) {
   FusedCaps c = fused_caps();
-  int cap = c.cus > 0 ? c.cus * (nw == 8 ? c.per8 : c.per4) : kMaxSlots;
+  const int per = k == K_FUSED4 ? c.per4 : k == K_FUSED8 ? c.per8 : k == K_RES4 ? c.res4 : c.res8;
+  int cap = c.cus > 0 ? c.cus * per : kMaxSlots;
   if (cap > kMaxSlots) cap = kMaxSlots;
   return (int)(batch < cap ? batch : cap);
 }
 
 struct FusedLayout {
-  size_t queue_off, order_off, slots8_off, slots4_off, total;
-  size_t slot8_doubles, slot4_doubles;
-  int slots8, slots4;
+  size_t queue_off, order_off, slots8_off, slots4_off, slotsr_off, total;
+  size_t slot8_doubles, slot4_doubles, slotr_doubles;
+  int slots8, slots4, slotsr;
 };
 
-// Separate slot arrays for the two kernels, so their sweeps may also run concurrently.  The
-// 4-wave kernel only sees padded orders up to 16 (kSplitT - 1).
+// Workspace of the fused path.  Separate slot arrays per sweep kernel, so the sweeps may run
+// concurrently: the global-memory kernels (8 buffers per slot; the 8-wave one serves np >= 80,
+// the 4-wave one np <= 64 — the resident kernels cover np <= 128 except for the learned
+// selector's feature rows) and the 8-wave resident kernel (two parked matrices per slot, for
+// np >= 96).
 FusedLayout fused_layout(int64_t n_max, int64_t batch) {
   FusedLayout L;
   const int64_t np = pad16(n_max);
   const int64_t np4 = std::min<int64_t>(np, 16 * (kSplitT - 1));
-  L.slots4 = grid_for(4, batch);
-  L.slots8 = np_max_t(n_max) >= kSplitT ? grid_for(8, batch) : 0;
+  const int64_t tr = std::min<int64_t>(np_max_t(n_max), kResT);
+  L.slots4 = grid_for(K_FUSED4, batch);
+  L.slots8 = np_max_t(n_max) >= kSplitT ? grid_for(K_FUSED8, batch) : 0;
+  L.slotsr = tr >= kResParkT ? grid_for(K_RES8, batch) : 0;
   L.slot8_doubles = (size_t)kFusedBufs * np * np;
   L.slot4_doubles = (size_t)kFusedBufs * np4 * np4;
+  L.slotr_doubles = (size_t)kResParkDoublesPerT * tr;
   L.queue_off = 0;
   L.order_off = kAlign;
   L.slots8_off = L.order_off + align_up(sizeof(int32_t) * (size_t)batch);
   L.slots4_off = L.slots8_off + align_up((size_t)L.slots8 * L.slot8_doubles * sizeof(double));
-  L.total = L.slots4_off + (size_t)L.slots4 * L.slot4_doubles * sizeof(double);
+  L.slotsr_off = L.slots4_off + align_up((size_t)L.slots4 * L.slot4_doubles * sizeof(double));
+  L.total = L.slotsr_off + (size_t)L.slotsr * L.slotr_doubles * sizeof(double);
   return L;
 }
 
@@ -150,8 +162,11 @@ size_t expm_workspace_bytes(int64_t n_max, int64_t batch, const expm_opts_t *opt
   return large_layout(nr, batch).total;
 }
 
-// stage: -1 all phases; 0 sort the batch into the work queue; 1 sweep of the 8-wave kernel;
-// 2 sweep of the 4-wave kernel (stages 1 and 2 need stage 0 first, and are independent).
+// stage: -1 all phases; 0 sort the batch into the work queue; 1 sweep of the 8-wave resident
+// kernel (real orders 80..128); 2 sweeps of every other order (np <= 64 on the 4-wave resident
+// kernel, np 144..256 on the 8-wave global-memory kernel).  Stages 1 and 2 need stage 0 first
+// and are independent of each other.  Feature rows (learned selector) run on the global-memory
+// kernels.
 static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, const int32_t *ns,
                                int64_t batch, int64_t n_uniform, int64_t n_max,
                                const expm_opts_t *opts, double u, int32_t *m_dev, int32_t *s_dev,
@@ -178,31 +193,53 @@ static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, cons
   a.n_uniform = (int)n_uniform;
   a.np_max = (int)pad16(nr_max);
   a.cplx = cplx;
-  a.sel = opts->sel;  // the fused kernels run all three rules
+  a.sel = opts->sel;  // every kernel runs all three rules
   a.select_only = select_only;
   a.features = features;
+  a.lo = 0;
+  a.hi = batch;
   hipStream_t st = (hipStream_t)stream;
-  FusedArgs a8 = a, a4 = a;
-  a8.slots = (double *)(base + L.slots8_off);
-  a8.slot_doubles = L.slot8_doubles;
-  a4.slots = (double *)(base + L.slots4_off);
-  a4.slot_doubles = L.slot4_doubles;
+  FusedArgs f8 = a, f4 = a, r8 = a, r4 = a;
+  f8.slots = (double *)(base + L.slots8_off);
+  f8.slot_doubles = L.slot8_doubles;
+  f4.slots = (double *)(base + L.slots4_off);
+  f4.slot_doubles = L.slot4_doubles;
+  r8.slots = L.slotsr > 0 ? (double *)(base + L.slotsr_off) : nullptr;
+  r8.slot_doubles = L.slotr_doubles;
+  r4.slots = nullptr;
+  r4.slot_doubles = 0;
+  const int tmax = np_max_t(nr_max);
+  auto go = [&](Kern k, FusedArgs &x, int ctr, int lo, int hi) -> bool {
+    x.q_ctr = ctr; x.q_lo = lo; x.q_hi = hi;
+    const int grid = k == K_FUSED8 ? L.slots8 : k == K_FUSED4 ? L.slots4 : k == K_RES8 ? grid_for(K_RES8, batch)
+                                                                                   : grid_for(K_RES4, batch);
+    if (k == K_RES8 && std::min(tmax, kResT) >= kResParkT && grid > L.slotsr) return false;
+    hipError_t e = (k == K_FUSED8 || k == K_FUSED4) ? launch_fused(x, k == K_FUSED8 ? 8 : 4, grid, st)
+                                                    : launch_resident(x, k == K_RES8 ? 8 : 4, grid, st);
+    return e == hipSuccess;
+  };
   if (ns) {
-    a8.order = a4.order = (const int32_t *)(base + L.order_off);
-    a8.queue = a4.queue = (unsigned long long *)(base + L.queue_off);
-    if ((stage == -1 || stage == 0) &&
-        launch_order(ns, batch, cplx, (int32_t *)a8.order, a8.queue, st) != hipSuccess)
+    int32_t *order = (int32_t *)(base + L.order_off);
+    unsigned long long *queue = (unsigned long long *)(base + L.queue_off);
+    f8.order = f4.order = r8.order = r4.order = order;
+    f8.queue = f4.queue = r8.queue = r4.queue = queue;
+    if ((stage == -1 || stage == 0) && launch_order(ns, batch, cplx, order, queue, st) != hipSuccess)
       return EXPM_E_HIP;
-    // largest orders first: the 8-wave kernel drains the front of the queue, then the 4-wave
-    // kernel the rest (either range may be empty)
-    if ((stage == -1 || stage == 1) && L.slots8 > 0 && launch_fused(a8, 8, L.slots8, st) != hipSuccess)
-      return EXPM_E_HIP;
-    if ((stage == -1 || stage == 2) && launch_fused(a4, 4, L.slots4, st) != hipSuccess) return EXPM_E_HIP;
+    if (features) {
+      // global-memory kernels: np >= 80 on 8 waves, the rest on 4 waves
+      if (tmax >= kSplitT && !go(K_FUSED8, f8, 0, 0, 2)) return EXPM_E_HIP;
+      if (!go(K_FUSED4, f4, 3, 2, 3)) return EXPM_E_HIP;
+      return EXPM_OK;
+    }
+    // largest orders first; each sweep drains its own range of the sorted queue
+    if ((stage == -1 || stage == 1) && tmax >= kSplitT && !go(K_RES8, r8, 1, 1, 2)) return EXPM_E_HIP;
+    if ((stage == -1 || stage == 2) && tmax > kResT && !go(K_FUSED8, f8, 0, 0, 1)) return EXPM_E_HIP;
+    if ((stage == -1 || stage == 2) && !go(K_RES4, r4, 2, 2, 3)) return EXPM_E_HIP;
   } else {
-    const bool big = np_max_t(nr_uni) >= kSplitT;
-    a8.split = a4.split = big ? batch : 0;
-    if (big ? launch_fused(a8, 8, L.slots8, st) != hipSuccess : launch_fused(a4, 4, L.slots4, st) != hipSuccess)
-      return EXPM_E_HIP;
+    const int t = np_max_t(nr_uni);
+    const bool ok = t > kResT ? go(K_FUSED8, f8, 0, 0, 0) : t >= kSplitT ? go(K_RES8, r8, 1, 0, 0)
+                                                                         : go(K_RES4, r4, 2, 0, 0);
+    if (!ok) return EXPM_E_HIP;
   }
   return EXPM_OK;
 }

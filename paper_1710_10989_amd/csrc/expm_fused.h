@@ -7,8 +7,20 @@
 
 namespace expm {
 
-// Orders with np / 16 >= kSplitT run on the 8-wave kernel, the rest on the 4-wave kernel.
+// Orders with np / 16 >= kSplitT run on 8-wave workgroups, the rest on 4-wave workgroups.
 constexpr int kSplitT = 5;
+// Largest np / 16 of the resident kernels (np <= 128).
+constexpr int kResT = 8;
+// The 8-wave resident kernel parks up to two matrices in HBM from np / 16 >= kResParkT on;
+// per np / 16 its slot needs 2 regions x 8 waves x 4 x 64 doubles.
+constexpr int kResParkT = 6;
+constexpr int kResParkDoublesPerT = 2 * 8 * 4 * 64;
+
+// Work-queue words written by the order kernel: [0, 4) counters of up to four sweeps;
+// [kQBound, kQBound + 4) range bounds of the sorted order (largest real order first):
+// 0, first entry with np <= 128, first entry with np <= 64, batch.
+constexpr int kQBound = 4;
+constexpr int kQWords = 8;
 
 struct FusedArgs {
   const double *A;        // packed inputs
@@ -16,12 +28,14 @@ struct FusedArgs {
   const int64_t *offs;    // per-matrix element offsets (nullptr: b * n_uniform^2)
   const int32_t *ns;      // per-matrix orders (nullptr: n_uniform)
   const int32_t *order;   // work-queue order (nullptr: identity)
-  unsigned long long *queue;  // [counter 8-wave, counter 4-wave, split]; nullptr: static
+  unsigned long long *queue;  // kQWords words (see below); nullptr: static range [lo, hi)
   int32_t *m_out, *s_out, *status;
   double *slots;          // gridDim.x slots of slot_doubles doubles (per kernel variant)
   size_t slot_doubles;
+  int q_ctr, q_lo, q_hi;  // this sweep's counter word and its range bounds queue[kQBound + q_lo],
+                          // queue[kQBound + q_hi]
+  int64_t lo, hi;         // static range (queue == nullptr)
   int64_t batch;
-  int64_t split;          // used when queue == nullptr
   int n_uniform;
   int np_max;             // largest padded order the slots can hold
   int sel;                // expm_sel_t
@@ -42,6 +56,9 @@ hipError_t learned_counts(unsigned long long out[2]);
 constexpr int kFusedBufs = 8;
 int fused_max_blocks_per_cu(int nw);
 hipError_t launch_fused(const FusedArgs &a, int nw, int grid, hipStream_t st);
+// Resident kernels (np <= 128: 8 waves for np 80..128, 4 waves for np <= 64).
+int resident_max_blocks_per_cu(int nw);
+hipError_t launch_resident(const FusedArgs &a, int nw, int grid, hipStream_t st);
 hipError_t launch_order(const int32_t *ns, int64_t batch, int cplx, int32_t *order,
                         unsigned long long *queue, hipStream_t st);
 

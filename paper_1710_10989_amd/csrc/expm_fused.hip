@@ -459,32 +459,75 @@ __device__ void run_one(const FusedArgs &a, int64_t b, double *slot, double *red
 
 }  // namespace
 
-// Queue ranges: the 8-wave kernel serves queue entries [0, split), the 4-wave kernel
-// [split, batch); split = q[2] written by the order kernel (uniform batches: set by the host).
-template <int NW>
-__global__ __launch_bounds__(64 * NW, NW == 4 ? 2 : 1) void expm_fused_kernel(FusedArgs a) {
-  __shared__ double red[64 * NW + 16];
+// Sweep range and counter of one launch: queue words when the batch is sorted on the device,
+// else the static range.
+struct Sweep {
+  int64_t lo, hi;
+  unsigned long long *ctr;
+};
+__device__ inline Sweep sweep_of(const FusedArgs &a) {
+  Sweep w;
+  if (a.queue) {
+    w.lo = (int64_t)a.queue[kQBound + a.q_lo];
+    w.hi = (int64_t)a.queue[kQBound + a.q_hi];
+    w.ctr = &a.queue[a.q_ctr];
+  } else {
+    w.lo = a.lo;
+    w.hi = a.hi;
+    w.ctr = nullptr;
+  }
+  return w;
+}
+
+// Persistent loop: each workgroup pops the next queue entry of its range until it is empty.
+template <class F>
+__device__ inline void sweep(const FusedArgs &a, const F &run) {
   __shared__ int64_t sh_idx;
-  const int64_t lo = NW == 8 ? 0 : (a.queue ? (int64_t)a.queue[2] : a.split);
-  const int64_t hi = NW == 8 ? (a.queue ? (int64_t)a.queue[2] : a.split) : a.batch;
-  double *slot = a.slots + (size_t)blockIdx.x * a.slot_doubles;
-  for (int64_t it = lo + blockIdx.x;; it += gridDim.x) {
+  const Sweep w = sweep_of(a);
+  for (int64_t it = w.lo + blockIdx.x;; it += gridDim.x) {
     int64_t idx = it;
-    if (a.queue) {
-      if (threadIdx.x == 0) sh_idx = lo + (int64_t)atomicAdd(&a.queue[NW == 8 ? 0 : 1], 1ull);
+    if (w.ctr) {
+      if (threadIdx.x == 0) sh_idx = w.lo + (int64_t)atomicAdd(w.ctr, 1ull);
       __syncthreads();
-      idx = sh_idx;
+      const long long v = sh_idx;
+      idx = (int64_t)(((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(v >> 32)) << 32) |
+                      (unsigned)__builtin_amdgcn_readfirstlane((int)v));
       __syncthreads();
     }
-    if (idx >= hi) break;
-    const int64_t b = a.order ? a.order[idx] : idx;
-    run_one<NW>(a, b, slot, red);
+    if (idx >= w.hi) break;
+    // entry and matrix index are uniform: keep them in scalar registers
+    const int64_t b = a.order ? (int64_t)__builtin_amdgcn_readfirstlane(a.order[idx]) : idx;
+    run(b);
     __syncthreads();
   }
 }
 
+template <int NW>
+__global__ __launch_bounds__(64 * NW, NW == 4 ? 2 : 1) void expm_fused_kernel(FusedArgs a) {
+  __shared__ double red[64 * NW + 16];
+  double *slot = a.slots + (size_t)blockIdx.x * a.slot_doubles;
+  sweep(a, [&](int64_t b) { run_one<NW>(a, b, slot, red); });
+}
+
+}  // namespace expm
+
+#include "resident.h"
+
+namespace expm {
+namespace {
+
+template <int NW>
+__global__ __launch_bounds__(64 * NW, NW == 4 ? 2 : 1) void expm_resident_kernel(FusedArgs a) {
+  __shared__ double red[64 * NW + 16];
+  double *slot = a.slots ? a.slots + (size_t)blockIdx.x * a.slot_doubles : nullptr;
+  res_init<NW>(a);
+  sweep(a, [&](int64_t b) { run_res_dispatch<NW>(a, b, slot, red); });
+}
+
+}  // namespace
+
 // Counting sort of the batch by padded order, largest first (the work-queue order); resets
-// both queue counters and records the split between the two kernels.  One workgroup.
+// the counters and records the range bounds.  One workgroup.
 __global__ void expm_order_kernel(const int32_t *ns, int64_t batch, int cplx, int32_t *order,
                                   unsigned long long *queue) {
   __shared__ int hist[18], start[18];
@@ -501,9 +544,11 @@ __global__ void expm_order_kernel(const int32_t *ns, int64_t batch, int cplx, in
   if (tid == 0) {
     int acc = 0;
     for (int i = 0; i < 18; ++i) { start[i] = acc; acc += hist[i]; }
-    queue[0] = 0ull;
-    queue[1] = 0ull;
-    queue[2] = (unsigned long long)start[16 - kSplitT + 1];  // entries with T >= kSplitT
+    for (int i = 0; i < kQBound; ++i) queue[i] = 0ull;
+    queue[kQBound + 0] = 0ull;
+    queue[kQBound + 1] = (unsigned long long)start[16 - kResT];       // np <= 128
+    queue[kQBound + 2] = (unsigned long long)start[16 - kSplitT + 1];  // np <= 64
+    queue[kQBound + 3] = (unsigned long long)batch;
   }
   __syncthreads();
   for (int64_t b = tid; b < batch; b += blockDim.x) {
@@ -524,6 +569,21 @@ int fused_max_blocks_per_cu(int nw) {
 hipError_t launch_fused(const FusedArgs &a, int nw, int grid, hipStream_t st) {
   if (nw == 8) hipLaunchKernelGGL(expm_fused_kernel<8>, dim3(grid), dim3(512), 0, st, a);
   else hipLaunchKernelGGL(expm_fused_kernel<4>, dim3(grid), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+int resident_max_blocks_per_cu(int nw) {
+  int nb = 0;
+  hipError_t e = nw == 8
+      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, expm_resident_kernel<8>, 512, 0)
+      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, expm_resident_kernel<4>, 256, 0);
+  if (e != hipSuccess) return 1;
+  return nb < 1 ? 1 : nb;
+}
+
+hipError_t launch_resident(const FusedArgs &a, int nw, int grid, hipStream_t st) {
+  if (nw == 8) hipLaunchKernelGGL(expm_resident_kernel<8>, dim3(grid), dim3(512), 0, st, a);
+  else hipLaunchKernelGGL(expm_resident_kernel<4>, dim3(grid), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

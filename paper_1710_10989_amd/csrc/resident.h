@@ -1,0 +1,638 @@
+// On-chip resident evaluation for real orders np <= 128 (np = n rounded up to 16): one
+// workgroup per matrix.  Besides the input and the output, only up to two parked matrices
+// (np >= 96) cross HBM.
+//
+// Data placement.  Wave w owns the column tile w (columns 16 w .. 16 w + 15) of every matrix
+// it holds in registers, as the D layout of the 16x16x4 FP64 MFMA: register r of row tile i
+// of lane l holds M[16 i + 4 r + l / 16][16 w + l % 16].  That layout is exactly the B-operand
+// layout of the same MFMA for rows 4 q .. 4 q + 3 of M (q = 4 i + r), so a product L * R with
+// R held in registers needs no data movement for R: per k step q each lane feeds its own
+// element R(q).  The left operand L is the one matrix resident in LDS (the whole np x np
+// matrix, 128 KiB at np = 128); lane l reads L[16 i + l % 16][4 q + l / 16] for row tile i.
+// Every product of the method has at most one operand that is not at hand in registers
+// (powers of A commute, so each product can be ordered to make that operand L), and the two
+// products whose operands are equal (squarings, A^3 A^3, B_4 B_4) read both from LDS.
+//
+// LDS layout: row stride S (np rounded up to 32 doubles), element (r, c) at
+// r S + (c ^ swz(r)) with swz(r) = (r & 15) | ((r & 1) << 4).  The XOR keeps the three access
+// patterns conflict-free whether the banks repeat every 128 or every 256 bytes: left-operand
+// reads (16 rows x 2 adjacent k per 32 lanes), right-operand reads and D-layout writes (2 rows x
+// 16 adjacent columns per 32 lanes).
+//
+// Included by expm_fused.hip (shares the selection helpers and the learned-selector state).
+#pragma once
+
+namespace expm {
+namespace {
+
+constexpr int kResTMax = 8;  // np <= 128
+
+template <int T>
+struct Res {
+  static constexpr int NP = 16 * T;
+  static constexpr int S = (NP + 31) & ~31;
+};
+
+__shared__ double g_res8[128 * 128];
+__shared__ double g_res4[64 * 64];
+__shared__ double sh_coef[32];
+__shared__ Consts sh_consts;  // copy of the kernel's constants for the out-of-line helpers
+template <int NW>
+__device__ inline double *res_lds() {
+  if constexpr (NW == 4) return g_res4;
+  else return g_res8;
+}
+
+__device__ inline int swz(int r) { return (r & 15) | ((r & 1) << 4); }
+
+// Opaque copy: address arithmetic derived from it is redone at each use instead of being
+// hoisted into registers that stay live across the whole matrix.
+__device__ inline int opq(int x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+// Wave-uniform integer moved to a scalar register: branches on it are then uniform
+// branches, not exec-masked regions that keep both sides' values alive.
+__device__ inline int ufi(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// A wave-uniform double moved to scalar registers (coefficients of the linear combinations).
+__device__ inline double uni(double x) {
+  const long long u = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readfirstlane((int)u);
+  const int hi = __builtin_amdgcn_readfirstlane((int)(u >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Per-lane geometry of the owned column tile.
+struct Lane {
+  int w, lr, lk, col;
+  __device__ Lane() {
+    const int tid = opq(threadIdx.x);  // recomputed per matrix, not held across the sweep
+    w = tid >> 6;
+    const int lane = tid & 63;
+    lr = lane & 15;
+    lk = lane >> 4;
+    col = 16 * w + lr;
+  }
+  __device__ int row(int i, int r) const { return 16 * i + 4 * r + lk; }
+};
+
+// LDS offsets of the lane's own elements: at(i, r) = own element (row 16 i + 4 r + lk, column
+// col); dd marks the diagonal: element (i, r) is on it iff 16 i + 4 r == dd.
+template <int T>
+struct Own {
+  static constexpr int S = Res<T>::S;
+  int b[4];
+  int dd;
+  __device__ explicit Own(const Lane &ln) {
+    const int lk = opq(ln.lk), col = opq(ln.col);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) b[r] = lk * S + (col ^ swz(4 * r + lk));
+    dd = col - lk;
+  }
+  __device__ int at(int i, int r) const { return b[r] + (16 * i + 4 * r) * S; }
+  __device__ double delta(int i, int r) const { return dd == 16 * i + 4 * r ? 1.0 : 0.0; }
+};
+
+template <int T>
+__device__ inline void zero(dbl4 (&x)[T]) {
+#pragma unroll
+  for (int i = 0; i < T; ++i) x[i] = dbl4{0.0, 0.0, 0.0, 0.0};
+}
+
+// Writes the lane's elements of a register matrix into the resident LDS matrix.
+template <int T>
+__device__ inline void to_lds(double *L, const Lane &ln, const dbl4 (&x)[T]) {
+  const Own<T> o(ln);
+#pragma unroll
+  for (int i = 0; i < T; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) L[o.at(i, r)] = x[i][r];
+}
+
+// acc += L * R over the owned column tile: L resident in LDS, R(q) the lane's B operand of k
+// step q (rows 4 q .. 4 q + 3 of R).  The left-operand fragments of step q + 1 are read while
+// step q multiplies; a scheduling barrier per step keeps the compiler from hoisting more
+// steps' reads (which would cost registers the resident matrices need).
+template <int T, class RF>
+__device__ inline void rgemm(const double *L, const Lane &ln, const RF &rf, dbl4 (&acc)[T]) {
+  constexpr int S = Res<T>::S;
+  const int lr = opq(ln.lr), lk = opq(ln.lk);
+  const double *Lrow = L + lr * S;
+  const int sw = swz(lr);  // rows 16 i + lr share the swizzle
+  double a[2][T];
+  auto fetch = [&](int q, double (&dst)[T]) {
+    const int kc = (4 * q + lk) ^ sw;
+#pragma unroll
+    for (int i = 0; i < T; ++i) dst[i] = Lrow[i * 16 * S + kc];
+  };
+  fetch(0, a[0]);
+#pragma unroll
+  for (int q = 0; q < 4 * T; ++q) {
+    if (q + 1 < 4 * T) fetch(q + 1, a[(q + 1) & 1]);
+    const double b = rf(q);
+#pragma unroll
+    for (int i = 0; i < T; ++i) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q & 1][i], b, acc[i], 0, 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// acc += L * R with R held in registers.
+template <int T>
+__device__ inline void rgemm_reg(const double *L, const Lane &ln, const dbl4 (&R)[T], dbl4 (&acc)[T]) {
+  rgemm<T>(L, ln, [&](int q) { return R[q >> 2][q & 3]; }, acc);
+}
+
+// acc += L * L (both operands from the resident matrix; the B operand of k step q is the
+// lane's element of rows 4 q .. 4 q + 3 in its own columns).
+template <int T>
+__device__ inline void rgemm_sq(const double *L, const Lane &ln, dbl4 (&acc)[T]) {
+  constexpr int S = Res<T>::S;
+  const int lk = opq(ln.lk), col = opq(ln.col);
+  int cb[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) cb[r] = lk * S + (col ^ swz(4 * r + lk));
+  rgemm<T>(L, ln, [&](int q) { return L[cb[q & 3] + 4 * q * S]; }, acc);
+}
+
+// Workgroup maximum of a per-lane value (every thread passes one; returns it to all).
+template <int NW>
+__device__ inline double wg_max(double v, double *red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = red[0];
+#pragma unroll
+  for (int k = 1; k < NW; ++k) r = fmax(r, red[k]);
+  __syncthreads();
+  return r;
+}
+
+template <int NW>
+__device__ inline double wg_sum(double v, double *red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = red[0];
+#pragma unroll
+  for (int k = 1; k < NW; ++k) r += red[k];
+  __syncthreads();
+  return r;
+}
+
+// Column sums of |x| over the owned tile, reduced over the 4 row groups of a column; the
+// workgroup maximum is the 1-norm of the register matrix.
+template <int T>
+__device__ inline double col_abs_sum(const dbl4 (&x)[T]) {
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < T; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) s += fabs(x[i][r]);
+  s += __shfl_xor(s, 16);
+  s += __shfl_xor(s, 32);
+  return s;
+}
+
+template <int NW, int T>
+__device__ inline double norm1(const dbl4 (&x)[T], bool act, double *red) {
+  return wg_max<NW>(act ? col_abs_sum<T>(x) : 0.0, red);  // act: compile-time in the callers
+}
+
+// Matrices parked in the workgroup's HBM slot (two regions of NW * T * 64 dbl4 each): lane l
+// of wave w keeps its element (i, r) at ((w T + i) 4 + r) 64 + l of the region, so every
+// access of a wave is 512 contiguous bytes, and each lane reads back only what it wrote.
+template <int NW, int T>
+struct Park {
+  gdouble *s;  // the workgroup's slot (uniform)
+  int base;    // this lane's first element in the region
+  __device__ Park(double *slot, int region) : s(gptr(slot)) {
+    const int tid = opq(threadIdx.x);
+    base = region * (NW * T * 4 * 64) + (tid >> 6) * (T * 4 * 64) + (tid & 63);
+  }
+  __device__ double get(int i, int r) const { return s[base + (i * 4 + r) * 64]; }
+  __device__ void put(int i, int r, double v) const { s[base + (i * 4 + r) * 64] = v; }
+  __device__ void put_all(const dbl4 (&x)[T]) const {
+#pragma unroll
+    for (int i = 0; i < T; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) put(i, r, x[i][r]);
+  }
+  __device__ void get_all(dbl4 (&x)[T]) const {
+#pragma unroll
+    for (int i = 0; i < T; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) x[i][r] = get(i, r);
+  }
+};
+
+// Calls f(i, r, v) for every owned element (i, r), v the element of a matrix held either in
+// registers (X) or, when PARKED, in the slot P.  Parked elements arrive in chunks of 8 with the
+// next chunk in flight; a scheduling barrier per chunk keeps the compiler from issuing every
+// chunk's loads up front (which would need the registers parking saves).
+template <bool PARKED, int NW, int T, class F>
+__device__ inline void each_elem(const Park<NW, T> &P, const dbl4 (&X)[T], const F &f) {
+  if constexpr (!PARKED) {
+#pragma unroll
+    for (int i = 0; i < T; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) f(i, r, X[i][r]);
+  } else {
+    constexpr int NE = 4 * T, CH = 8, NC = (NE + CH - 1) / CH;
+    double buf[2][CH];
+    auto fetch = [&](int g, double (&d)[CH]) {
+#pragma unroll
+      for (int u = 0; u < CH; ++u)
+        if (g * CH + u < NE) d[u] = P.get((g * CH + u) >> 2, (g * CH + u) & 3);
+    };
+    fetch(0, buf[0]);
+#pragma unroll
+    for (int g = 0; g < NC; ++g) {
+      if (g + 1 < NC) fetch(g + 1, buf[(g + 1) & 1]);
+#pragma unroll
+      for (int u = 0; u < CH; ++u)
+        if (g * CH + u < NE) f((g * CH + u) >> 2, (g * CH + u) & 3, buf[g & 1][u]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
+// Scalar selection work runs out of line: it executes once per matrix on one thread, and
+// inlined its math-library code would compete for registers with the register-held matrices.
+__device__ __noinline__ void res_select(const double *theta, int alpha, double n1, double n2, double n3, int *m,
+                                        int *s) {
+  select_ms(theta, alpha, n1, n2, n3, m, s);
+}
+__device__ __noinline__ int res_proposal_ok(const double *theta, double n1, double n2, double n3, int m, int s) {
+  return proposal_ok(theta, n1, n2, n3, m, s) ? 1 : 0;
+}
+__device__ __noinline__ void res_coefs(const Consts *k, int m, int s, double *c) { make_coefs(*k, m, s, c); }
+
+// Copies the kernel's constants to LDS (the helpers above take pointers; a pointer into the
+// kernel argument itself would force a private copy of the whole argument block).
+template <int NW>
+__device__ inline void res_init(const FusedArgs &a) {
+  const double *src = reinterpret_cast<const double *>(&a.k);
+  double *dst = reinterpret_cast<double *>(&sh_consts);
+  for (int e = threadIdx.x; e < (int)(sizeof(Consts) / sizeof(double)); e += 64 * NW) dst[e] = src[e];
+  __syncthreads();
+}
+template <int NT>
+__device__ __noinline__ int res_mlp(double n1, double n2, double tr, double asym, int n) {
+  return mlp_infer<NT>(n1, n2, tr, asym, n);
+}
+
+// Runs the method on matrix b of real order n (np = 16 T) with the resident scheme.  Waves
+// beyond T own no column tile (IDLE): they run the same control flow, barriers and
+// reductions without touching the matrices.  IDLE is a compile-time parameter so that the
+// working waves update their register matrices unconditionally (a run-time guard around an
+// update would keep the old and the new values alive together).
+template <int NW, int T, bool IDLE>
+__device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, int64_t off, double *slot,
+                        double *red) {
+  double *L = res_lds<NW>();
+  const int tid = threadIdx.x;
+  const Lane ln;
+  constexpr bool act = !IDLE;
+  dbl4 X0[T], X1[T], X2[T], AC[T];
+
+  // ---- load A (real form of a complex input) into X0 and LDS; finiteness, 1-norm ----
+  int bad = 0;
+  if constexpr (act) {
+    cgdouble *Ag = gptr(a.A + off);
+    const int lk = opq(ln.lk), c = opq(ln.col);
+#pragma unroll
+    for (int i = 0; i < T; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * i + 4 * r + lk;
+        double x = 0.0;
+        if (row < n && c < n) {
+          if (!cx) {
+            x = Ag[(size_t)row * n + c];
+          } else {
+            const int ri = row < nin ? row : row - nin, ci = c < nin ? c : c - nin;
+            const bool im = (row < nin) != (c < nin);
+            x = Ag[2 * ((size_t)ri * nin + ci) + (im ? 1 : 0)];
+            if (im && row < nin) x = -x;
+          }
+        }
+        X0[i][r] = x;
+      }
+#pragma unroll
+    for (int i = 0; i < T; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) bad |= !isfinite(X0[i][r]);
+    to_lds<T>(L, ln, X0);
+  }
+  bad = ufi(__syncthreads_or(bad));
+  if (bad) {
+    double *E = a.E ? a.E + off : nullptr;
+    if (E) for (int e = tid; e < nin * nin * (cx ? 2 : 1); e += 64 * NW) E[e] = __builtin_nan("");
+    if (tid == 0) {
+      a.m_out[b] = -1; a.s_out[b] = -1;
+      if (a.status) a.status[b] = EXPM_E_NONFINITE;
+    }
+    __syncthreads();
+    return;
+  }
+  const double eta = norm1<NW, T>(X0, act, red);
+
+  if (tid == 0) res_select(sh_consts.theta, 0, eta, -1.0, -1.0, &sh_ms[0], &sh_ms[1]);
+  __syncthreads();
+  const int m_plain = ufi(sh_ms[0]), s_plain = ufi(sh_ms[1]);
+  int m = m_plain, s = s_plain;
+
+  // ---- A^2 (X1), the norms the selector needs, then A^3 (X2) at most once ----
+  if (m_plain >= 2 && !IDLE) {
+    zero<T>(X1);
+    rgemm_reg<T>(L, ln, X0, X1);
+  }
+  double n2 = -1.0, n3 = -1.0;
+  bool need3 = false;
+  int mq = 0, sq = 0;
+  if (a.sel == EXPM_SEL_ALPHA && m_plain >= 2) {
+    n2 = norm1<NW, T>(X1, act, red);
+    need3 = m_plain >= 12;
+  } else if (a.sel == EXPM_SEL_LEARNED && m_plain >= 2) {
+    n2 = norm1<NW, T>(X1, act, red);
+    double tr = 0.0, asy = 0.0;
+    if constexpr (act) {
+      constexpr int S = Res<T>::S;
+      const Own<T> o(ln);
+      const int lk = opq(ln.lk), col = opq(ln.col);
+#pragma unroll
+      for (int i = 0; i < T; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          tr += o.delta(i, r) * X0[i][r];
+          const int row = 16 * i + 4 * r + lk;  // A^T element from the resident A
+          asy += fabs(X0[i][r] - L[col * S + (row ^ swz(col))]);
+        }
+      asy += __shfl_xor(asy, 16);
+      asy += __shfl_xor(asy, 32);
+    }
+    tr = wg_sum<NW>(act ? tr : 0.0, red);
+    asy = wg_max<NW>(act ? asy : 0.0, red);
+    const int cls = ufi(res_mlp<64 * NW>(eta, n2, tr, asy, n));
+    mlp_class_ms(cls, &mq, &sq);
+    if (mq >= 12) {
+      need3 = true;  // the acceptance test uses ||A^3||
+    } else {
+      const bool ok = ufi(res_proposal_ok(sh_consts.theta, eta, n2, -1.0, mq, sq)) != 0;
+      if (ok) { m = mq; s = sq; }
+      if (tid == 0) atomicAdd(&g_learned_counts[ok ? 0 : 1], 1ull);
+      need3 = m >= 12;
+    }
+  } else {
+    need3 = m_plain >= 12;
+  }
+
+  // From here on A is read elementwise only: at np >= 96 on 8 waves it waits in the
+  // workgroup's HBM slot (region 0), so that no phase holds more than two register matrices
+  // besides the accumulator.
+  constexpr bool kPark = NW == 8 && T >= kResParkT;
+  const Park<NW, T> P0(slot, 0), P1(slot, 1);
+  if constexpr (kPark) {
+    if constexpr (act) P0.put_all(X0);
+  }
+
+  if (need3) {
+    if constexpr (act) {
+      zero<T>(X2);
+      rgemm_reg<T>(L, ln, X1, X2);
+    }
+    if (a.sel == EXPM_SEL_ALPHA) {
+      n3 = norm1<NW, T>(X2, act, red);
+      if (tid == 0) res_select(sh_consts.theta, 1, eta, n2, n3, &sh_ms[0], &sh_ms[1]);
+      __syncthreads();
+      m = ufi(sh_ms[0]); s = ufi(sh_ms[1]);
+    } else if (a.sel == EXPM_SEL_LEARNED && mq >= 12) {
+      n3 = norm1<NW, T>(X2, act, red);
+      const bool ok = ufi(res_proposal_ok(sh_consts.theta, eta, n2, n3, mq, sq)) != 0;
+      if (ok) { m = mq; s = sq; }
+      if (tid == 0) atomicAdd(&g_learned_counts[ok ? 0 : 1], 1ull);
+    }
+  } else if (a.sel == EXPM_SEL_ALPHA && m_plain >= 2) {
+    // plain m < 12 implies s = 0 and an alpha choice of m <= 8: A^3 is never needed here
+    if (tid == 0) res_select(sh_consts.theta, 1, eta, n2, -1.0, &sh_ms[0], &sh_ms[1]);
+    __syncthreads();
+    m = ufi(sh_ms[0]); s = ufi(sh_ms[1]);
+  }
+  if (tid == 0) {
+    res_coefs(&sh_consts, m, s, sh_coef);
+    a.m_out[b] = m; a.s_out[b] = s;
+    if (a.status) a.status[b] = EXPM_OK;
+  }
+  __syncthreads();
+  if (a.select_only) return;
+  const double *c = sh_coef;
+
+  // ---- T_m(A / 2^s) into AC.  Products of polynomials in A commute, so each product is
+  // ordered to make the operand that is not at hand in registers the resident one. ----
+  if (m <= 2) {
+    const double c0 = uni(c[0]), c1 = m == 2 ? uni(c[1]) : 0.0;
+    if constexpr (act) {
+      const Own<T> o(ln);
+      each_elem<kPark>(P0, X0, [&](int i, int r, double a1) {
+        AC[i][r] = o.delta(i, r) + c0 * a1 + (m == 2 ? c1 * X1[i][r] : 0.0);
+      });
+    }
+  } else if (m == 4) {
+    // T = I + c0 A + c1 V, V = A^2 W = c2 A^2 + (c3 A + c4 A^2) A^2
+    const double c0 = uni(c[0]), c1 = uni(c[1]), c2 = uni(c[2]), c3 = uni(c[3]), c4 = uni(c[4]);
+    __syncthreads();
+    if constexpr (act) {
+      const Own<T> o(ln);
+      each_elem<kPark>(P0, X0, [&](int i, int r, double a1) { L[o.at(i, r)] = c3 * a1 + c4 * X1[i][r]; });
+    }
+    __syncthreads();
+    if constexpr (act) {
+      zero<T>(AC);
+      rgemm_reg<T>(L, ln, X1, AC);
+      const Own<T> o(ln);
+      each_elem<kPark>(P0, X0, [&](int i, int r, double a1) {
+        AC[i][r] = o.delta(i, r) + c0 * a1 + c1 * (AC[i][r] + c2 * X1[i][r]);
+      });
+    }
+  } else if (m == 8) {
+    // V = W1 A^2 (W1 = c0 A + c1 A^2); A_4 = c2 V; Lm = c3 A^2 + A_4;
+    // Rm = c4 I + c5 A + c6 A^2 + c7 A_4; T = Lm Rm + c8 I + c9 A + c10 A^2   (eq. Algorithm83eA)
+    const double c0 = uni(c[0]), c1 = uni(c[1]), c2 = uni(c[2]), c3 = uni(c[3]), c4 = uni(c[4]),
+                 c5 = uni(c[5]), c6 = uni(c[6]), c7 = uni(c[7]), c8 = uni(c[8]), c9 = uni(c[9]),
+                 c10 = uni(c[10]);
+    __syncthreads();
+    if constexpr (act) {
+      const Own<T> o(ln);
+      each_elem<kPark>(P0, X0, [&](int i, int r, double a1) { L[o.at(i, r)] = c0 * a1 + c1 * X1[i][r]; });
+    }
+    __syncthreads();
+    if constexpr (act) {
+      zero<T>(AC);
+      rgemm_reg<T>(L, ln, X1, AC);
+    }
+    __syncthreads();
+    if constexpr (act) {
+      const Own<T> o(ln);
+      each_elem<kPark>(P0, X0, [&](int i, int r, double a1) {
+        const double d = o.delta(i, r), a2 = X1[i][r], a4 = c2 * AC[i][r];
+        L[o.at(i, r)] = c3 * a2 + a4;
+        X2[i][r] = c4 * d + c5 * a1 + c6 * a2 + c7 * a4;
+        AC[i][r] = c8 * d + c9 * a1 + c10 * a2;
+      });
+    }
+    __syncthreads();
+    if constexpr (act) rgemm_reg<T>(L, ln, X2, AC);
+  } else if (m == 12) {
+    // B_j over (I, A, A^2, A^3); A_6 = B_3 + B_4^2; T = B_1 + (B_2 + A_6) A_6   (eq. poly12)
+    __syncthreads();
+    if constexpr (act) {
+      double k[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) k[j] = uni(c[j]);
+      const Own<T> o(ln);
+      each_elem<kPark>(P0, X0, [&](int i, int r, double a1) {
+        const double d = o.delta(i, r), a2 = X1[i][r], a3 = X2[i][r];
+        L[o.at(i, r)] = k[12] * d + k[13] * a1 + k[14] * a2 + k[15] * a3;  // B_4
+        const double b1 = k[0] * d + k[1] * a1 + k[2] * a2 + k[3] * a3;
+        if constexpr (kPark) P0.put(i, r, b1);
+        else X0[i][r] = b1;
+        X1[i][r] = k[4] * d + k[5] * a1 + k[6] * a2 + k[7] * a3;   // B_2
+        AC[i][r] = k[8] * d + k[9] * a1 + k[10] * a2 + k[11] * a3;  // B_3
+      });
+    }
+    __syncthreads();
+    if constexpr (act) {
+      rgemm_sq<T>(L, ln, AC);  // A_6 = B_3 + B_4 B_4
+#pragma unroll
+      for (int i = 0; i < T; ++i) X1[i] += AC[i];  // Y = B_2 + A_6
+    }
+    __syncthreads();
+    if constexpr (act) to_lds<T>(L, ln, X1);
+    __syncthreads();
+    if constexpr (act) {
+      if constexpr (kPark) P0.get_all(X0);
+      rgemm_reg<T>(L, ln, AC, X0);  // T = B_1 + Y A_6
+#pragma unroll
+      for (int i = 0; i < T; ++i) AC[i] = X0[i];
+    }
+  } else {
+    // m == 18: A^6 = A^3 A^3; B_1 over (I, A, A^2, A^3), B_2..B_5 over (I, A, A^2, A^3, A^6);
+    // A_9 = B_1 B_5 + B_4; T = B_2 + (B_3 + A_9) A_9   (eq. poly.18)
+    __syncthreads();
+    if constexpr (act) to_lds<T>(L, ln, X2);
+    __syncthreads();
+    if constexpr (act) {
+      zero<T>(AC);
+      rgemm_sq<T>(L, ln, AC);  // A^6
+    }
+    __syncthreads();
+    if constexpr (act) {
+      double k[24];
+#pragma unroll
+      for (int j = 0; j < 24; ++j) k[j] = uni(c[j]);
+      const Own<T> o(ln);
+      each_elem<kPark>(P0, X0, [&](int i, int r, double a1) {
+          const double d = o.delta(i, r), a2 = X1[i][r], a3 = L[o.at(i, r)], a6 = AC[i][r];
+          L[o.at(i, r)] = k[0] * d + k[1] * a1 + k[2] * a2 + k[3] * a3;  // B_1
+          const double b2 = k[4] * d + k[5] * a1 + k[6] * a2 + k[7] * a3 + k[8] * a6;
+          const double b3 = k[9] * d + k[10] * a1 + k[11] * a2 + k[12] * a3 + k[13] * a6;
+          if constexpr (kPark) {
+            P0.put(i, r, b2);
+            P1.put(i, r, b3);
+          } else {
+            X2[i][r] = b2;
+            X1[i][r] = b3;
+          }
+          AC[i][r] = k[14] * d + k[15] * a1 + k[16] * a2 + k[17] * a3 + k[18] * a6;  // B_4
+          X0[i][r] = k[19] * d + k[20] * a1 + k[21] * a2 + k[22] * a3 + k[23] * a6;  // B_5
+      });
+    }
+    __syncthreads();
+    if constexpr (act) rgemm_reg<T>(L, ln, X0, AC);  // A_9 = B_1 B_5 + B_4
+    __syncthreads();
+    if constexpr (act) {  // Y = B_3 + A_9 becomes the resident matrix
+      const Own<T> o(ln);
+      each_elem<kPark>(P1, X1, [&](int i, int r, double b3) { L[o.at(i, r)] = b3 + AC[i][r]; });
+    }
+    __syncthreads();
+    if constexpr (act) {
+      if constexpr (kPark) P0.get_all(X0);
+      else {
+#pragma unroll
+        for (int i = 0; i < T; ++i) X0[i] = X2[i];
+      }
+      rgemm_reg<T>(L, ln, AC, X0);  // T = B_2 + Y A_9
+#pragma unroll
+      for (int i = 0; i < T; ++i) AC[i] = X0[i];
+    }
+  }
+
+  // ---- s squarings: the resident matrix is both operands ----
+  for (int q = 0; q < s; ++q) {
+    __syncthreads();
+    if constexpr (act) to_lds<T>(L, ln, AC);
+    __syncthreads();
+    if constexpr (act) {
+      zero<T>(AC);
+      rgemm_sq<T>(L, ln, AC);
+    }
+  }
+
+  // ---- e^A ----
+  if constexpr (act) {
+    gdouble *E = gptr(a.E + off);
+    const int lk = opq(ln.lk), col = opq(ln.col);
+#pragma unroll
+    for (int i = 0; i < T; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) put_dst(E, n, nin, cx, 16 * i + 4 * r + lk, col, AC[i][r]);
+  }
+  __syncthreads();
+}
+
+template <int NW>
+__device__ void run_res_dispatch(const FusedArgs &a, int64_t b, double *slot, double *red) {
+  const int tid = threadIdx.x;
+  const int nin = ufi(a.ns ? a.ns[b] : a.n_uniform);
+  const int cx = a.cplx;
+  const int n = cx ? 2 * nin : nin;
+  const int64_t off = (a.offs ? a.offs[b] : b * (int64_t)nin * nin) * (cx ? 2 : 1);
+  const int t = (n + 15) >> 4;
+  const bool fits = NW == 8 ? (t >= 5 && t <= 8) : (t >= 1 && t <= 4);
+  if (nin < 1 || n > a.np_max || !fits) {  // invalid order, or routed to the wrong variant
+    if (tid == 0) {
+      a.m_out[b] = -1; a.s_out[b] = -1;
+      if (a.status) a.status[b] = (nin < 1 || n > a.np_max) ? EXPM_E_INVALID_ARG : EXPM_E_UNSUPPORTED;
+    }
+    return;
+  }
+  const bool idle = (int)(threadIdx.x >> 6) >= t;  // wave-uniform
+  if constexpr (NW == 8) {
+    switch (t) {
+      case 5: idle ? run_res<8, 5, true>(a, b, n, nin, cx, off, slot, red)
+                   : run_res<8, 5, false>(a, b, n, nin, cx, off, slot, red); break;
+      case 6: idle ? run_res<8, 6, true>(a, b, n, nin, cx, off, slot, red)
+                   : run_res<8, 6, false>(a, b, n, nin, cx, off, slot, red); break;
+      case 7: idle ? run_res<8, 7, true>(a, b, n, nin, cx, off, slot, red)
+                   : run_res<8, 7, false>(a, b, n, nin, cx, off, slot, red); break;
+      default: run_res<8, 8, false>(a, b, n, nin, cx, off, slot, red); break;
+    }
+  } else {
+    switch (t) {
+      case 1: idle ? run_res<4, 1, true>(a, b, n, nin, cx, off, slot, red)
+                   : run_res<4, 1, false>(a, b, n, nin, cx, off, slot, red); break;
+      case 2: idle ? run_res<4, 2, true>(a, b, n, nin, cx, off, slot, red)
+                   : run_res<4, 2, false>(a, b, n, nin, cx, off, slot, red); break;
+      case 3: idle ? run_res<4, 3, true>(a, b, n, nin, cx, off, slot, red)
+                   : run_res<4, 3, false>(a, b, n, nin, cx, off, slot, red); break;
+      default: run_res<4, 4, false>(a, b, n, nin, cx, off, slot, red); break;
+    }
+  }
+}
+
+}  // namespace
+}  // namespace expm
