@@ -36,6 +36,34 @@ import numpy as np
 
 PRODUCTS = {1: 0, 2: 1, 4: 2, 8: 3, 12: 4, 18: 5}
 PEAK_FP64 = 78.6e12
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def sources_sha256():
+    """Digest of the kernel sources (csrc/*.h, *.hip, *.cpp) the library is built from."""
+    import hashlib
+    d = os.path.join(HERE, "paper_1710_10989_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".h", ".hip", ".cpp")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(tag):
+    """HBM bytes per launch of a kernel from its committed PMC summary (FETCH_SIZE and
+    WRITE_SIZE, each scaled by the same counter's reading on a copy of known size), or None
+    when the summary was taken on other kernel sources than the current ones."""
+    path = os.path.join(HERE, "profiles", tag + "_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("sources_sha256") != sources_sha256():
+        return None
+    return d.get("bytes_per_launch")
 
 
 def executed_flops(ms, ss, ns):
@@ -113,7 +141,8 @@ def run_batched(args, torch, P, W):
               "mean_products_plus_squarings": float(np.mean([PRODUCTS[int(a)] + int(b) for a, b in zip(m, s)]))}
     roof = {"bound": "mfma", "kernel": "expm_resident_kernel<8> (orders 80..128 of the batch)",
             "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64,
-            "traffic": None, "kernel_ms": ms_k8, "step_tflops": flops / (ms_step * 1e-3) / 1e12}
+            "traffic": measured_traffic("expm_resident_kernel8_batched_4096_mixed"), "kernel_ms": ms_k8,
+            "step_tflops": flops / (ms_step * 1e-3) / 1e12}
     return line(args, "expm matrices/s (rel err <= 1e-12, FP64)", nb / (ms_step * 1e-3), ms_step, "f64", config,
                 roof, cpu)
 
