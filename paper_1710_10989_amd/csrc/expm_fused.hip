@@ -516,12 +516,12 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 2 : 1) void expm_fused_kernel(Fu
 namespace expm {
 namespace {
 
-template <int NW>
+template <int NW, int SEL>
 __global__ __launch_bounds__(64 * NW, NW == 4 ? 2 : 1) void expm_resident_kernel(FusedArgs a) {
   __shared__ double red[64 * NW + 16];
   double *slot = a.slots ? a.slots + (size_t)blockIdx.x * a.slot_doubles : nullptr;
   res_init<NW>(a);
-  sweep(a, [&](int64_t b) { run_res_dispatch<NW>(a, b, slot, red); });
+  sweep(a, [&](int64_t b) { run_res_dispatch<NW, SEL>(a, b, slot, red); });
 }
 
 }  // namespace
@@ -575,15 +575,27 @@ hipError_t launch_fused(const FusedArgs &a, int nw, int grid, hipStream_t st) {
 int resident_max_blocks_per_cu(int nw) {
   int nb = 0;
   hipError_t e = nw == 8
-      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, expm_resident_kernel<8>, 512, 0)
-      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, expm_resident_kernel<4>, 256, 0);
+      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, expm_resident_kernel<8, EXPM_SEL_PLAIN>, 512, 0)
+      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, expm_resident_kernel<4, EXPM_SEL_PLAIN>, 256, 0);
   if (e != hipSuccess) return 1;
   return nb < 1 ? 1 : nb;
 }
 
 hipError_t launch_resident(const FusedArgs &a, int nw, int grid, hipStream_t st) {
-  if (nw == 8) hipLaunchKernelGGL(expm_resident_kernel<8>, dim3(grid), dim3(512), 0, st, a);
-  else hipLaunchKernelGGL(expm_resident_kernel<4>, dim3(grid), dim3(256), 0, st, a);
+  // every variant of a wave count has the same launch bounds and LDS footprint
+  if (nw == 8) {
+    switch (a.sel) {
+      case EXPM_SEL_ALPHA: hipLaunchKernelGGL((expm_resident_kernel<8, EXPM_SEL_ALPHA>), dim3(grid), dim3(512), 0, st, a); break;
+      case EXPM_SEL_LEARNED: hipLaunchKernelGGL((expm_resident_kernel<8, EXPM_SEL_LEARNED>), dim3(grid), dim3(512), 0, st, a); break;
+      default: hipLaunchKernelGGL((expm_resident_kernel<8, EXPM_SEL_PLAIN>), dim3(grid), dim3(512), 0, st, a); break;
+    }
+  } else {
+    switch (a.sel) {
+      case EXPM_SEL_ALPHA: hipLaunchKernelGGL((expm_resident_kernel<4, EXPM_SEL_ALPHA>), dim3(grid), dim3(256), 0, st, a); break;
+      case EXPM_SEL_LEARNED: hipLaunchKernelGGL((expm_resident_kernel<4, EXPM_SEL_LEARNED>), dim3(grid), dim3(256), 0, st, a); break;
+      default: hipLaunchKernelGGL((expm_resident_kernel<4, EXPM_SEL_PLAIN>), dim3(grid), dim3(256), 0, st, a); break;
+    }
+  }
   return hipGetLastError();
 }
 

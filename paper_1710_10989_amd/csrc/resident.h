@@ -21,6 +21,7 @@
 //
 // Included by expm_fused.hip (shares the selection helpers and the learned-selector state).
 #pragma once
+#include <type_traits>
 
 namespace expm {
 namespace {
@@ -35,7 +36,6 @@ struct Res {
 
 __shared__ double g_res8[128 * 128];
 __shared__ double g_res4[64 * 64];
-__shared__ double sh_coef[32];
 __shared__ Consts sh_consts;  // copy of the kernel's constants for the out-of-line helpers
 template <int NW>
 __device__ inline double *res_lds() {
@@ -262,6 +262,7 @@ __device__ inline void each_elem(const Park<NW, T> &P, const dbl4 (&X)[T], const
 
 // Scalar selection work runs out of line: it executes once per matrix on one thread, and
 // inlined its math-library code would compete for registers with the register-held matrices.
+// The coefficients are cheap and inline.
 __device__ __noinline__ void res_select(const double *theta, int alpha, double n1, double n2, double n3, int *m,
                                         int *s) {
   select_ms(theta, alpha, n1, n2, n3, m, s);
@@ -269,7 +270,6 @@ __device__ __noinline__ void res_select(const double *theta, int alpha, double n
 __device__ __noinline__ int res_proposal_ok(const double *theta, double n1, double n2, double n3, int m, int s) {
   return proposal_ok(theta, n1, n2, n3, m, s) ? 1 : 0;
 }
-__device__ __noinline__ void res_coefs(const Consts *k, int m, int s, double *c) { make_coefs(*k, m, s, c); }
 
 // Copies the kernel's constants to LDS (the helpers above take pointers; a pointer into the
 // kernel argument itself would force a private copy of the whole argument block).
@@ -285,12 +285,14 @@ __device__ __noinline__ int res_mlp(double n1, double n2, double tr, double asym
   return mlp_infer<NT>(n1, n2, tr, asym, n);
 }
 
-// Runs the method on matrix b of real order n (np = 16 T) with the resident scheme.  Waves
+// Runs the method on matrix b of real order n (np = 16 T) with the resident scheme; SEL is the
+// (m, s) rule, a compile-time parameter so that the plain rule's kernel carries none of the
+// other rules' code and registers.  Waves
 // beyond T own no column tile (IDLE): they run the same control flow, barriers and
 // reductions without touching the matrices.  IDLE is a compile-time parameter so that the
 // working waves update their register matrices unconditionally (a run-time guard around an
 // update would keep the old and the new values alive together).
-template <int NW, int T, bool IDLE>
+template <int NW, int SEL, int T, bool IDLE>
 __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, int64_t off, double *slot,
                         double *red) {
   double *L = res_lds<NW>();
@@ -354,10 +356,10 @@ __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, i
   double n2 = -1.0, n3 = -1.0;
   bool need3 = false;
   int mq = 0, sq = 0;
-  if (a.sel == EXPM_SEL_ALPHA && m_plain >= 2) {
+  if (SEL == EXPM_SEL_ALPHA && m_plain >= 2) {
     n2 = norm1<NW, T>(X1, act, red);
     need3 = m_plain >= 12;
-  } else if (a.sel == EXPM_SEL_LEARNED && m_plain >= 2) {
+  } else if (SEL == EXPM_SEL_LEARNED && m_plain >= 2) {
     n2 = norm1<NW, T>(X1, act, red);
     double tr = 0.0, asy = 0.0;
     if constexpr (act) {
@@ -405,36 +407,46 @@ __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, i
       zero<T>(X2);
       rgemm_reg<T>(L, ln, X1, X2);
     }
-    if (a.sel == EXPM_SEL_ALPHA) {
+    if (SEL == EXPM_SEL_ALPHA) {
       n3 = norm1<NW, T>(X2, act, red);
       if (tid == 0) res_select(sh_consts.theta, 1, eta, n2, n3, &sh_ms[0], &sh_ms[1]);
       __syncthreads();
       m = ufi(sh_ms[0]); s = ufi(sh_ms[1]);
-    } else if (a.sel == EXPM_SEL_LEARNED && mq >= 12) {
+    } else if (SEL == EXPM_SEL_LEARNED && mq >= 12) {
       n3 = norm1<NW, T>(X2, act, red);
       const bool ok = ufi(res_proposal_ok(sh_consts.theta, eta, n2, n3, mq, sq)) != 0;
       if (ok) { m = mq; s = sq; }
       if (tid == 0) atomicAdd(&g_learned_counts[ok ? 0 : 1], 1ull);
     }
-  } else if (a.sel == EXPM_SEL_ALPHA && m_plain >= 2) {
+  } else if (SEL == EXPM_SEL_ALPHA && m_plain >= 2) {
     // plain m < 12 implies s = 0 and an alpha choice of m <= 8: A^3 is never needed here
     if (tid == 0) res_select(sh_consts.theta, 1, eta, n2, -1.0, &sh_ms[0], &sh_ms[1]);
     __syncthreads();
     m = ufi(sh_ms[0]); s = ufi(sh_ms[1]);
   }
   if (tid == 0) {
-    res_coefs(&sh_consts, m, s, sh_coef);
     a.m_out[b] = m; a.s_out[b] = s;
     if (a.status) a.status[b] = EXPM_OK;
   }
-  __syncthreads();
-  if (a.select_only) return;
-  const double *c = sh_coef;
+  if (a.select_only) {
+    __syncthreads();
+    return;
+  }
+  // scaled coefficients of degree M, computed by every lane from the constants in LDS and
+  // moved to scalar registers
+  auto coefs = [&](auto deg, double *c, int count) {
+    double t[24];
+    make_coefs(sh_consts, decltype(deg)::value, s, t);
+    for (int j = 0; j < count; ++j) c[j] = uni(t[j]);
+  };
 
   // ---- T_m(A / 2^s) into AC.  Products of polynomials in A commute, so each product is
   // ordered to make the operand that is not at hand in registers the resident one. ----
   if (m <= 2) {
-    const double c0 = uni(c[0]), c1 = m == 2 ? uni(c[1]) : 0.0;
+    double c[2];
+    if (m == 2) coefs(std::integral_constant<int, 2>(), c, 2);
+    else { coefs(std::integral_constant<int, 1>(), c, 1); c[1] = 0.0; }
+    const double c0 = c[0], c1 = c[1];
     if constexpr (act) {
       const Own<T> o(ln);
       each_elem<kPark>(P0, X0, [&](int i, int r, double a1) {
@@ -443,7 +455,9 @@ __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, i
     }
   } else if (m == 4) {
     // T = I + c0 A + c1 V, V = A^2 W = c2 A^2 + (c3 A + c4 A^2) A^2
-    const double c0 = uni(c[0]), c1 = uni(c[1]), c2 = uni(c[2]), c3 = uni(c[3]), c4 = uni(c[4]);
+    double c[5];
+    coefs(std::integral_constant<int, 4>(), c, 5);
+    const double c0 = c[0], c1 = c[1], c2 = c[2], c3 = c[3], c4 = c[4];
     __syncthreads();
     if constexpr (act) {
       const Own<T> o(ln);
@@ -461,9 +475,10 @@ __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, i
   } else if (m == 8) {
     // V = W1 A^2 (W1 = c0 A + c1 A^2); A_4 = c2 V; Lm = c3 A^2 + A_4;
     // Rm = c4 I + c5 A + c6 A^2 + c7 A_4; T = Lm Rm + c8 I + c9 A + c10 A^2   (eq. Algorithm83eA)
-    const double c0 = uni(c[0]), c1 = uni(c[1]), c2 = uni(c[2]), c3 = uni(c[3]), c4 = uni(c[4]),
-                 c5 = uni(c[5]), c6 = uni(c[6]), c7 = uni(c[7]), c8 = uni(c[8]), c9 = uni(c[9]),
-                 c10 = uni(c[10]);
+    double c[11];
+    coefs(std::integral_constant<int, 8>(), c, 11);
+    const double c0 = c[0], c1 = c[1], c2 = c[2], c3 = c[3], c4 = c[4], c5 = c[5], c6 = c[6], c7 = c[7],
+                 c8 = c[8], c9 = c[9], c10 = c[10];
     __syncthreads();
     if constexpr (act) {
       const Own<T> o(ln);
@@ -491,8 +506,7 @@ __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, i
     __syncthreads();
     if constexpr (act) {
       double k[16];
-#pragma unroll
-      for (int j = 0; j < 16; ++j) k[j] = uni(c[j]);
+      coefs(std::integral_constant<int, 12>(), k, 16);
       const Own<T> o(ln);
       each_elem<kPark>(P0, X0, [&](int i, int r, double a1) {
         const double d = o.delta(i, r), a2 = X1[i][r], a3 = X2[i][r];
@@ -532,8 +546,7 @@ __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, i
     __syncthreads();
     if constexpr (act) {
       double k[24];
-#pragma unroll
-      for (int j = 0; j < 24; ++j) k[j] = uni(c[j]);
+      coefs(std::integral_constant<int, 18>(), k, 24);
       const Own<T> o(ln);
       each_elem<kPark>(P0, X0, [&](int i, int r, double a1) {
           const double d = o.delta(i, r), a2 = X1[i][r], a3 = L[o.at(i, r)], a6 = AC[i][r];
@@ -594,7 +607,7 @@ __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, i
   __syncthreads();
 }
 
-template <int NW>
+template <int NW, int SEL>
 __device__ void run_res_dispatch(const FusedArgs &a, int64_t b, double *slot, double *red) {
   const int tid = threadIdx.x;
   const int nin = ufi(a.ns ? a.ns[b] : a.n_uniform);
@@ -613,23 +626,23 @@ __device__ void run_res_dispatch(const FusedArgs &a, int64_t b, double *slot, do
   const bool idle = (int)(threadIdx.x >> 6) >= t;  // wave-uniform
   if constexpr (NW == 8) {
     switch (t) {
-      case 5: idle ? run_res<8, 5, true>(a, b, n, nin, cx, off, slot, red)
-                   : run_res<8, 5, false>(a, b, n, nin, cx, off, slot, red); break;
-      case 6: idle ? run_res<8, 6, true>(a, b, n, nin, cx, off, slot, red)
-                   : run_res<8, 6, false>(a, b, n, nin, cx, off, slot, red); break;
-      case 7: idle ? run_res<8, 7, true>(a, b, n, nin, cx, off, slot, red)
-                   : run_res<8, 7, false>(a, b, n, nin, cx, off, slot, red); break;
-      default: run_res<8, 8, false>(a, b, n, nin, cx, off, slot, red); break;
+      case 5: idle ? run_res<8, SEL, 5, true>(a, b, n, nin, cx, off, slot, red)
+                   : run_res<8, SEL, 5, false>(a, b, n, nin, cx, off, slot, red); break;
+      case 6: idle ? run_res<8, SEL, 6, true>(a, b, n, nin, cx, off, slot, red)
+                   : run_res<8, SEL, 6, false>(a, b, n, nin, cx, off, slot, red); break;
+      case 7: idle ? run_res<8, SEL, 7, true>(a, b, n, nin, cx, off, slot, red)
+                   : run_res<8, SEL, 7, false>(a, b, n, nin, cx, off, slot, red); break;
+      default: run_res<8, SEL, 8, false>(a, b, n, nin, cx, off, slot, red); break;
     }
   } else {
     switch (t) {
-      case 1: idle ? run_res<4, 1, true>(a, b, n, nin, cx, off, slot, red)
-                   : run_res<4, 1, false>(a, b, n, nin, cx, off, slot, red); break;
-      case 2: idle ? run_res<4, 2, true>(a, b, n, nin, cx, off, slot, red)
-                   : run_res<4, 2, false>(a, b, n, nin, cx, off, slot, red); break;
-      case 3: idle ? run_res<4, 3, true>(a, b, n, nin, cx, off, slot, red)
-                   : run_res<4, 3, false>(a, b, n, nin, cx, off, slot, red); break;
-      default: run_res<4, 4, false>(a, b, n, nin, cx, off, slot, red); break;
+      case 1: idle ? run_res<4, SEL, 1, true>(a, b, n, nin, cx, off, slot, red)
+                   : run_res<4, SEL, 1, false>(a, b, n, nin, cx, off, slot, red); break;
+      case 2: idle ? run_res<4, SEL, 2, true>(a, b, n, nin, cx, off, slot, red)
+                   : run_res<4, SEL, 2, false>(a, b, n, nin, cx, off, slot, red); break;
+      case 3: idle ? run_res<4, SEL, 3, true>(a, b, n, nin, cx, off, slot, red)
+                   : run_res<4, SEL, 3, false>(a, b, n, nin, cx, off, slot, red); break;
+      default: run_res<4, SEL, 4, false>(a, b, n, nin, cx, off, slot, red); break;
     }
   }
 }
