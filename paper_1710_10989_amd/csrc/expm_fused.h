@@ -13,7 +13,7 @@ constexpr int kSplitT = 5;
 constexpr int kResT = 8;
 // The 8-wave resident kernel parks up to two matrices in HBM from np / 16 >= kResParkT on;
 // per np / 16 its slot needs 2 regions x 8 waves x 4 x 64 doubles.
-constexpr int kResParkT = 6;
+constexpr int kResParkT = 5;
 constexpr int kResParkDoublesPerT = 2 * 8 * 4 * 64;
 
 // Work-queue words written by the order kernel: [0, 4) counters of up to four sweeps;

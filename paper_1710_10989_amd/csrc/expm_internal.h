@@ -32,15 +32,17 @@ bool make_consts(double u, Consts *out);
 // theta_m(u), host.
 bool theta_of(int m, double u, double *out);
 
-// Smallest s >= 0 with eta / 2^s <= theta (exact comparisons; scaling by 2^s is exact).
+// Smallest s >= 0 with eta / 2^s <= theta (exact: scaling by 2^s is exact).  For eta > theta
+// (both positive, finite, normal) write eta = me 2^ee and theta = mt 2^et with me, mt in
+// [1/2, 1): eta <= theta 2^s iff me / mt <= 2^(et + s - ee), and me / mt lies in (1/2, 2), so
+// s = ee - et when me <= mt and ee - et + 1 otherwise.  Both are read off the bit patterns.
 __host__ __device__ inline int scale_exp(double eta, double theta) {
   if (!(eta > theta)) return 0;
-  int e;
-  (void)frexp(eta / theta, &e);  // eta/theta in [2^(e-1), 2^e)
-  int s = e > 0 ? e : 0;
-  while (s > 0 && eta <= ldexp(theta, s - 1)) --s;
-  while (eta > ldexp(theta, s)) ++s;
-  return s;
+  const unsigned long long be = __builtin_bit_cast(unsigned long long, eta);
+  const unsigned long long bt = __builtin_bit_cast(unsigned long long, theta);
+  const unsigned long long kFrac = (1ull << 52) - 1;
+  const int ee = (int)((be >> 52) & 0x7ff), et = (int)((bt >> 52) & 0x7ff);
+  return ee - et + ((be & kFrac) > (bt & kFrac) ? 1 : 0);
 }
 
 // Norm quantities for the ALPHA rule from ||A||, ||A^2||, ||A^3|| (n2, n3 < 0: not formed,

@@ -45,6 +45,10 @@ __device__ inline double *res_lds() {
 
 __device__ inline int swz(int r) { return (r & 15) | ((r & 1) << 4); }
 
+// Fourth word of a raw (untyped) buffer resource on gfx9-family targets: 32-bit data format.
+constexpr int kBufWord3 = 0x00020000;
+typedef unsigned int u2v __attribute__((ext_vector_type(2)));
+
 // Opaque copy: address arithmetic derived from it is redone at each use instead of being
 // hoisted into registers that stay live across the whole matrix.
 __device__ inline int opq(int x) {
@@ -109,6 +113,16 @@ __device__ inline void to_lds(double *L, const Lane &ln, const dbl4 (&x)[T]) {
   for (int i = 0; i < T; ++i)
 #pragma unroll
     for (int r = 0; r < 4; ++r) L[o.at(i, r)] = x[i][r];
+}
+
+// Reads the lane's elements of the resident LDS matrix into a register matrix.
+template <int T>
+__device__ inline void from_lds(const double *L, const Lane &ln, dbl4 (&x)[T]) {
+  const Own<T> o(ln);
+#pragma unroll
+  for (int i = 0; i < T; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) x[i][r] = L[o.at(i, r)];
 }
 
 // acc += L * R over the owned column tile: L resident in LDS, R(q) the lane's B operand of k
@@ -207,14 +221,42 @@ __device__ inline double norm1(const dbl4 (&x)[T], bool act, double *red) {
 // access of a wave is 512 contiguous bytes, and each lane reads back only what it wrote.
 template <int NW, int T>
 struct Park {
-  gdouble *s;  // the workgroup's slot (uniform)
-  int base;    // this lane's first element in the region
-  __device__ Park(double *slot, int region) : s(gptr(slot)) {
+  // Two addressings, chosen per order by measurement: for np >= 112 a buffer resource over
+  // the region plus this lane's byte offset (each access is one VGPR offset and a constant
+  // scalar offset, so no per-element 64-bit addresses are formed or kept: the register
+  // budget is tightest there); below, plain global addressing.
+  static constexpr bool kBuf = T >= 7;
+  __amdgpu_buffer_rsrc_t rs;
+  gdouble *s;
+  int base;  // element offset (global form) or byte offset (buffer form) of this lane
+  __device__ Park(double *slot, int region) {
+    constexpr int kRegion = NW * T * 4 * 64;  // doubles
     const int tid = opq(threadIdx.x);
-    base = region * (NW * T * 4 * 64) + (tid >> 6) * (T * 4 * 64) + (tid & 63);
+    const int lane_off = (tid >> 6) * (T * 4 * 64) + (tid & 63);
+    if constexpr (kBuf) {
+      rs = __builtin_amdgcn_make_buffer_rsrc(slot + (size_t)region * kRegion, 0, kRegion * 8, kBufWord3);
+      base = lane_off * 8;
+    } else {
+      s = gptr(slot);
+      base = region * kRegion + lane_off;
+    }
   }
-  __device__ double get(int i, int r) const { return s[base + (i * 4 + r) * 64]; }
-  __device__ void put(int i, int r, double v) const { s[base + (i * 4 + r) * 64] = v; }
+  __device__ double get(int i, int r) const {
+    if constexpr (kBuf) {
+      const u2v v = __builtin_amdgcn_raw_buffer_load_b64(rs, base, (i * 4 + r) * 512, 0);
+      return __longlong_as_double((long long)(((unsigned long long)v[1] << 32) | v[0]));
+    } else {
+      return s[base + (i * 4 + r) * 64];
+    }
+  }
+  __device__ void put(int i, int r, double x) const {
+    if constexpr (kBuf) {
+      const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+      __builtin_amdgcn_raw_buffer_store_b64(u2v{(unsigned)u, (unsigned)(u >> 32)}, rs, base, (i * 4 + r) * 512, 0);
+    } else {
+      s[base + (i * 4 + r) * 64] = x;
+    }
+  }
   __device__ void put_all(const dbl4 (&x)[T]) const {
 #pragma unroll
     for (int i = 0; i < T; ++i)
@@ -260,9 +302,9 @@ __device__ inline void each_elem(const Park<NW, T> &P, const dbl4 (&X)[T], const
   }
 }
 
-// Scalar selection work runs out of line: it executes once per matrix on one thread, and
-// inlined its math-library code would compete for registers with the register-held matrices.
-// The coefficients are cheap and inline.
+// The alpha rule's selection work runs out of line: it executes once per matrix on one
+// thread, and inlined its math-library code (roots, powers) would compete for registers with
+// the register-held matrices.  The plain rule and the coefficients are cheap and inline.
 __device__ __noinline__ void res_select(const double *theta, int alpha, double n1, double n2, double n3, int *m,
                                         int *s) {
   select_ms(theta, alpha, n1, n2, n3, m, s);
@@ -301,34 +343,51 @@ __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, i
   constexpr bool act = !IDLE;
   dbl4 X0[T], X1[T], X2[T], AC[T];
 
-  // ---- load A (real form of a complex input) into X0 and LDS; finiteness, 1-norm ----
+  // ---- load A (real form of a complex input) into LDS; finiteness, 1-norm.  No register
+  // copy of A lives across the selection (a call); X0 is read back from LDS afterwards. ----
   int bad = 0;
+  double csum = 0.0;
   if constexpr (act) {
     cgdouble *Ag = gptr(a.A + off);
     const int lk = opq(ln.lk), c = opq(ln.col);
+    // every lane loads (indices clamped into the matrix) and zeroes what lies outside, so the
+    // loads are issued back to back instead of one masked branch at a time
+    const bool cin = c < n;
+    const int cc = cin ? c : n - 1;
+    const int ci = cc < nin ? cc : cc - nin;
 #pragma unroll
     for (int i = 0; i < T; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = 16 * i + 4 * r + lk;
-        double x = 0.0;
-        if (row < n && c < n) {
-          if (!cx) {
-            x = Ag[(size_t)row * n + c];
-          } else {
-            const int ri = row < nin ? row : row - nin, ci = c < nin ? c : c - nin;
-            const bool im = (row < nin) != (c < nin);
-            x = Ag[2 * ((size_t)ri * nin + ci) + (im ? 1 : 0)];
-            if (im && row < nin) x = -x;
-          }
+        const int rr = row < n ? row : n - 1;
+        if (!cx) {
+          X0[i][r] = Ag[(size_t)rr * n + cc];
+        } else {
+          const int ri = rr < nin ? rr : rr - nin;
+          const bool im = (rr < nin) != (cc < nin);
+          X0[i][r] = Ag[2 * ((size_t)ri * nin + ci) + (im ? 1 : 0)];
         }
-        X0[i][r] = x;
       }
 #pragma unroll
     for (int i = 0; i < T; ++i)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) bad |= !isfinite(X0[i][r]);
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * i + 4 * r + lk;
+        double x = X0[i][r];
+        if (cx && (row < nin) && !(cc < nin)) x = -x;  // -Y block of the real form
+        X0[i][r] = (row < n && cin) ? x : 0.0;
+      }
+#pragma unroll
+    for (int i = 0; i < T; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        bad |= !isfinite(X0[i][r]);
+        csum += fabs(X0[i][r]);
+      }
     to_lds<T>(L, ln, X0);
+    csum += __shfl_xor(csum, 16);
+    csum += __shfl_xor(csum, 32);
   }
   bad = ufi(__syncthreads_or(bad));
   if (bad) {
@@ -341,12 +400,15 @@ __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, i
     __syncthreads();
     return;
   }
-  const double eta = norm1<NW, T>(X0, act, red);
+  const double eta = wg_max<NW>(csum, red);
 
-  if (tid == 0) res_select(sh_consts.theta, 0, eta, -1.0, -1.0, &sh_ms[0], &sh_ms[1]);
-  __syncthreads();
-  const int m_plain = ufi(sh_ms[0]), s_plain = ufi(sh_ms[1]);
+  // plain rule, evaluated by every lane on the (uniform) norm: integer work on bit patterns
+  int m_plain, s_plain;
+  select_ms(sh_consts.theta, 0, eta, -1.0, -1.0, &m_plain, &s_plain);
+  m_plain = ufi(m_plain);
+  s_plain = ufi(s_plain);
   int m = m_plain, s = s_plain;
+  if constexpr (act) from_lds<T>(L, ln, X0);
 
   // ---- A^2 (X1), the norms the selector needs, then A^3 (X2) at most once ----
   if (m_plain >= 2 && !IDLE) {
@@ -441,27 +503,29 @@ __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, i
   };
 
   // ---- T_m(A / 2^s) into AC.  Products of polynomials in A commute, so each product is
-  // ordered to make the operand that is not at hand in registers the resident one. ----
+  // ordered to make the operand that is not at hand in registers the resident one.  Every
+  // elementwise pass writes its results in place of inputs that die with it, so no pass
+  // holds more register matrices than the product that follows it. ----
   if (m <= 2) {
     double c[2];
     if (m == 2) coefs(std::integral_constant<int, 2>(), c, 2);
     else { coefs(std::integral_constant<int, 1>(), c, 1); c[1] = 0.0; }
-    const double c0 = c[0], c1 = c[1];
     if constexpr (act) {
       const Own<T> o(ln);
       each_elem<kPark>(P0, X0, [&](int i, int r, double a1) {
-        AC[i][r] = o.delta(i, r) + c0 * a1 + (m == 2 ? c1 * X1[i][r] : 0.0);
+        X1[i][r] = o.delta(i, r) + c[0] * a1 + (m == 2 ? c[1] * X1[i][r] : 0.0);
       });
+#pragma unroll
+      for (int i = 0; i < T; ++i) AC[i] = X1[i];
     }
   } else if (m == 4) {
-    // T = I + c0 A + c1 V, V = A^2 W = c2 A^2 + (c3 A + c4 A^2) A^2
+    // T = I + c0 A + c1 V, V = A^2 W = (c3 A + c4 A^2) A^2 + c2 A^2
     double c[5];
     coefs(std::integral_constant<int, 4>(), c, 5);
-    const double c0 = c[0], c1 = c[1], c2 = c[2], c3 = c[3], c4 = c[4];
     __syncthreads();
     if constexpr (act) {
       const Own<T> o(ln);
-      each_elem<kPark>(P0, X0, [&](int i, int r, double a1) { L[o.at(i, r)] = c3 * a1 + c4 * X1[i][r]; });
+      each_elem<kPark>(P0, X0, [&](int i, int r, double a1) { L[o.at(i, r)] = c[3] * a1 + c[4] * X1[i][r]; });
     }
     __syncthreads();
     if constexpr (act) {
@@ -469,7 +533,7 @@ __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, i
       rgemm_reg<T>(L, ln, X1, AC);
       const Own<T> o(ln);
       each_elem<kPark>(P0, X0, [&](int i, int r, double a1) {
-        AC[i][r] = o.delta(i, r) + c0 * a1 + c1 * (AC[i][r] + c2 * X1[i][r]);
+        AC[i][r] = o.delta(i, r) + c[0] * a1 + c[1] * (AC[i][r] + c[2] * X1[i][r]);
       });
     }
   } else if (m == 8) {
@@ -477,36 +541,34 @@ __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, i
     // Rm = c4 I + c5 A + c6 A^2 + c7 A_4; T = Lm Rm + c8 I + c9 A + c10 A^2   (eq. Algorithm83eA)
     double c[11];
     coefs(std::integral_constant<int, 8>(), c, 11);
-    const double c0 = c[0], c1 = c[1], c2 = c[2], c3 = c[3], c4 = c[4], c5 = c[5], c6 = c[6], c7 = c[7],
-                 c8 = c[8], c9 = c[9], c10 = c[10];
     __syncthreads();
     if constexpr (act) {
       const Own<T> o(ln);
-      each_elem<kPark>(P0, X0, [&](int i, int r, double a1) { L[o.at(i, r)] = c0 * a1 + c1 * X1[i][r]; });
+      each_elem<kPark>(P0, X0, [&](int i, int r, double a1) { L[o.at(i, r)] = c[0] * a1 + c[1] * X1[i][r]; });
     }
     __syncthreads();
     if constexpr (act) {
       zero<T>(AC);
-      rgemm_reg<T>(L, ln, X1, AC);
+      rgemm_reg<T>(L, ln, X1, AC);  // V
     }
     __syncthreads();
     if constexpr (act) {
       const Own<T> o(ln);
       each_elem<kPark>(P0, X0, [&](int i, int r, double a1) {
-        const double d = o.delta(i, r), a2 = X1[i][r], a4 = c2 * AC[i][r];
-        L[o.at(i, r)] = c3 * a2 + a4;
-        X2[i][r] = c4 * d + c5 * a1 + c6 * a2 + c7 * a4;
-        AC[i][r] = c8 * d + c9 * a1 + c10 * a2;
+        const double d = o.delta(i, r), a2 = X1[i][r], a4 = c[2] * AC[i][r];
+        L[o.at(i, r)] = c[3] * a2 + a4;                                 // Lm
+        X1[i][r] = c[4] * d + c[5] * a1 + c[6] * a2 + c[7] * a4;         // Rm
+        AC[i][r] = c[8] * d + c[9] * a1 + c[10] * a2;
       });
     }
     __syncthreads();
-    if constexpr (act) rgemm_reg<T>(L, ln, X2, AC);
+    if constexpr (act) rgemm_reg<T>(L, ln, X1, AC);
   } else if (m == 12) {
     // B_j over (I, A, A^2, A^3); A_6 = B_3 + B_4^2; T = B_1 + (B_2 + A_6) A_6   (eq. poly12)
+    double k[16];
+    coefs(std::integral_constant<int, 12>(), k, 16);
     __syncthreads();
     if constexpr (act) {
-      double k[16];
-      coefs(std::integral_constant<int, 12>(), k, 16);
       const Own<T> o(ln);
       each_elem<kPark>(P0, X0, [&](int i, int r, double a1) {
         const double d = o.delta(i, r), a2 = X1[i][r], a3 = X2[i][r];
@@ -515,27 +577,35 @@ __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, i
         if constexpr (kPark) P0.put(i, r, b1);
         else X0[i][r] = b1;
         X1[i][r] = k[4] * d + k[5] * a1 + k[6] * a2 + k[7] * a3;   // B_2
-        AC[i][r] = k[8] * d + k[9] * a1 + k[10] * a2 + k[11] * a3;  // B_3
+        X2[i][r] = k[8] * d + k[9] * a1 + k[10] * a2 + k[11] * a3;  // B_3
       });
     }
     __syncthreads();
     if constexpr (act) {
-      rgemm_sq<T>(L, ln, AC);  // A_6 = B_3 + B_4 B_4
+      rgemm_sq<T>(L, ln, X2);  // A_6 = B_3 + B_4 B_4
 #pragma unroll
-      for (int i = 0; i < T; ++i) X1[i] += AC[i];  // Y = B_2 + A_6
+      for (int i = 0; i < T; ++i) X1[i] += X2[i];  // Y = B_2 + A_6
     }
     __syncthreads();
-    if constexpr (act) to_lds<T>(L, ln, X1);
+    if constexpr (act) {
+      to_lds<T>(L, ln, X1);
+      if constexpr (kPark) P0.get_all(X1);  // B_1
+      else {
+#pragma unroll
+        for (int i = 0; i < T; ++i) X1[i] = X0[i];
+      }
+    }
     __syncthreads();
     if constexpr (act) {
-      if constexpr (kPark) P0.get_all(X0);
-      rgemm_reg<T>(L, ln, AC, X0);  // T = B_1 + Y A_6
+      rgemm_reg<T>(L, ln, X2, X1);  // T = B_1 + Y A_6
 #pragma unroll
-      for (int i = 0; i < T; ++i) AC[i] = X0[i];
+      for (int i = 0; i < T; ++i) AC[i] = X1[i];
     }
   } else {
     // m == 18: A^6 = A^3 A^3; B_1 over (I, A, A^2, A^3), B_2..B_5 over (I, A, A^2, A^3, A^6);
     // A_9 = B_1 B_5 + B_4; T = B_2 + (B_3 + A_9) A_9   (eq. poly.18)
+    double k[24];
+    coefs(std::integral_constant<int, 18>(), k, 24);
     __syncthreads();
     if constexpr (act) to_lds<T>(L, ln, X2);
     __syncthreads();
@@ -545,42 +615,42 @@ __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, i
     }
     __syncthreads();
     if constexpr (act) {
-      double k[24];
-      coefs(std::integral_constant<int, 18>(), k, 24);
       const Own<T> o(ln);
       each_elem<kPark>(P0, X0, [&](int i, int r, double a1) {
-          const double d = o.delta(i, r), a2 = X1[i][r], a3 = L[o.at(i, r)], a6 = AC[i][r];
-          L[o.at(i, r)] = k[0] * d + k[1] * a1 + k[2] * a2 + k[3] * a3;  // B_1
-          const double b2 = k[4] * d + k[5] * a1 + k[6] * a2 + k[7] * a3 + k[8] * a6;
-          const double b3 = k[9] * d + k[10] * a1 + k[11] * a2 + k[12] * a3 + k[13] * a6;
-          if constexpr (kPark) {
-            P0.put(i, r, b2);
-            P1.put(i, r, b3);
-          } else {
-            X2[i][r] = b2;
-            X1[i][r] = b3;
-          }
-          AC[i][r] = k[14] * d + k[15] * a1 + k[16] * a2 + k[17] * a3 + k[18] * a6;  // B_4
-          X0[i][r] = k[19] * d + k[20] * a1 + k[21] * a2 + k[22] * a3 + k[23] * a6;  // B_5
+        const double d = o.delta(i, r), a2 = X1[i][r], a3 = L[o.at(i, r)], a6 = AC[i][r];
+        L[o.at(i, r)] = k[0] * d + k[1] * a1 + k[2] * a2 + k[3] * a3;  // B_1
+        const double b2 = k[4] * d + k[5] * a1 + k[6] * a2 + k[7] * a3 + k[8] * a6;
+        const double b3 = k[9] * d + k[10] * a1 + k[11] * a2 + k[12] * a3 + k[13] * a6;
+        if constexpr (kPark) {
+          P0.put(i, r, b2);
+          P1.put(i, r, b3);
+        } else {
+          X0[i][r] = b2;
+          X2[i][r] = b3;
+        }
+        AC[i][r] = k[14] * d + k[15] * a1 + k[16] * a2 + k[17] * a3 + k[18] * a6;  // B_4
+        X1[i][r] = k[19] * d + k[20] * a1 + k[21] * a2 + k[22] * a3 + k[23] * a6;  // B_5
       });
     }
     __syncthreads();
-    if constexpr (act) rgemm_reg<T>(L, ln, X0, AC);  // A_9 = B_1 B_5 + B_4
+    if constexpr (act) {
+      rgemm_reg<T>(L, ln, X1, AC);  // A_9 = B_1 B_5 + B_4
+      if constexpr (kPark) P0.get_all(X1);  // B_2, in flight while Y is formed
+      else {
+#pragma unroll
+        for (int i = 0; i < T; ++i) X1[i] = X0[i];
+      }
+    }
     __syncthreads();
     if constexpr (act) {  // Y = B_3 + A_9 becomes the resident matrix
       const Own<T> o(ln);
-      each_elem<kPark>(P1, X1, [&](int i, int r, double b3) { L[o.at(i, r)] = b3 + AC[i][r]; });
+      each_elem<kPark>(P1, X2, [&](int i, int r, double b3) { L[o.at(i, r)] = b3 + AC[i][r]; });
     }
     __syncthreads();
     if constexpr (act) {
-      if constexpr (kPark) P0.get_all(X0);
-      else {
+      rgemm_reg<T>(L, ln, AC, X1);  // T = B_2 + Y A_9
 #pragma unroll
-        for (int i = 0; i < T; ++i) X0[i] = X2[i];
-      }
-      rgemm_reg<T>(L, ln, AC, X0);  // T = B_2 + Y A_9
-#pragma unroll
-      for (int i = 0; i < T; ++i) AC[i] = X0[i];
+      for (int i = 0; i < T; ++i) AC[i] = X1[i];
     }
   }
 
