@@ -130,12 +130,13 @@ EXPM_API expm_status_t expm_batched(const void *A_dev, void *E_dev, const int64_
                            int32_t *status_dev, void *ws_dev, size_t ws_bytes, void *stream);
 
 /* expm_batched in three phases, for callers that time or overlap them: stage 0 sorts the
- * batch into the device work queue (largest real order first); stage 1 runs the 8-wave kernel
- * over the orders 80..256 of the queue; stage 2 runs the 4-wave kernel over the orders up to
- * 64.  Stages 1 and 2 need stage 0 to have completed and are independent of each other (they
- * use separate workspace slots, so they may run on two streams).  Calling 0, 1, 2 in order on
- * one stream is exactly expm_batched.  Arguments as expm_batched; stage outside 0..2 is
- * EXPM_E_INVALID_ARG. */
+ * batch into the device work queue (largest real order first); stage 1 runs the 8-wave
+ * on-chip kernel over the real orders 80..128 of the queue; stage 2 runs the sweeps of every
+ * other order (up to 64 on 4 waves, 144..256 on the 8-wave global-memory kernel).  Stages 1
+ * and 2 need stage 0 to have completed and are independent of each other (they use separate
+ * workspace slots and queue counters, so they may run on two streams).  Calling 0, 1, 2 in
+ * order on one stream is exactly expm_batched.  Arguments as expm_batched; stage outside
+ * 0..2 is EXPM_E_INVALID_ARG. */
 EXPM_API expm_status_t expm_batched_stage(const void *A_dev, void *E_dev, const int64_t *offsets_dev,
                                  const int32_t *n_dev, int64_t batch, int64_t n_max,
                                  const expm_opts_t *opts, int32_t *m_dev, int32_t *s_dev,
