@@ -3,9 +3,10 @@
 Default workload (batched): 4096 FP64 matrices of uneven order n in {16, 32, 48, 64, 96, 128},
 ||A||_1 log-uniform in [1e-3, 1e2], structure mix 40 % dense Gaussian / 20 % skew-symmetric /
 20 % strictly upper triangular / 20 % diagonal + rank 4 (seeded, synthetic).  One step = one
-expm_batched call on the whole batch (device work-queue ordering + the persistent fused
+expm_batched call on the whole batch (device work-queue ordering + the persistent resident
 kernels: norm, (m, s) selection, product-reduced Taylor polynomial, squarings), inputs
-already resident in HBM.
+already resident in HBM.  The dominant kernel (orders 112..128) is then timed alone, phase by
+phase, for its roofline.
 
 Other workloads (one JSON line each, selected with --workload):
   single     one 64 x 64 FP64 matrix, ||A||_1 = 2 (latency-bound; repeated expm_taylor calls)
@@ -104,33 +105,38 @@ def run_batched(args, torch, P, W):
             torch.empty(nb, dtype=torch.int32, device="cuda"), torch.empty(nb, dtype=torch.int32, device="cuda"))
     stream = torch.cuda.current_stream()
 
-    def step(ev=None):
-        # one step = expm_batched in its three phases on the current stream; the events bracket
-        # the 8-wave kernel (orders 80..128), the dominant kernel of this workload
+    def step():
+        # one step = one expm_batched call on the whole batch
+        P.batched(B, selector=args.selector, workspace=ws, outs=outs)
+
+    def staged(ev):
+        # the same work in its three phases on one stream, events bracketing phase 1: the 8-wave
+        # resident kernel (orders 112..128), the dominant kernel of this workload, run alone
         P.batched(B, selector=args.selector, workspace=ws, outs=outs, stage=0)
-        if ev is not None:
-            ev[0].record(stream)
+        ev[0].record(stream)
         P.batched(B, selector=args.selector, workspace=ws, outs=outs, stage=1)
-        if ev is not None:
-            ev[1].record(stream)
+        ev[1].record(stream)
         P.batched(B, selector=args.selector, workspace=ws, outs=outs, stage=2)
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    kev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0.record(stream)
     for i in range(args.steps):
-        step(kev[i])
+        step()
     t1.record(stream)
     torch.cuda.synchronize()
     ms_step = t0.elapsed_time(t1) / args.steps
+    kev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for i in range(args.steps):
+        staged(kev[i])
+    torch.cuda.synchronize()
     ms_k8 = sum(a.elapsed_time(b) for a, b in kev) / args.steps
     _, m, s, st = (x.cpu().numpy() for x in outs)
     assert np.all(st == 0), "non-ok status in the batch"
     ns = np.array([a.shape[0] for a in mats], dtype=np.float64)
-    big = ((ns + 15) // 16) >= 5  # real orders handled by the 8-wave kernel
+    big = ((ns + 15) // 16) >= 7  # real orders handled by the 8-wave resident kernel (112..128)
     flops = executed_flops(m, s, ns)
     flops_k8 = executed_flops(m[big], s[big], ns[big])
     achieved = flops_k8 / (ms_k8 * 1e-3)
@@ -139,9 +145,11 @@ def run_batched(args, torch, P, W):
                           "40/20/20/20 dense/skew/nilpotent/diag+rank4; one expm_batched call per step",
               "selector": args.selector,
               "mean_products_plus_squarings": float(np.mean([PRODUCTS[int(a)] + int(b) for a, b in zip(m, s)]))}
-    roof = {"bound": "mfma", "kernel": "expm_resident_kernel<8> (orders 80..128 of the batch)",
+    roof = {"bound": "mfma", "kernel": "expm_resident_kernel<8> (orders 112..128 of the batch)",
             "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64,
             "traffic": measured_traffic("expm_resident_kernel8_batched_4096_mixed"), "kernel_ms": ms_k8,
+            "kernel_timing": "HIP events around the kernel's phase, run alone (expm_batched_stage 1), "
+                             "%d steps right after the timed region" % args.steps,
             "step_tflops": flops / (ms_step * 1e-3) / 1e12}
     return line(args, "expm matrices/s (rel err <= 1e-12, FP64)", nb / (ms_step * 1e-3), ms_step, "f64", config,
                 roof, cpu)
@@ -309,24 +317,26 @@ def run_learned(args, torch, P, W):
     acc //= max(1, args.steps)
     rej //= max(1, args.steps)
     nsh = ns.cpu().numpy()
-    # dominant kernel of the learned run: time the 8-wave phase with events
+    # dominant kernel of the learned run (order 256 on the 8-wave global-memory kernel): time
+    # its phase alone with events
     kev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     for i in range(args.steps):
         P.batched(B, selector="learned", workspace=ws, outs=outs, stage=0)
         kev[i][0].record()
-        P.batched(B, selector="learned", workspace=ws, outs=outs, stage=1)
+        P.batched(B, selector="learned", workspace=ws, outs=outs, stage=3)
         kev[i][1].record()
-        P.batched(B, selector="learned", workspace=ws, outs=outs, stage=2)
+        for stg in (1, 4, 5):
+            P.batched(B, selector="learned", workspace=ws, outs=outs, stage=stg)
     torch.cuda.synchronize()
     ms_k8 = sum(a.elapsed_time(b) for a, b in kev) / args.steps
-    big = ((nsh + 15) // 16) >= 5
+    big = ((nsh + 15) // 16) > 8
     ml, sl = res["learned"]["m"], res["learned"]["s"]
     achieved = executed_flops(ml[big], sl[big], nsh[big]) / (ms_k8 * 1e-3)
     cpu = None
     if not args.no_cpu:
         sample = [stacks[i % 4][i].cpu().numpy() for i in range(16)]
         cpu = cpu_oracle(sample, args.cpu_seconds, "16 of the held-out matrices (4 per order)")
-    roof = {"bound": "mfma", "kernel": "expm_fused_kernel<8> (orders 80..256, learned selector)",
+    roof = {"bound": "mfma", "kernel": "expm_fused_kernel<8> (orders 144..256, learned selector)",
             "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64,
             "traffic": None, "kernel_ms": ms_k8}
     config = {"workload": "20000 held-out FP64 matrices, n in {32,64,128,256} (5000 each), ||A||_1 log-U[1e-2,1e3], "

@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
 
 #include "expm_fused.h"
@@ -50,7 +51,7 @@ expm_status_t check_opts(const expm_opts_t *o, double *u) {
 
 // Resident workgroups per CU of the four sweep kernels on the current device (cached).
 struct FusedCaps {
-  int cus = 0, per4 = 1, per8 = 1, res4 = 1, res8 = 1;
+  int cus = 0, per4 = 1, per8 = 1, res4 = 1, res6 = 1, res8 = 1;
 };
 
 FusedCaps fused_caps() {
@@ -66,6 +67,7 @@ FusedCaps fused_caps() {
       caps.per4 = fused_max_blocks_per_cu(4);
       caps.per8 = fused_max_blocks_per_cu(8);
       caps.res4 = resident_max_blocks_per_cu(4);
+      caps.res6 = resident_max_blocks_per_cu(12);
       caps.res8 = resident_max_blocks_per_cu(8);
       init = true;
     } else {
@@ -75,11 +77,11 @@ FusedCaps fused_caps() {
   return caps;
 }
 
-enum Kern { K_FUSED4, K_FUSED8, K_RES4, K_RES8 };
+enum Kern { K_FUSED4, K_FUSED8, K_RES4, K_RES6, K_RES8 };  // K_RES6: split-row kernel, np 80..96
 
 int grid_for(Kern k, int64_t batch) {
   FusedCaps c = fused_caps();
-  const int per = k == K_FUSED4 ? c.per4 : k == K_FUSED8 ? c.per8 : k == K_RES4 ? c.res4 : c.res8;
+  const int per = k == K_FUSED4 ? c.per4 : k == K_FUSED8 ? c.per8 : k == K_RES4 ? c.res4 : k == K_RES6 ? c.res6 : c.res8;
   int cap = c.cus > 0 ? c.cus * per : kMaxSlots;
   if (cap > kMaxSlots) cap = kMaxSlots;
   return (int)(batch < cap ? batch : cap);
@@ -103,7 +105,7 @@ FusedLayout fused_layout(int64_t n_max, int64_t batch) {
   const int64_t tr = std::min<int64_t>(np_max_t(n_max), kResT);
   L.slots4 = grid_for(K_FUSED4, batch);
   L.slots8 = np_max_t(n_max) >= kSplitT ? grid_for(K_FUSED8, batch) : 0;
-  L.slotsr = tr >= kResParkT ? grid_for(K_RES8, batch) : 0;
+  L.slotsr = tr > kRes6T ? grid_for(K_RES8, batch) : 0;  // the 8-wave resident kernel: np 112, 128
   L.slot8_doubles = (size_t)kFusedBufs * np * np;
   L.slot4_doubles = (size_t)kFusedBufs * np4 * np4;
   L.slotr_doubles = (size_t)kResParkDoublesPerT * tr;
@@ -114,6 +116,32 @@ FusedLayout fused_layout(int64_t n_max, int64_t batch) {
   L.slotsr_off = L.slots4_off + align_up((size_t)L.slots4 * L.slot4_doubles * sizeof(double));
   L.total = L.slotsr_off + (size_t)L.slotsr * L.slotr_doubles * sizeof(double);
   return L;
+}
+
+// Second stream of the current device for the sweeps that run beside the 8-wave resident
+// sweep (created once per device, default priority), with the fork and join events.  The
+// mutex makes each call's record/wait pairs atomic, so concurrent host threads cannot
+// interleave them.
+struct ForkJoin {
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+std::mutex g_fj_mu;
+
+bool fork_join_for_device(ForkJoin *out) {
+  static std::map<int, ForkJoin> per_dev;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  auto it = per_dev.find(dev);
+  if (it == per_dev.end()) {
+    ForkJoin f;
+    if (hipStreamCreateWithFlags(&f.side, hipStreamNonBlocking) != hipSuccess) return false;
+    if (hipEventCreateWithFlags(&f.fork, hipEventDisableTiming) != hipSuccess) return false;
+    if (hipEventCreateWithFlags(&f.join, hipEventDisableTiming) != hipSuccess) return false;
+    it = per_dev.emplace(dev, f).first;
+  }
+  *out = it->second;
+  return true;
 }
 
 }  // namespace
@@ -163,9 +191,10 @@ size_t expm_workspace_bytes(int64_t n_max, int64_t batch, const expm_opts_t *opt
 }
 
 // stage: -1 all phases; 0 sort the batch into the work queue; 1 sweep of the 8-wave resident
-// kernel (real orders 80..128); 2 sweeps of every other order (np <= 64 on the 4-wave resident
-// kernel, np 144..256 on the 8-wave global-memory kernel).  Stages 1 and 2 need stage 0 first
-// and are independent of each other.  Feature rows (learned selector) run on the global-memory
+// kernel (real orders 112..128); 2 sweeps of every other order, i.e. stages 3, 4, 5 in turn:
+// 3 np 144..256 on the 8-wave global-memory kernel, 4 np 80..96 on the split-row resident
+// kernel, 5 np <= 64 on the 4-wave resident kernel.  Stages 1..5 need stage 0 first and are
+// independent of each other.  Feature rows (learned selector) run on the global-memory
 // kernels.
 static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, const int32_t *ns,
                                int64_t batch, int64_t n_uniform, int64_t n_max,
@@ -199,46 +228,87 @@ static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, cons
   a.lo = 0;
   a.hi = batch;
   hipStream_t st = (hipStream_t)stream;
-  FusedArgs f8 = a, f4 = a, r8 = a, r4 = a;
+  FusedArgs f8 = a, f4 = a, r8 = a, r6 = a, r4 = a;
   f8.slots = (double *)(base + L.slots8_off);
   f8.slot_doubles = L.slot8_doubles;
   f4.slots = (double *)(base + L.slots4_off);
   f4.slot_doubles = L.slot4_doubles;
   r8.slots = L.slotsr > 0 ? (double *)(base + L.slotsr_off) : nullptr;
   r8.slot_doubles = L.slotr_doubles;
-  r4.slots = nullptr;
-  r4.slot_doubles = 0;
+  r6.slots = r4.slots = nullptr;
+  r6.slot_doubles = r4.slot_doubles = 0;
   const int tmax = np_max_t(nr_max);
   auto go = [&](Kern k, FusedArgs &x, int ctr, int lo, int hi) -> bool {
     x.q_ctr = ctr; x.q_lo = lo; x.q_hi = hi;
-    const int grid = k == K_FUSED8 ? L.slots8 : k == K_FUSED4 ? L.slots4 : k == K_RES8 ? grid_for(K_RES8, batch)
-                                                                                   : grid_for(K_RES4, batch);
-    if (k == K_RES8 && std::min(tmax, kResT) >= kResParkT && grid > L.slotsr) return false;
-    hipError_t e = (k == K_FUSED8 || k == K_FUSED4) ? launch_fused(x, k == K_FUSED8 ? 8 : 4, grid, st)
-                                                    : launch_resident(x, k == K_RES8 ? 8 : 4, grid, st);
+    int grid;
+    hipError_t e;
+    switch (k) {
+      case K_FUSED8: grid = L.slots8; e = launch_fused(x, 8, grid, st); break;
+      case K_FUSED4: grid = L.slots4; e = launch_fused(x, 4, grid, st); break;
+      case K_RES8:
+        grid = grid_for(K_RES8, batch);
+        if (grid > L.slotsr) return false;
+        e = launch_resident(x, 8, grid, st);
+        break;
+      case K_RES6: grid = grid_for(K_RES6, batch); e = launch_resident(x, 12, grid, st); break;
+      default: grid = grid_for(K_RES4, batch); e = launch_resident(x, 4, grid, st); break;
+    }
     return e == hipSuccess;
   };
+  // queue words: counters 0 (np 144..256), 1 (112..128), 2 (80..96), 3 (<= 64), 4 (feature
+  // rows of np <= 64); bounds kQBound + 0..4 (see the order kernel)
   if (ns) {
     int32_t *order = (int32_t *)(base + L.order_off);
     unsigned long long *queue = (unsigned long long *)(base + L.queue_off);
-    f8.order = f4.order = r8.order = r4.order = order;
-    f8.queue = f4.queue = r8.queue = r4.queue = queue;
+    f8.order = f4.order = r8.order = r6.order = r4.order = order;
+    f8.queue = f4.queue = r8.queue = r6.queue = r4.queue = queue;
     if ((stage == -1 || stage == 0) && launch_order(ns, batch, cplx, order, queue, st) != hipSuccess)
       return EXPM_E_HIP;
     if (features) {
       // global-memory kernels: np >= 80 on 8 waves, the rest on 4 waves
-      if (tmax >= kSplitT && !go(K_FUSED8, f8, 0, 0, 2)) return EXPM_E_HIP;
-      if (!go(K_FUSED4, f4, 3, 2, 3)) return EXPM_E_HIP;
+      if (tmax >= kSplitT && !go(K_FUSED8, f8, 0, 0, 3)) return EXPM_E_HIP;
+      if (!go(K_FUSED4, f4, 4, 3, 4)) return EXPM_E_HIP;
       return EXPM_OK;
     }
-    // largest orders first; each sweep drains its own range of the sorted queue
-    if ((stage == -1 || stage == 1) && tmax >= kSplitT && !go(K_RES8, r8, 1, 1, 2)) return EXPM_E_HIP;
-    if ((stage == -1 || stage == 2) && tmax > kResT && !go(K_FUSED8, f8, 0, 0, 1)) return EXPM_E_HIP;
-    if ((stage == -1 || stage == 2) && !go(K_RES4, r4, 2, 2, 3)) return EXPM_E_HIP;
+    // largest orders first; each sweep drains its own range of the sorted queue.  A full call
+    // runs the 8-wave resident sweep on the caller's stream and the other sweeps beside it on
+    // a second stream (fork after the sort, join before return), so the sweeps share the CUs
+    // instead of each waiting for the previous one's last matrices.
+    auto sub = [&](int k) -> bool {
+      switch (k) {
+        case 3: return tmax <= kResT || go(K_FUSED8, f8, 0, 0, 1);
+        case 4: return tmax < kSplitT || go(K_RES6, r6, 2, 2, 3);
+        default: return go(K_RES4, r4, 3, 3, 4);
+      }
+    };
+    auto stage2 = [&](hipStream_t s2) -> bool {
+      const hipStream_t keep = st;
+      st = s2;
+      const bool ok = sub(3) && sub(4) && sub(5);
+      st = keep;
+      return ok;
+    };
+    if (stage == 1) return (tmax <= kRes6T || go(K_RES8, r8, 1, 1, 2)) ? EXPM_OK : EXPM_E_HIP;
+    if (stage == 2) return stage2(st) ? EXPM_OK : EXPM_E_HIP;
+    if (stage >= 3) return sub(stage) ? EXPM_OK : EXPM_E_HIP;
+    if (stage == -1) {
+      std::lock_guard<std::mutex> lk(g_fj_mu);
+      ForkJoin fj;
+      if (!fork_join_for_device(&fj)) return EXPM_E_HIP;
+      if (hipEventRecord(fj.fork, st) != hipSuccess || hipStreamWaitEvent(fj.side, fj.fork, 0) != hipSuccess)
+        return EXPM_E_HIP;
+      const bool ok2 = stage2(fj.side);
+      const bool ok1 = tmax <= kRes6T || go(K_RES8, r8, 1, 1, 2);
+      if (hipEventRecord(fj.join, fj.side) != hipSuccess || hipStreamWaitEvent(st, fj.join, 0) != hipSuccess)
+        return EXPM_E_HIP;
+      if (!ok1 || !ok2) return EXPM_E_HIP;
+    }
   } else {
     const int t = np_max_t(nr_uni);
-    const bool ok = t > kResT ? go(K_FUSED8, f8, 0, 0, 0) : t >= kSplitT ? go(K_RES8, r8, 1, 0, 0)
-                                                                         : go(K_RES4, r4, 2, 0, 0);
+    const bool ok = t > kResT    ? go(K_FUSED8, f8, 0, 0, 0)
+                    : t > kRes6T  ? go(K_RES8, r8, 1, 0, 0)
+                    : t >= kSplitT ? go(K_RES6, r6, 2, 0, 0)
+                                   : go(K_RES4, r4, 3, 0, 0);
     if (!ok) return EXPM_E_HIP;
   }
   return EXPM_OK;
@@ -316,7 +386,7 @@ expm_status_t expm_batched_stage(const void *A_dev, void *E_dev, const int64_t *
   expm_status_t st = check_opts(opts, &u);
   if (st != EXPM_OK) return st;
   if (!A_dev || !E_dev || !offsets_dev || !n_dev || !m_dev || !s_dev || batch < 1 || n_max < 1 ||
-      A_dev == E_dev || stage < 0 || stage > 2)
+      A_dev == E_dev || stage < 0 || stage > 5)
     return EXPM_E_INVALID_ARG;
   if (real_order(opts, n_max) > kFusedNMax || opts->prec != EXPM_PREC_FP64) return EXPM_E_UNSUPPORTED;
   return run_fused(A_dev, E_dev, offsets_dev, n_dev, batch, 0, n_max, opts, u, m_dev, s_dev,

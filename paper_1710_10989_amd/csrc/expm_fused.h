@@ -16,11 +16,14 @@ constexpr int kResT = 8;
 constexpr int kResParkT = 5;
 constexpr int kResParkDoublesPerT = 2 * 8 * 4 * 64;
 
-// Work-queue words written by the order kernel: [0, 4) counters of up to four sweeps;
-// [kQBound, kQBound + 4) range bounds of the sorted order (largest real order first):
-// 0, first entry with np <= 128, first entry with np <= 64, batch.
-constexpr int kQBound = 4;
-constexpr int kQWords = 8;
+// Orders np 80..96 (np / 16 = 5, 6) run on the split-row resident kernel (12 waves).
+constexpr int kRes6T = 6;
+
+// Work-queue words written by the order kernel: [0, kQBound) counters of up to five sweeps;
+// [kQBound, kQBound + 5) range bounds of the sorted order (largest real order first):
+// 0, first entry with np <= 128, with np <= 96, with np <= 64, batch.
+constexpr int kQBound = 8;
+constexpr int kQWords = 16;
 
 struct FusedArgs {
   const double *A;        // packed inputs
@@ -56,9 +59,10 @@ hipError_t learned_counts(unsigned long long out[2]);
 constexpr int kFusedBufs = 8;
 int fused_max_blocks_per_cu(int nw);
 hipError_t launch_fused(const FusedArgs &a, int nw, int grid, hipStream_t st);
-// Resident kernels (np <= 128: 8 waves for np 80..128, 4 waves for np <= 64).
+// Resident kernels (np <= 128: 8 waves for np 112..128, split-row 12 waves for np 80..96,
+// 4 waves for np <= 64).
 int resident_max_blocks_per_cu(int nw);
-hipError_t launch_resident(const FusedArgs &a, int nw, int grid, hipStream_t st);
+hipError_t launch_resident(const FusedArgs &a, int nw, int grid, hipStream_t st);  // nw = 8, 12, 4
 hipError_t launch_order(const int32_t *ns, int64_t batch, int cplx, int32_t *order,
                         unsigned long long *queue, hipStream_t st);
 

@@ -512,6 +512,7 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 2 : 1) void expm_fused_kernel(Fu
 }  // namespace expm
 
 #include "resident.h"
+#include "resident_sr.h"
 
 namespace expm {
 namespace {
@@ -522,6 +523,13 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 2 : 1) void expm_resident_kernel
   double *slot = a.slots ? a.slots + (size_t)blockIdx.x * a.slot_doubles : nullptr;
   res_init<NW>(a);
   sweep(a, [&](int64_t b) { run_res_dispatch<NW, SEL>(a, b, slot, red); });
+}
+
+template <int SEL>
+__global__ __launch_bounds__(64 * kSrNW, 3) void expm_sr_kernel(FusedArgs a) {
+  __shared__ double red[64 * kSrNW + 16];
+  res_init<kSrNW>(a);
+  sweep(a, [&](int64_t b) { run_sr_dispatch<SEL>(a, b, red); });
 }
 
 }  // namespace
@@ -547,8 +555,9 @@ __global__ void expm_order_kernel(const int32_t *ns, int64_t batch, int cplx, in
     for (int i = 0; i < kQBound; ++i) queue[i] = 0ull;
     queue[kQBound + 0] = 0ull;
     queue[kQBound + 1] = (unsigned long long)start[16 - kResT];       // np <= 128
-    queue[kQBound + 2] = (unsigned long long)start[16 - kSplitT + 1];  // np <= 64
-    queue[kQBound + 3] = (unsigned long long)batch;
+    queue[kQBound + 2] = (unsigned long long)start[16 - kRes6T];      // np <= 96
+    queue[kQBound + 3] = (unsigned long long)start[16 - kSplitT + 1];  // np <= 64
+    queue[kQBound + 4] = (unsigned long long)batch;
   }
   __syncthreads();
   for (int64_t b = tid; b < batch; b += blockDim.x) {
@@ -574,27 +583,34 @@ hipError_t launch_fused(const FusedArgs &a, int nw, int grid, hipStream_t st) {
 
 int resident_max_blocks_per_cu(int nw) {
   int nb = 0;
-  hipError_t e = nw == 8
-      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, expm_resident_kernel<8, EXPM_SEL_PLAIN>, 512, 0)
-      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, expm_resident_kernel<4, EXPM_SEL_PLAIN>, 256, 0);
+  hipError_t e = nw == 8    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, expm_resident_kernel<8, EXPM_SEL_PLAIN>, 512, 0)
+                 : nw == 12 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, expm_sr_kernel<EXPM_SEL_PLAIN>, 768, 0)
+                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, expm_resident_kernel<4, EXPM_SEL_PLAIN>, 256, 0);
   if (e != hipSuccess) return 1;
   return nb < 1 ? 1 : nb;
 }
 
+// Every selector variant of a kernel has the same launch bounds and LDS footprint.
+template <int NW>
+static void launch_res_sel(const FusedArgs &a, int grid, hipStream_t st) {
+  switch (a.sel) {
+    case EXPM_SEL_ALPHA: hipLaunchKernelGGL((expm_resident_kernel<NW, EXPM_SEL_ALPHA>), dim3(grid), dim3(64 * NW), 0, st, a); break;
+    case EXPM_SEL_LEARNED: hipLaunchKernelGGL((expm_resident_kernel<NW, EXPM_SEL_LEARNED>), dim3(grid), dim3(64 * NW), 0, st, a); break;
+    default: hipLaunchKernelGGL((expm_resident_kernel<NW, EXPM_SEL_PLAIN>), dim3(grid), dim3(64 * NW), 0, st, a); break;
+  }
+}
+
 hipError_t launch_resident(const FusedArgs &a, int nw, int grid, hipStream_t st) {
-  // every variant of a wave count has the same launch bounds and LDS footprint
   if (nw == 8) {
+    launch_res_sel<8>(a, grid, st);
+  } else if (nw == 12) {
     switch (a.sel) {
-      case EXPM_SEL_ALPHA: hipLaunchKernelGGL((expm_resident_kernel<8, EXPM_SEL_ALPHA>), dim3(grid), dim3(512), 0, st, a); break;
-      case EXPM_SEL_LEARNED: hipLaunchKernelGGL((expm_resident_kernel<8, EXPM_SEL_LEARNED>), dim3(grid), dim3(512), 0, st, a); break;
-      default: hipLaunchKernelGGL((expm_resident_kernel<8, EXPM_SEL_PLAIN>), dim3(grid), dim3(512), 0, st, a); break;
+      case EXPM_SEL_ALPHA: hipLaunchKernelGGL((expm_sr_kernel<EXPM_SEL_ALPHA>), dim3(grid), dim3(64 * kSrNW), 0, st, a); break;
+      case EXPM_SEL_LEARNED: hipLaunchKernelGGL((expm_sr_kernel<EXPM_SEL_LEARNED>), dim3(grid), dim3(64 * kSrNW), 0, st, a); break;
+      default: hipLaunchKernelGGL((expm_sr_kernel<EXPM_SEL_PLAIN>), dim3(grid), dim3(64 * kSrNW), 0, st, a); break;
     }
   } else {
-    switch (a.sel) {
-      case EXPM_SEL_ALPHA: hipLaunchKernelGGL((expm_resident_kernel<4, EXPM_SEL_ALPHA>), dim3(grid), dim3(256), 0, st, a); break;
-      case EXPM_SEL_LEARNED: hipLaunchKernelGGL((expm_resident_kernel<4, EXPM_SEL_LEARNED>), dim3(grid), dim3(256), 0, st, a); break;
-      default: hipLaunchKernelGGL((expm_resident_kernel<4, EXPM_SEL_PLAIN>), dim3(grid), dim3(256), 0, st, a); break;
-    }
+    launch_res_sel<4>(a, grid, st);
   }
   return hipGetLastError();
 }

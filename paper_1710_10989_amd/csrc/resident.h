@@ -685,7 +685,7 @@ __device__ void run_res_dispatch(const FusedArgs &a, int64_t b, double *slot, do
   const int n = cx ? 2 * nin : nin;
   const int64_t off = (a.offs ? a.offs[b] : b * (int64_t)nin * nin) * (cx ? 2 : 1);
   const int t = (n + 15) >> 4;
-  const bool fits = NW == 8 ? (t >= 5 && t <= 8) : (t >= 1 && t <= 4);
+  const bool fits = NW == 8 ? (t > kRes6T && t <= kResT) : (t >= 1 && t < kSplitT);
   if (nin < 1 || n > a.np_max || !fits) {  // invalid order, or routed to the wrong variant
     if (tid == 0) {
       a.m_out[b] = -1; a.s_out[b] = -1;
@@ -695,14 +695,11 @@ __device__ void run_res_dispatch(const FusedArgs &a, int64_t b, double *slot, do
   }
   const bool idle = (int)(threadIdx.x >> 6) >= t;  // wave-uniform
   if constexpr (NW == 8) {
-    switch (t) {
-      case 5: idle ? run_res<8, SEL, 5, true>(a, b, n, nin, cx, off, slot, red)
-                   : run_res<8, SEL, 5, false>(a, b, n, nin, cx, off, slot, red); break;
-      case 6: idle ? run_res<8, SEL, 6, true>(a, b, n, nin, cx, off, slot, red)
-                   : run_res<8, SEL, 6, false>(a, b, n, nin, cx, off, slot, red); break;
-      case 7: idle ? run_res<8, SEL, 7, true>(a, b, n, nin, cx, off, slot, red)
-                   : run_res<8, SEL, 7, false>(a, b, n, nin, cx, off, slot, red); break;
-      default: run_res<8, SEL, 8, false>(a, b, n, nin, cx, off, slot, red); break;
+    if (t == 7) {
+      idle ? run_res<8, SEL, 7, true>(a, b, n, nin, cx, off, slot, red)
+           : run_res<8, SEL, 7, false>(a, b, n, nin, cx, off, slot, red);
+    } else {
+      run_res<8, SEL, 8, false>(a, b, n, nin, cx, off, slot, red);
     }
   } else {
     switch (t) {

@@ -121,7 +121,7 @@ class Batch:
 
 def batched(batch, u=None, prec="fp64", selector="plain", workspace=None, out=None, stage=None, outs=None):
     """e^A for every matrix of a Batch.  Returns (E_packed, m, s, status) device tensors.
-    stage: None (all phases) or 0 / 1 / 2 (expm_batched_stage); outs: reuse (E, m, s, status)."""
+    stage: None (all phases) or 0..5 (expm_batched_stage); outs: reuse (E, m, s, status)."""
     nb = batch.ns.numel()
     o = _opts(batch.packed.dtype, prec, selector, u)
     ws = workspace if workspace is not None else _workspace(

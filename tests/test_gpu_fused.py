@@ -254,3 +254,28 @@ def test_staged_calls_match_and_may_overlap(P):
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
     assert torch.equal(outs[0], E0)
+
+
+def test_sub_stages_match_full_call(P):
+    # orders in every sweep: np <= 64, 80..96, 112..128 and 144..256
+    rng = np.random.default_rng(77)
+    mats = []
+    for n in (7, 33, 64, 65, 90, 96, 100, 128, 129, 200, 256):
+        for _ in range(6):
+            A = rng.standard_normal((n, n))
+            mats.append(A * (10.0 ** rng.uniform(-2, 1.5)) / np.abs(A).sum(0).max())
+    from paper_1710_10989_amd.expm import Batch
+    B = Batch.from_host(mats)
+    say("case sub-stages")
+    E0, m0, s0, st0 = P.batched(B)
+    nb = len(mats)
+    ws = torch.empty(P.workspace_bytes(B.n_max, nb), dtype=torch.uint8, device="cuda")
+    outs = (torch.zeros_like(B.packed), torch.empty(nb, dtype=torch.int32, device="cuda"),
+            torch.empty(nb, dtype=torch.int32, device="cuda"), torch.empty(nb, dtype=torch.int32, device="cuda"))
+    for stg in (0, 5, 3, 1, 4):  # any order after the sort
+        P.batched(B, workspace=ws, outs=outs, stage=stg)
+    torch.cuda.synchronize()
+    assert bool((st0 == 0).all())
+    assert torch.equal(outs[0], E0) and torch.equal(outs[1], m0) and torch.equal(outs[2], s0)
+    with pytest.raises(RuntimeError):
+        P.batched(B, workspace=ws, outs=outs, stage=6)
