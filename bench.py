@@ -40,29 +40,32 @@ PEAK_FP64 = 78.6e12
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def sources_sha256():
-    """Digest of the kernel sources (csrc/*.h, *.hip, *.cpp) the library is built from."""
+KERNEL_SOURCES = ("coefs.h", "expm_api.cpp", "expm_fused.h", "expm_fused.hip", "expm_internal.h", "resident.h")
+
+
+def sources_sha256(files=KERNEL_SOURCES):
+    """Digest of the csrc files a kernel and its launch are built from."""
     import hashlib
     d = os.path.join(HERE, "paper_1710_10989_amd", "csrc")
     h = hashlib.sha256()
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".h", ".hip", ".cpp")):
-            h.update(f.encode())
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(fh.read())
+    for f in sorted(files):
+        h.update(f.encode())
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()
 
 
 def measured_traffic(tag):
     """HBM bytes per launch of a kernel from its committed PMC summary (FETCH_SIZE and
     WRITE_SIZE, each scaled by the same counter's reading on a copy of known size), or None
-    when the summary was taken on other kernel sources than the current ones."""
+    when the summary was taken on other sources of that kernel than the current ones."""
     path = os.path.join(HERE, "profiles", tag + "_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    if d.get("sources_sha256") != sources_sha256():
+    files = d.get("sources", [])
+    if not files or d.get("sources_sha256") != sources_sha256(files):
         return None
     return d.get("bytes_per_launch")
 
