@@ -18,6 +18,10 @@ Other workloads (one JSON line each, selected with --workload):
              `python -m paper_1710_10989_amd.learned train`; its checkpoint is loaded if present)
   complex    512 complex matrices -i H dt (H Hermitian, spectral radius 1, n = 256,
              dt log-uniform in [1e-2, 1e2]) + one dense FP64 n = 8192 with ||A||_1 = 20
+  small      65536 skew-symmetric FP64 matrices of order 16, ||A||_1 log-uniform in [0.05, 1]
+             (the exponents of a Magnus integrator; one wave per matrix)
+  magnus     one fourth-order Magnus step for 65536 linear systems Y' = (S0 + u(t) S1) Y of
+             order 16 (expm_magnus4_step: exponent, e^Omega and its product with Y on chip)
   copy       device-to-device copy of a 1 GiB buffer (the known-size calibration kernel
              for HBM byte counters; not a matrix-exponential figure)
 
@@ -91,8 +95,8 @@ def cpu_oracle(mats, seconds, label):
                       "matrices, %.1f s" % (done, label, c1 - c0)}
 
 
-def line(args, metric, value, ms_step, dtype, config, roofline, cpu):
-    return {"metric": metric, "value": value, "unit": "matrices/s", "n_gpus": 1, "steps": args.steps,
+def line(args, metric, value, ms_step, dtype, config, roofline, cpu, unit="matrices/s"):
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config, "roofline": roofline,
             "cpu_baseline": cpu}
@@ -353,6 +357,96 @@ def run_learned(args, torch, P, W):
                 res["learned"]["ms"], "f64", config, roof, cpu)
 
 
+PEAK_HBM = 8.0e12
+
+
+def timed(torch, args, fn):
+    """Average ms of fn() over args.steps calls after args.warmup, HIP events on the current
+    stream (the launch stream of the calls)."""
+    for _ in range(args.warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(args.steps):
+        fn()
+    t1.record()
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / args.steps
+
+
+def run_small(args, torch, P, W):
+    count, n = 65536, 16
+    A = W.small_skew_batch(count=count, n=n)
+    Ad = torch.from_numpy(A).cuda()
+    ws = torch.empty(P.workspace_bytes(n, count), dtype=torch.uint8, device="cuda")
+    out = torch.empty_like(Ad)
+    outs = tuple(torch.empty(count, dtype=torch.int32, device="cuda") for _ in range(3))
+
+    def step():
+        P.batched_uniform(Ad, selector=args.selector, workspace=ws, out=out, outs=outs)
+
+    ms = timed(torch, args, step)
+    m, s, st = (x.cpu().numpy() for x in outs)
+    assert np.all(st == 0)
+    nbytes = count * (16 * n * n + 12)  # A in, e^A out, (m, s, status) out
+    achieved = nbytes / (ms * 1e-3)
+    roof = {"bound": "hbm", "kernel": "expm_tiny_kernel (one wave per matrix)", "achieved": achieved / 1e9,
+            "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": achieved / PEAK_HBM,
+            "traffic": measured_traffic("expm_tiny_kernel_65536_n16"), "kernel_ms": ms,
+            "step_tflops": executed_flops(m, s, [n] * count) / (ms * 1e-3) / 1e12}
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_oracle([A[i] for i in range(4096)], args.cpu_seconds, "4096 of the matrices")
+    config = {"workload": "%d FP64 skew-symmetric matrices of order %d (Magnus-integrator exponents), "
+                          "||A||_1 log-uniform [0.05, 1]; one expm_batched_uniform call per step" % (count, n),
+              "selector": args.selector,
+              "mean_products_plus_squarings": float(np.mean([PRODUCTS[int(a)] + int(b) for a, b in zip(m, s)]))}
+    return line(args, "expm matrices/s (rel err <= 1e-12, FP64)", count / (ms * 1e-3), ms, "f64", config, roof, cpu)
+
+
+def run_magnus(args, torch, P, W):
+    count, n, h = 65536, 16, 0.1
+    S0, S1, Y0, a, w, phi = W.magnus_systems(count=count, n=n)
+    u1, u2 = W.control_at_gauss_points(a, w, phi, 0.0, h)
+    d = [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in (S0, S1, Y0, u1, u2)]
+    Yo = torch.empty_like(d[2])
+    outs = tuple(torch.empty(count, dtype=torch.int32, device="cuda") for _ in range(3))
+
+    def step():
+        P.magnus4_step(d[0], d[1], d[2], d[3], d[4], h, selector=args.selector, out=Yo, outs=outs)
+
+    ms = timed(torch, args, step)
+    m, s, st = (x.cpu().numpy() for x in outs)
+    assert np.all(st == 0)
+    nbytes = count * (4 * 8 * n * n + 16 + 12)  # S0, S1, Y in, Y out; u1, u2; (m, s, status)
+    achieved = nbytes / (ms * 1e-3)
+    gemms = [3 + PRODUCTS[int(a_)] + int(b_) for a_, b_ in zip(m, s)]  # commutator (2), e^Omega, e^Omega Y
+    roof = {"bound": "hbm", "kernel": "expm_magnus4_kernel (one wave per system)", "achieved": achieved / 1e9,
+            "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": achieved / PEAK_HBM,
+            "traffic": measured_traffic("expm_magnus4_kernel_65536_n16"), "kernel_ms": ms,
+            "step_tflops": sum(gemms) * 2.0 * n ** 3 / (ms * 1e-3) / 1e12}
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        done, c0 = 0, time.perf_counter()
+        while time.perf_counter() - c0 < args.cpu_seconds:
+            b = done % count
+            oracle.magnus4_step(S0[b], S1[b], Y0[b], u1[b], u2[b], h, prec="d")
+            done += 1
+        c1 = time.perf_counter()
+        cpu = {"value": done / (c1 - c0), "unit": "steps/s", "cores": 1, "kind": "oracle",
+               "sample": "%d systems of the workload, one step each (FP64 Omega, FP64 direct-Taylor "
+                         "exponential, one thread), %.1f s" % (done, c1 - c0)}
+    config = {"workload": "%d linear systems Y' = (S0 + u(t) S1) Y of order %d, S0, S1 skew (||.||_1 = 2, 1), "
+                          "u = a cos(w t + phi), one fourth-order Magnus step of h = %g per step "
+                          "(expm_magnus4_step)" % (count, n, h),
+              "selector": args.selector,
+              "mean_products_plus_squarings": float(np.mean([PRODUCTS[int(a_)] + int(b_) for a_, b_ in zip(m, s)]))}
+    return line(args, "Magnus-4 system steps/s (FP64)", count / (ms * 1e-3), ms, "f64", config, roof, cpu,
+                unit="steps/s")
+
+
 def run_copy(args, torch, P, W):
     nbytes = 1 << 30
     src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
@@ -379,7 +473,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="batched", choices=["batched", "single", "precision", "complex", "learned",
-                                                             "copy"])
+                                                             "small", "magnus", "copy"])
     ap.add_argument("--selector", default="plain", choices=["plain", "alpha"])
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--count", type=int, default=4096)
@@ -395,7 +489,7 @@ def main():
     import paper_1710_10989_amd as P
     from paper_1710_10989_amd import workloads as W
     fn = {"batched": run_batched, "single": run_single, "precision": run_precision, "complex": run_complex,
-          "learned": run_learned, "copy": run_copy}
+          "learned": run_learned, "small": run_small, "magnus": run_magnus, "copy": run_copy}
     print(json.dumps(fn[args.workload](args, torch, P, W)), flush=True)
 
 

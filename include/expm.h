@@ -157,6 +157,27 @@ EXPM_API expm_status_t expm_batched_uniform(const void *A_dev, void *E_dev, int6
                                    const expm_opts_t *opts, int32_t *m_dev, int32_t *s_dev,
                                    int32_t *status_dev, void *ws_dev, size_t ws_bytes, void *stream);
 
+/* One step of the fourth-order Magnus integrator for `batch` linear systems Y' = F(t) Y with
+ * F(t) = S0 + u(t) S1 (an exponential integrator, in which the exponential of the method is
+ * the inner stage; concluding remarks of the paper).  Per system b, with the control sampled
+ * at the two Gauss points, u1 = u(t + (1/2 - sqrt(3)/6) h) and u2 = u(t + (1/2 + sqrt(3)/6) h):
+ *   Omega = h S0 + (h / 2)(u1 + u2) S1 + (sqrt(3) h^2 / 12)(u1 - u2)(S0 S1 - S1 S0)
+ * (the midpoint-sum and commutator terms of the two-point Gauss Magnus expansion, written out
+ * for this F), then Y_out = e^Omega Y_in with e^Omega by the product-reduced Taylor method
+ * ((m, s) of Omega by opts->sel, PLAIN or ALPHA; accuracy opts->u).
+ * Real FP64, order 1 <= n <= 16 (one wavefront per system, everything on chip).  Layout:
+ * row-major n x n; system b's S0, S1 at element b * s_stride (s_stride = n^2 for per-system
+ * matrices, 0 for one pair shared by all), Y_in and Y_out at b * n^2; Y_out may equal Y_in
+ * (in place); u1_dev, u2_dev: batch doubles each.  Outputs m_dev[b], s_dev[b] (the (m, s)
+ * used for Omega) and status_dev[b] (may be NULL; EXPM_E_NONFINITE and a NaN Y_out when an
+ * input of the system is not finite).  Needs no workspace; graph-capturable.  Returns
+ * EXPM_E_UNSUPPORTED for complex dtype, reduced precision, the learned selector or n > 16. */
+EXPM_API expm_status_t expm_magnus4_step(const double *S0_dev, const double *S1_dev, int64_t s_stride,
+                                         const double *Y_in_dev, double *Y_out_dev, const double *u1_dev,
+                                         const double *u2_dev, int64_t n, int64_t batch, double h,
+                                         const expm_opts_t *opts, int32_t *m_dev, int32_t *s_dev,
+                                         int32_t *status_dev, void *stream);
+
 /* ---------------------------------------------------------------------------------------
  * Learned (m, s) selector (EXPM_SEL_LEARNED).  Not part of the paper: a small MLP proposes
  * (m, s) from features that exist once A^2 is formed; the proposal is kept only when the

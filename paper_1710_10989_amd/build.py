@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libexpm.so")
-SOURCES = ["expm_api.cpp", "theta.cpp", "expm_fused.hip", "expm_large.hip", "mlp.hip"]
+SOURCES = ["expm_api.cpp", "theta.cpp", "expm_fused.hip", "expm_large.hip", "expm_tiny.hip", "mlp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

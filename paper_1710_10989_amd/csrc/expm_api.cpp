@@ -51,7 +51,7 @@ expm_status_t check_opts(const expm_opts_t *o, double *u) {
 
 // Resident workgroups per CU of the four sweep kernels on the current device (cached).
 struct FusedCaps {
-  int cus = 0, per4 = 1, per8 = 1, res4 = 1, res6 = 1, res8 = 1;
+  int cus = 0, per4 = 1, per8 = 1, res4 = 1, res6 = 1, res8 = 1, tiny = 1;
 };
 
 FusedCaps fused_caps() {
@@ -69,6 +69,7 @@ FusedCaps fused_caps() {
       caps.res4 = resident_max_blocks_per_cu(4);
       caps.res6 = resident_max_blocks_per_cu(12);
       caps.res8 = resident_max_blocks_per_cu(8);
+      caps.tiny = tiny_max_blocks_per_cu();
       init = true;
     } else {
       caps.cus = 0;  // no device visible: size for the largest launch, do not cache
@@ -77,10 +78,17 @@ FusedCaps fused_caps() {
   return caps;
 }
 
-enum Kern { K_FUSED4, K_FUSED8, K_RES4, K_RES6, K_RES8 };  // K_RES6: split-row kernel, np 80..96
+// K_RES6: split-row kernel, np 80..96; K_TINY: one wave per matrix, np 16
+enum Kern { K_FUSED4, K_FUSED8, K_RES4, K_RES6, K_RES8, K_TINY };
 
 int grid_for(Kern k, int64_t batch) {
   FusedCaps c = fused_caps();
+  if (k == K_TINY) {  // one matrix per wave; no per-workgroup slot
+    const int64_t w = tiny_waves_per_block();
+    const int64_t need = (batch + w - 1) / w;
+    const int64_t cap = c.cus > 0 ? (int64_t)c.cus * c.tiny : 8192;
+    return (int)(need < cap ? need : cap);
+  }
   const int per = k == K_FUSED4 ? c.per4 : k == K_FUSED8 ? c.per8 : k == K_RES4 ? c.res4 : k == K_RES6 ? c.res6 : c.res8;
   int cap = c.cus > 0 ? c.cus * per : kMaxSlots;
   if (cap > kMaxSlots) cap = kMaxSlots;
@@ -193,7 +201,7 @@ size_t expm_workspace_bytes(int64_t n_max, int64_t batch, const expm_opts_t *opt
 // stage: -1 all phases; 0 sort the batch into the work queue; 1 sweep of the 8-wave resident
 // kernel (real orders 112..128); 2 sweeps of every other order, i.e. stages 3, 4, 5 in turn:
 // 3 np 144..256 on the 8-wave global-memory kernel, 4 np 80..96 on the split-row resident
-// kernel, 5 np <= 64 on the 4-wave resident kernel.  Stages 1..5 need stage 0 first and are
+// kernel, 5 np 32..64 on the 4-wave resident kernel and np 16 on the one-wave kernel.  Stages 1..5 need stage 0 first and are
 // independent of each other.  Feature rows (learned selector) run on the global-memory
 // kernels.
 static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, const int32_t *ns,
@@ -228,15 +236,18 @@ static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, cons
   a.lo = 0;
   a.hi = batch;
   hipStream_t st = (hipStream_t)stream;
-  FusedArgs f8 = a, f4 = a, r8 = a, r6 = a, r4 = a;
+  FusedArgs f8 = a, f4 = a, r8 = a, r6 = a, r4 = a, tn = a;
   f8.slots = (double *)(base + L.slots8_off);
   f8.slot_doubles = L.slot8_doubles;
   f4.slots = (double *)(base + L.slots4_off);
   f4.slot_doubles = L.slot4_doubles;
   r8.slots = L.slotsr > 0 ? (double *)(base + L.slotsr_off) : nullptr;
   r8.slot_doubles = L.slotr_doubles;
-  r6.slots = r4.slots = nullptr;
-  r6.slot_doubles = r4.slot_doubles = 0;
+  r6.slots = r4.slots = tn.slots = nullptr;
+  r6.slot_doubles = r4.slot_doubles = tn.slot_doubles = 0;
+  // np = 16 runs one matrix per wave, except under the learned selector (whose network
+  // lives with the workgroup kernels)
+  const bool tiny = opts->sel != EXPM_SEL_LEARNED;
   const int tmax = np_max_t(nr_max);
   auto go = [&](Kern k, FusedArgs &x, int ctr, int lo, int hi) -> bool {
     x.q_ctr = ctr; x.q_lo = lo; x.q_hi = hi;
@@ -251,23 +262,25 @@ static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, cons
         e = launch_resident(x, 8, grid, st);
         break;
       case K_RES6: grid = grid_for(K_RES6, batch); e = launch_resident(x, 12, grid, st); break;
+      case K_TINY: grid = grid_for(K_TINY, batch); e = launch_tiny(x, grid, st); break;
       default: grid = grid_for(K_RES4, batch); e = launch_resident(x, 4, grid, st); break;
     }
     return e == hipSuccess;
   };
-  // queue words: counters 0 (np 144..256), 1 (112..128), 2 (80..96), 3 (<= 64), 4 (feature
-  // rows of np <= 64); bounds kQBound + 0..4 (see the order kernel)
+  // queue words: counters 0 (np 144..256), 1 (112..128), 2 (80..96), 3 (32..64, or <= 64
+  // without the one-wave kernel), 4 (feature rows of np <= 64), 5 (np 16); bounds
+  // kQBound + 0..5 (see the order kernel)
   if (ns) {
     int32_t *order = (int32_t *)(base + L.order_off);
     unsigned long long *queue = (unsigned long long *)(base + L.queue_off);
-    f8.order = f4.order = r8.order = r6.order = r4.order = order;
-    f8.queue = f4.queue = r8.queue = r6.queue = r4.queue = queue;
+    f8.order = f4.order = r8.order = r6.order = r4.order = tn.order = order;
+    f8.queue = f4.queue = r8.queue = r6.queue = r4.queue = tn.queue = queue;
     if ((stage == -1 || stage == 0) && launch_order(ns, batch, cplx, order, queue, st) != hipSuccess)
       return EXPM_E_HIP;
     if (features) {
       // global-memory kernels: np >= 80 on 8 waves, the rest on 4 waves
       if (tmax >= kSplitT && !go(K_FUSED8, f8, 0, 0, 3)) return EXPM_E_HIP;
-      if (!go(K_FUSED4, f4, 4, 3, 4)) return EXPM_E_HIP;
+      if (!go(K_FUSED4, f4, 4, 3, 5)) return EXPM_E_HIP;
       return EXPM_OK;
     }
     // largest orders first; each sweep drains its own range of the sorted queue.  A full call
@@ -278,7 +291,7 @@ static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, cons
       switch (k) {
         case 3: return tmax <= kResT || go(K_FUSED8, f8, 0, 0, 1);
         case 4: return tmax < kSplitT || go(K_RES6, r6, 2, 2, 3);
-        default: return go(K_RES4, r4, 3, 3, 4);
+        default: return tiny ? go(K_RES4, r4, 3, 3, 4) && go(K_TINY, tn, 5, 4, 5) : go(K_RES4, r4, 3, 3, 5);
       }
     };
     auto stage2 = [&](hipStream_t s2) -> bool {
@@ -308,6 +321,7 @@ static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, cons
     const bool ok = t > kResT    ? go(K_FUSED8, f8, 0, 0, 0)
                     : t > kRes6T  ? go(K_RES8, r8, 1, 0, 0)
                     : t >= kSplitT ? go(K_RES6, r6, 2, 0, 0)
+                    : (t == 1 && tiny) ? go(K_TINY, tn, 5, 0, 0)
                                    : go(K_RES4, r4, 3, 0, 0);
     if (!ok) return EXPM_E_HIP;
   }
@@ -404,6 +418,27 @@ expm_status_t expm_batched_uniform(const void *A_dev, void *E_dev, int64_t n, in
     return run_large_call(A_dev, E_dev, n, batch, opts, u, m_dev, s_dev, status_dev, ws_dev, ws_bytes, stream, 0);
   return run_fused(A_dev, E_dev, nullptr, nullptr, batch, n, n, opts, u, m_dev, s_dev, status_dev,
                    ws_dev, ws_bytes, stream, 0);
+}
+
+expm_status_t expm_magnus4_step(const double *S0_dev, const double *S1_dev, int64_t s_stride, const double *Y_in_dev,
+                                double *Y_out_dev, const double *u1_dev, const double *u2_dev, int64_t n,
+                                int64_t batch, double h, const expm_opts_t *opts, int32_t *m_dev, int32_t *s_dev,
+                                int32_t *status_dev, void *stream) {
+  double u;
+  expm_status_t st = check_opts(opts, &u);
+  if (st != EXPM_OK) return st;
+  if (!S0_dev || !S1_dev || !Y_in_dev || !Y_out_dev || !u1_dev || !u2_dev || !m_dev || !s_dev || n < 1 ||
+      batch < 1 || s_stride < 0 || !isfinite(h))
+    return EXPM_E_INVALID_ARG;
+  if (opts->dtype != EXPM_F64 || opts->prec != EXPM_PREC_FP64 || opts->sel == EXPM_SEL_LEARNED || n > 16)
+    return EXPM_E_UNSUPPORTED;
+  Consts k;
+  if (!make_consts(u, &k)) return EXPM_E_INVALID_ARG;
+  const int grid = grid_for(K_TINY, batch);
+  return launch_magnus4(S0_dev, S1_dev, s_stride, Y_in_dev, Y_out_dev, u1_dev, u2_dev, (int)n, batch, h, opts->sel,
+                        k, m_dev, s_dev, status_dev, grid, (hipStream_t)stream) == hipSuccess
+             ? EXPM_OK
+             : EXPM_E_HIP;
 }
 
 expm_status_t expm_features(const void *A_dev, const int64_t *offsets_dev, const int32_t *n_dev, int64_t batch,

@@ -19,9 +19,9 @@ constexpr int kResParkDoublesPerT = 2 * 8 * 4 * 64;
 // Orders np 80..96 (np / 16 = 5, 6) run on the split-row resident kernel (12 waves).
 constexpr int kRes6T = 6;
 
-// Work-queue words written by the order kernel: [0, kQBound) counters of up to five sweeps;
-// [kQBound, kQBound + 5) range bounds of the sorted order (largest real order first):
-// 0, first entry with np <= 128, with np <= 96, with np <= 64, batch.
+// Work-queue words written by the order kernel: [0, kQBound) counters of up to six sweeps;
+// [kQBound, kQBound + 6) range bounds of the sorted order (largest real order first):
+// 0, first entry with np <= 128, with np <= 96, with np <= 64, with np = 16, batch.
 constexpr int kQBound = 8;
 constexpr int kQWords = 16;
 
@@ -62,6 +62,16 @@ hipError_t launch_fused(const FusedArgs &a, int nw, int grid, hipStream_t st);
 // Resident kernels (np <= 128: 8 waves for np 112..128, split-row 12 waves for np 80..96,
 // 4 waves for np <= 64).
 int resident_max_blocks_per_cu(int nw);
+// One wave per matrix of real order <= 16 (expm_tiny.hip): persistent launch over the sweep
+// described by a (queue range or static range), PLAIN or ALPHA rule.
+int tiny_max_blocks_per_cu();
+int tiny_waves_per_block();
+hipError_t launch_tiny(const FusedArgs &a, int grid, hipStream_t st);
+// Fourth-order Magnus steps, one system of order n <= 16 per wave (expm_tiny.hip).
+hipError_t launch_magnus4(const double *S0, const double *S1, int64_t s_stride, const double *Yin, double *Yout,
+                          const double *u1, const double *u2, int n, int64_t batch, double h, int sel,
+                          const Consts &k, int32_t *m_out, int32_t *s_out, int32_t *status, int grid,
+                          hipStream_t st);
 hipError_t launch_resident(const FusedArgs &a, int nw, int grid, hipStream_t st);  // nw = 8, 12, 4
 hipError_t launch_order(const int32_t *ns, int64_t batch, int cplx, int32_t *order,
                         unsigned long long *queue, hipStream_t st);

@@ -557,7 +557,8 @@ __global__ void expm_order_kernel(const int32_t *ns, int64_t batch, int cplx, in
     queue[kQBound + 1] = (unsigned long long)start[16 - kResT];       // np <= 128
     queue[kQBound + 2] = (unsigned long long)start[16 - kRes6T];      // np <= 96
     queue[kQBound + 3] = (unsigned long long)start[16 - kSplitT + 1];  // np <= 64
-    queue[kQBound + 4] = (unsigned long long)batch;
+    queue[kQBound + 4] = (unsigned long long)start[15];                // np = 16
+    queue[kQBound + 5] = (unsigned long long)batch;
   }
   __syncthreads();
   for (int64_t b = tid; b < batch; b += blockDim.x) {

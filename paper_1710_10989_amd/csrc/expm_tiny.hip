@@ -1,0 +1,451 @@
+// One wavefront per matrix of real order <= 16: the batched exponential of small matrices and
+// the fourth-order Magnus step built on it (exponential integrators, concluding remarks).
+//
+// At np = 16 the resident workgroup kernels keep three of their four waves idle.  Here every
+// wave takes its own matrix.  A 16 x 16 matrix in the D layout of the 16x16x4 FP64 MFMA is one
+// register quad per lane (lane l, register r: row 4 r + l / 16, column l % 16); that layout is
+// also the B-operand layout of the same MFMA for k rows 4 r .. 4 r + 3, so the right operand
+// of a product is fed from the lane's own registers.  The left operand goes through a 16 x 17
+// LDS tile private to the wave (odd stride: the 16 rows of a fragment read fall in distinct
+// banks).  No workgroup barrier is needed: one wave's LDS operations complete in issue order,
+// and a wavefront-scope fence keeps the compiler from reordering them.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "coefs.h"
+#include "expm_fused.h"
+#include "expm_internal.h"
+#include "tile_gemm.h"
+
+namespace expm {
+namespace {
+
+constexpr int kTinyW = 4;          // waves per workgroup
+constexpr int kTinyLd = 17;        // LDS row stride (doubles)
+constexpr int kTinyTile = 16 * kTinyLd;
+
+typedef double q4[4];
+
+__device__ inline void wsync() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+
+__device__ inline int lane_id() { return threadIdx.x & 63; }
+
+// A wave-uniform double in scalar registers.
+__device__ inline double tuni(double x) {
+  const long long u = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readfirstlane((int)u);
+  const int hi = __builtin_amdgcn_readfirstlane((int)(u >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+struct TLane {
+  int lr, lk;
+  __device__ TLane() {
+    const int l = lane_id();
+    lr = l & 15;
+    lk = l >> 4;
+  }
+  __device__ int row(int r) const { return 4 * r + lk; }
+  __device__ double delta(int r) const { return 4 * r + lk == lr ? 1.0 : 0.0; }
+};
+
+__device__ inline void t_zero(q4 &x) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) x[r] = 0.0;
+}
+
+__device__ inline void t_copy(q4 &d, const q4 &x) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) d[r] = x[r];
+}
+
+// LDS tile <- register matrix (own elements).
+__device__ inline void t_put(double *L, const TLane &ln, const q4 &x) {
+  wsync();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) L[ln.row(r) * kTinyLd + ln.lr] = x[r];
+  wsync();
+}
+
+// acc += L * R, L in the wave's LDS tile, R in registers.
+__device__ inline void t_gemm(const double *L, const TLane &ln, const q4 &R, q4 &acc) {
+  dbl4 c = {acc[0], acc[1], acc[2], acc[3]};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) c = __builtin_amdgcn_mfma_f64_16x16x4f64(L[ln.lr * kTinyLd + 4 * q + ln.lk], R[q], c, 0, 0, 0);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) acc[r] = c[r];
+}
+
+// acc += L * L.
+__device__ inline void t_gemm_sq(const double *L, const TLane &ln, q4 &acc) {
+  dbl4 c = {acc[0], acc[1], acc[2], acc[3]};
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(L[ln.lr * kTinyLd + 4 * q + ln.lk], L[ln.row(q) * kTinyLd + ln.lr], c, 0,
+                                             0, 0);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) acc[r] = c[r];
+}
+
+// 1-norm (largest column sum of |x|), the same value on every lane.
+__device__ inline double t_norm1(const q4 &x) {
+  double s = fabs(x[0]) + fabs(x[1]) + fabs(x[2]) + fabs(x[3]);
+  s += __shfl_xor(s, 16);
+  s += __shfl_xor(s, 32);
+#pragma unroll
+  for (int o = 1; o < 16; o <<= 1) s = fmax(s, __shfl_xor(s, o));
+  return tuni(s);
+}
+
+// Loads matrix (n x n real, or the real form [[X, -Y], [Y, X]] of an nin x nin interleaved
+// complex matrix, n = 2 nin) zero-padded to 16 x 16.
+__device__ inline void t_load(const double *A, int n, int nin, int cx, const TLane &ln, q4 &x) {
+  cgdouble *Ag = gptr(A);
+  const int c = ln.lr;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = ln.row(r);
+    double v = 0.0;
+    if (row < n && c < n) {
+      if (!cx) {
+        v = Ag[row * n + c];
+      } else {
+        const int ri = row < nin ? row : row - nin, ci = c < nin ? c : c - nin;
+        const bool im = (row < nin) != (c < nin);
+        v = Ag[2 * (ri * nin + ci) + (im ? 1 : 0)];
+        if (row < nin && c >= nin) v = -v;
+      }
+    }
+    x[r] = v;
+  }
+}
+
+__device__ inline void t_store(double *E, int n, int nin, int cx, const TLane &ln, const q4 &x) {
+  gdouble *Eg = gptr(E);
+  const int c = ln.lr;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = ln.row(r);
+    if (!cx) {
+      if (row < n && c < n) Eg[row * n + c] = x[r];
+    } else if (c < nin) {
+      if (row < nin) Eg[2 * (row * nin + c)] = x[r];
+      else if (row < n) Eg[2 * ((row - nin) * nin + c) + 1] = x[r];
+    }
+  }
+}
+
+// Selection (eq. theta; Table 2), then T_m(A / 2^s) (eqs. Algorithm83eA, poly12, poly.18) and
+// s squarings, all within the wave.  X0 = A on entry; the result is left in AC.  Returns false
+// when only (m, s) was asked for.
+template <int SEL>
+__device__ bool t_expm(const Consts &K, double *L, const TLane &ln, const q4 &X0, double eta, int select_only,
+                       int *m_out, int *s_out, q4 &AC) {
+  int m, s;
+  select_ms(K.theta, 0, eta, -1.0, -1.0, &m, &s);
+  m = __builtin_amdgcn_readfirstlane(m);
+  s = __builtin_amdgcn_readfirstlane(s);
+  const int m_plain = m;
+  q4 X1, X2;
+  if (m_plain >= 2) {
+    t_put(L, ln, X0);
+    t_zero(X1);
+    t_gemm(L, ln, X0, X1);  // A^2
+  }
+  if (m_plain >= 12) {
+    t_zero(X2);
+    t_gemm(L, ln, X1, X2);  // A^3
+  }
+  if (SEL == EXPM_SEL_ALPHA && m_plain >= 2) {
+    // a plain degree below 12 means s = 0 and an alpha degree of at most 8: A^3 is not needed
+    const double n2 = t_norm1(X1), n3 = m_plain >= 12 ? t_norm1(X2) : -1.0;
+    select_ms(K.theta, 1, eta, n2, n3, &m, &s);
+    m = __builtin_amdgcn_readfirstlane(m);
+    s = __builtin_amdgcn_readfirstlane(s);
+  }
+  *m_out = m;
+  *s_out = s;
+  if (select_only) return false;
+  double c[24] = {};
+  make_coefs(K, m, s, c);
+#pragma unroll
+  for (int j = 0; j < 24; ++j) c[j] = tuni(c[j]);
+  if (m == 1) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) AC[r] = ln.delta(r) + c[0] * X0[r];
+  } else if (m == 2) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) AC[r] = ln.delta(r) + c[0] * X0[r] + c[1] * X1[r];
+  } else if (m == 4) {
+    // T = I + c0 A + c1 (A^2 W), A^2 W = (c3 A + c4 A^2) A^2 + c2 A^2
+    q4 W;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) W[r] = c[3] * X0[r] + c[4] * X1[r];
+    t_put(L, ln, W);
+    t_zero(AC);
+    t_gemm(L, ln, X1, AC);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) AC[r] = ln.delta(r) + c[0] * X0[r] + c[1] * (AC[r] + c[2] * X1[r]);
+  } else if (m == 8) {
+    // V = (c0 A + c1 A^2) A^2; A_4 = c2 V; T = (c3 A^2 + A_4)(c4 I + c5 A + c6 A^2 + c7 A_4)
+    //   + c8 I + c9 A + c10 A^2
+    q4 W, V, R;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) W[r] = c[0] * X0[r] + c[1] * X1[r];
+    t_put(L, ln, W);
+    t_zero(V);
+    t_gemm(L, ln, X1, V);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double d = ln.delta(r), a4 = c[2] * V[r];
+      W[r] = c[3] * X1[r] + a4;
+      R[r] = c[4] * d + c[5] * X0[r] + c[6] * X1[r] + c[7] * a4;
+      AC[r] = c[8] * d + c[9] * X0[r] + c[10] * X1[r];
+    }
+    t_put(L, ln, W);
+    t_gemm(L, ln, R, AC);
+  } else if (m == 12) {
+    // B_j over (I, A, A^2, A^3); A_6 = B_3 + B_4 B_4; T = B_1 + (B_2 + A_6) A_6
+    q4 B1, B2, B3, B4;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double d = ln.delta(r);
+      B1[r] = c[0] * d + c[1] * X0[r] + c[2] * X1[r] + c[3] * X2[r];
+      B2[r] = c[4] * d + c[5] * X0[r] + c[6] * X1[r] + c[7] * X2[r];
+      B3[r] = c[8] * d + c[9] * X0[r] + c[10] * X1[r] + c[11] * X2[r];
+      B4[r] = c[12] * d + c[13] * X0[r] + c[14] * X1[r] + c[15] * X2[r];
+    }
+    t_put(L, ln, B4);
+    t_gemm_sq(L, ln, B3);  // A_6
+#pragma unroll
+    for (int r = 0; r < 4; ++r) B2[r] += B3[r];
+    t_put(L, ln, B2);
+    t_copy(AC, B1);
+    t_gemm(L, ln, B3, AC);
+  } else {
+    // A^6 = A^3 A^3; B_1 over (I, A, A^2, A^3), B_2..B_5 over (I, A, A^2, A^3, A^6);
+    // A_9 = B_1 B_5 + B_4; T = B_2 + (B_3 + A_9) A_9
+    q4 X6, B2, B3, B4, B5;
+    t_put(L, ln, X2);
+    t_zero(X6);
+    t_gemm_sq(L, ln, X6);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double d = ln.delta(r), a1 = X0[r], a2 = X1[r], a3 = X2[r], a6 = X6[r];
+      X2[r] = c[0] * d + c[1] * a1 + c[2] * a2 + c[3] * a3;  // B_1
+      B2[r] = c[4] * d + c[5] * a1 + c[6] * a2 + c[7] * a3 + c[8] * a6;
+      B3[r] = c[9] * d + c[10] * a1 + c[11] * a2 + c[12] * a3 + c[13] * a6;
+      B4[r] = c[14] * d + c[15] * a1 + c[16] * a2 + c[17] * a3 + c[18] * a6;
+      B5[r] = c[19] * d + c[20] * a1 + c[21] * a2 + c[22] * a3 + c[23] * a6;
+    }
+    t_put(L, ln, X2);
+    t_gemm(L, ln, B5, B4);  // A_9
+#pragma unroll
+    for (int r = 0; r < 4; ++r) B3[r] += B4[r];
+    t_put(L, ln, B3);
+    t_copy(AC, B2);
+    t_gemm(L, ln, B4, AC);
+  }
+  for (int q = 0; q < s; ++q) {
+    t_put(L, ln, AC);
+    t_zero(AC);
+    t_gemm_sq(L, ln, AC);
+  }
+  return true;
+}
+
+__device__ inline void copy_consts(const Consts &src, Consts *dst) {
+  const double *s = reinterpret_cast<const double *>(&src);
+  double *d = reinterpret_cast<double *>(dst);
+  for (int e = threadIdx.x; e < (int)(sizeof(Consts) / sizeof(double)); e += blockDim.x) d[e] = s[e];
+  __syncthreads();
+}
+
+// Next matrix of this wave: from the work queue (one atomic per matrix) or, without a queue,
+// a static stride over [lo, hi).
+struct TSweep {
+  int64_t lo, hi, next, stride;
+  unsigned long long *ctr;
+  __device__ explicit TSweep(const FusedArgs &a) {
+    const int64_t wave = (int64_t)blockIdx.x * kTinyW + (threadIdx.x >> 6);
+    if (a.queue) {
+      lo = (int64_t)a.queue[kQBound + a.q_lo];
+      hi = (int64_t)a.queue[kQBound + a.q_hi];
+      ctr = &a.queue[a.q_ctr];
+    } else {
+      lo = a.lo;
+      hi = a.hi;
+      ctr = nullptr;
+    }
+    next = lo + wave;
+    stride = (int64_t)gridDim.x * kTinyW;
+  }
+  __device__ int64_t pop() {
+    int64_t idx;
+    if (ctr) {
+      unsigned long long v = 0;
+      if (lane_id() == 0) v = atomicAdd(ctr, 1ull);
+      v = __shfl(v, 0);
+      idx = lo + (int64_t)v;
+    } else {
+      idx = next;
+      next += stride;
+    }
+    const unsigned long long u = (unsigned long long)idx;
+    return (int64_t)(((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(u >> 32)) << 32) |
+                     (unsigned)__builtin_amdgcn_readfirstlane((int)u));
+  }
+};
+
+template <int SEL>
+__global__ __launch_bounds__(64 * kTinyW) void expm_tiny_kernel(FusedArgs a) {
+  __shared__ double tiles[kTinyW * kTinyTile];
+  __shared__ Consts K;
+  copy_consts(a.k, &K);
+  double *L = tiles + (threadIdx.x >> 6) * kTinyTile;
+  const TLane ln;
+  TSweep sw(a);
+  for (;;) {
+    const int64_t idx = sw.pop();
+    if (idx >= sw.hi) break;
+    const int64_t b = a.order ? (int64_t)__builtin_amdgcn_readfirstlane(a.order[idx]) : idx;
+    const int nin = __builtin_amdgcn_readfirstlane(a.ns ? a.ns[b] : a.n_uniform);
+    const int cx = a.cplx;
+    const int n = cx ? 2 * nin : nin;
+    const int64_t off = (a.offs ? a.offs[b] : b * (int64_t)nin * nin) * (cx ? 2 : 1);
+    const bool head = lane_id() == 0;
+    if (nin < 1 || n > 16) {
+      if (head) {
+        a.m_out[b] = -1; a.s_out[b] = -1;
+        if (a.status) a.status[b] = (nin < 1 || n > a.np_max) ? EXPM_E_INVALID_ARG : EXPM_E_UNSUPPORTED;
+      }
+      continue;
+    }
+    q4 X0, AC;
+    t_load(a.A + off, n, nin, cx, ln, X0);
+    const bool bad = __any(!isfinite(X0[0]) || !isfinite(X0[1]) || !isfinite(X0[2]) || !isfinite(X0[3]));
+    if (bad) {
+      if (a.E)
+        for (int e = lane_id(); e < nin * nin * (cx ? 2 : 1); e += 64) a.E[off + e] = __builtin_nan("");
+      if (head) {
+        a.m_out[b] = -1; a.s_out[b] = -1;
+        if (a.status) a.status[b] = EXPM_E_NONFINITE;
+      }
+      continue;
+    }
+    int m, s;
+    const bool full = t_expm<SEL>(K, L, ln, X0, t_norm1(X0), a.select_only, &m, &s, AC);
+    if (head) {
+      a.m_out[b] = m; a.s_out[b] = s;
+      if (a.status) a.status[b] = EXPM_OK;
+    }
+    if (full) t_store(a.E + off, n, nin, cx, ln, AC);
+  }
+}
+
+struct MagnusArgs {
+  const double *S0, *S1, *Yin;
+  double *Yout;
+  const double *u1, *u2;
+  int32_t *m_out, *s_out, *status;
+  int64_t batch, s_stride;
+  int n;
+  double h, k_comm;  // h and sqrt(3) h^2 / 12
+  Consts k;
+};
+
+// One fourth-order Magnus step per wave:
+//   Omega = h S0 + (h/2)(u1 + u2) S1 + (sqrt(3) h^2 / 12)(u1 - u2)(S0 S1 - S1 S0),
+//   Y <- e^Omega Y.
+template <int SEL>
+__global__ __launch_bounds__(64 * kTinyW) void expm_magnus4_kernel(MagnusArgs a) {
+  __shared__ double tiles[kTinyW * kTinyTile];
+  __shared__ Consts K;
+  copy_consts(a.k, &K);
+  double *L = tiles + (threadIdx.x >> 6) * kTinyTile;
+  const TLane ln;
+  const int n = a.n;
+  const int64_t stride = (int64_t)gridDim.x * kTinyW;
+  for (int64_t b = (int64_t)blockIdx.x * kTinyW + (threadIdx.x >> 6); b < a.batch; b += stride) {
+    const bool head = lane_id() == 0;
+    const int64_t so = b * a.s_stride, yo = b * (int64_t)n * n;
+    q4 S0, S1, Y, C, AC;
+    t_load(a.S0 + so, n, n, 0, ln, S0);
+    t_load(a.S1 + so, n, n, 0, ln, S1);
+    t_load(a.Yin + yo, n, n, 0, ln, Y);
+    const double u1 = tuni(a.u1[b]), u2 = tuni(a.u2[b]);
+    bool bad = !isfinite(u1) || !isfinite(u2);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bad = bad || !isfinite(S0[r]) || !isfinite(S1[r]) || !isfinite(Y[r]);
+    if (__any(bad)) {
+      for (int e = lane_id(); e < n * n; e += 64) a.Yout[yo + e] = __builtin_nan("");
+      if (head) {
+        a.m_out[b] = -1; a.s_out[b] = -1;
+        if (a.status) a.status[b] = EXPM_E_NONFINITE;
+      }
+      continue;
+    }
+    // Omega, with the commutator S0 S1 - S1 S0 from two products
+    q4 P, W;
+    t_zero(P);
+    t_put(L, ln, S0);
+    t_gemm(L, ln, S1, P);  // S0 S1
+    t_zero(C);
+    t_put(L, ln, S1);
+    t_gemm(L, ln, S0, C);  // S1 S0
+    const double ca = a.h, cb = 0.5 * a.h * (u1 + u2), cc = a.k_comm * (u1 - u2);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) W[r] = ca * S0[r] + cb * S1[r] + cc * (P[r] - C[r]);
+    int m, s;
+    t_expm<SEL>(K, L, ln, W, t_norm1(W), 0, &m, &s, AC);
+    t_put(L, ln, AC);
+    t_zero(C);
+    t_gemm(L, ln, Y, C);
+    t_store(a.Yout + yo, n, n, 0, ln, C);
+    if (head) {
+      a.m_out[b] = m; a.s_out[b] = s;
+      if (a.status) a.status[b] = EXPM_OK;
+    }
+  }
+}
+
+}  // namespace
+
+int tiny_max_blocks_per_cu() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, expm_tiny_kernel<EXPM_SEL_PLAIN>, 64 * kTinyW, 0) !=
+      hipSuccess)
+    return 1;
+  return nb < 1 ? 1 : nb;
+}
+
+hipError_t launch_tiny(const FusedArgs &a, int grid, hipStream_t st) {
+  if (a.sel == EXPM_SEL_ALPHA)
+    hipLaunchKernelGGL(expm_tiny_kernel<EXPM_SEL_ALPHA>, dim3(grid), dim3(64 * kTinyW), 0, st, a);
+  else
+    hipLaunchKernelGGL(expm_tiny_kernel<EXPM_SEL_PLAIN>, dim3(grid), dim3(64 * kTinyW), 0, st, a);
+  return hipGetLastError();
+}
+
+int tiny_waves_per_block() { return kTinyW; }
+
+hipError_t launch_magnus4(const double *S0, const double *S1, int64_t s_stride, const double *Yin, double *Yout,
+                          const double *u1, const double *u2, int n, int64_t batch, double h, int sel,
+                          const Consts &k, int32_t *m_out, int32_t *s_out, int32_t *status, int grid,
+                          hipStream_t st) {
+  MagnusArgs a;
+  a.S0 = S0; a.S1 = S1; a.Yin = Yin; a.Yout = Yout; a.u1 = u1; a.u2 = u2;
+  a.m_out = m_out; a.s_out = s_out; a.status = status;
+  a.batch = batch; a.s_stride = s_stride; a.n = n;
+  a.h = h;
+  a.k_comm = sqrt(3.0) * h * h / 12.0;
+  a.k = k;
+  if (sel == EXPM_SEL_ALPHA)
+    hipLaunchKernelGGL(expm_magnus4_kernel<EXPM_SEL_ALPHA>, dim3(grid), dim3(64 * kTinyW), 0, st, a);
+  else
+    hipLaunchKernelGGL(expm_magnus4_kernel<EXPM_SEL_PLAIN>, dim3(grid), dim3(64 * kTinyW), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace expm

@@ -142,9 +142,9 @@ def batched(batch, u=None, prec="fp64", selector="plain", workspace=None, out=No
     return E, m, s, status
 
 
-def batched_uniform(A, u=None, prec="fp64", selector="plain", workspace=None, out=None):
+def batched_uniform(A, u=None, prec="fp64", selector="plain", workspace=None, out=None, outs=None):
     """e^A for a stack A of shape (batch, n, n) of same-order matrices (float64 or complex128).
-    Returns (E, m, s, status) device tensors."""
+    outs reuses (m, s, status).  Returns (E, m, s, status) device tensors."""
     if A.dim() != 3 or A.shape[1] != A.shape[2]:
         raise ValueError("A must have shape (batch, n, n)")
     if not A.is_cuda or A.dtype not in (torch.float64, torch.complex128):
@@ -155,10 +155,46 @@ def batched_uniform(A, u=None, prec="fp64", selector="plain", workspace=None, ou
     ws = workspace if workspace is not None else _workspace(
         N.lib().expm_workspace_bytes(n, nb, ctypes.byref(o)), A.device)
     E = out if out is not None else torch.empty_like(A)
-    m = torch.empty(nb, dtype=torch.int32, device=A.device)
-    s = torch.empty_like(m)
-    status = torch.empty_like(m)
+    if outs is not None:
+        m, s, status = outs
+    else:
+        m = torch.empty(nb, dtype=torch.int32, device=A.device)
+        s = torch.empty_like(m)
+        status = torch.empty_like(m)
     st = N.lib().expm_batched_uniform(_ptr(A), _ptr(E), n, nb, ctypes.byref(o), _ptr(m), _ptr(s), _ptr(status),
                                       _ptr(ws), ws.numel(), _stream())
     N.check(st, "expm_batched_uniform")
     return E, m, s, status
+
+
+def magnus4_step(S0, S1, Y, u1, u2, h, u=None, selector="plain", out=None, outs=None):
+    """One fourth-order Magnus step Y <- e^Omega Y for a batch of systems Y' = (S0 + u(t) S1) Y
+    (expm_magnus4_step).  S0, S1: (batch, n, n) or (n, n) shared by all systems; Y: (batch, n, n);
+    u1, u2: (batch,) control values at the two Gauss points; h: step.  float64 device tensors,
+    n <= 16.  out may be Y itself (in place); outs reuses (m, s, status).  Returns
+    (Y_out, m, s, status)."""
+    if Y.dim() != 3 or Y.shape[1] != Y.shape[2]:
+        raise ValueError("Y must have shape (batch, n, n)")
+    nb, n = Y.shape[0], Y.shape[1]
+    for t in (S0, S1, Y, u1, u2):
+        if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+            raise ValueError("inputs must be contiguous float64 device tensors")
+    if S0.shape != S1.shape or S0.shape[-2:] != (n, n) or S0.dim() not in (2, 3):
+        raise ValueError("S0 and S1 must have shape (n, n) or (batch, n, n)")
+    if S0.dim() == 3 and S0.shape[0] != nb:
+        raise ValueError("per-system S0, S1 need one pair per system")
+    if u1.shape != (nb,) or u2.shape != (nb,):
+        raise ValueError("u1 and u2 need one value per system")
+    stride = 0 if S0.dim() == 2 else n * n
+    o = _opts(torch.float64, "fp64", selector, u)
+    Yo = out if out is not None else torch.empty_like(Y)
+    if outs is not None:
+        m, s, status = outs
+    else:
+        m = torch.empty(nb, dtype=torch.int32, device=Y.device)
+        s = torch.empty_like(m)
+        status = torch.empty_like(m)
+    st = N.lib().expm_magnus4_step(_ptr(S0), _ptr(S1), stride, _ptr(Y), _ptr(Yo), _ptr(u1), _ptr(u2), n, nb,
+                                   float(h), ctypes.byref(o), _ptr(m), _ptr(s), _ptr(status), _stream())
+    N.check(st, "expm_magnus4_step")
+    return Yo, m, s, status

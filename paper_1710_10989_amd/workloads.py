@@ -94,3 +94,49 @@ def hermitian_unitary_batch(count=512, n=256, dt_range=(1e-2, 1e2), config_id=5,
         mats.append(-1j * H * dt)
         dts.append(dt)
     return mats, dts
+
+
+def magnus_systems(count=65536, n=16, s0_norm=2.0, s1_norm=1.0, config_id=6, seed_stream=0):
+    """Linear systems Y' = (S0 + u(t) S1) Y on the orthogonal group, the setting of the
+    exponential (Magnus) integrators in the paper's concluding remarks: S0, S1 skew-symmetric
+    (G - G^T, G Gaussian) rescaled to the given 1-norms, the state Y0 a random orthogonal
+    matrix (QR of a Gaussian), and a control u(t) = a cos(w t + phi) per system with a in
+    [0.5, 2], w in [1, 10], phi in [0, 2 pi).  Returns S0, S1, Y0 as (count, n, n) arrays and
+    a, w, phi as (count,) arrays."""
+    g = rng(config_id, seed_stream)
+
+    def skew(norm):
+        G = g.standard_normal((count, n, n))
+        S = G - np.transpose(G, (0, 2, 1))
+        nr = np.abs(S).sum(axis=1).max(axis=1)
+        nr[nr == 0] = 1.0
+        return S * (norm / nr)[:, None, None]
+
+    S0 = skew(s0_norm)
+    S1 = skew(s1_norm)
+    Q, R = np.linalg.qr(g.standard_normal((count, n, n)))
+    Y0 = Q * np.sign(np.diagonal(R, axis1=1, axis2=2))[:, None, :]
+    a = g.uniform(0.5, 2.0, count)
+    w = g.uniform(1.0, 10.0, count)
+    phi = g.uniform(0.0, 2 * np.pi, count)
+    return S0, S1, np.ascontiguousarray(Y0), a, w, phi
+
+
+def control_at_gauss_points(a, w, phi, t, h):
+    """u = a cos(w t + phi) sampled at the two Gauss-Legendre nodes of [t, t + h],
+    t + (1/2 -+ sqrt(3)/6) h; returns (u1, u2)."""
+    c = np.sqrt(3.0) / 6.0
+    return a * np.cos(w * (t + (0.5 - c) * h) + phi), a * np.cos(w * (t + (0.5 + c) * h) + phi)
+
+
+def small_skew_batch(count=65536, n=16, norm_range=(0.05, 1.0), config_id=7, seed_stream=0):
+    """count skew-symmetric n x n matrices (G - G^T) with ||A||_1 log-uniform in norm_range:
+    the small, modest-norm exponents an exponential integrator on the orthogonal group
+    produces at each step.  Returns a (count, n, n) array."""
+    g = rng(config_id, seed_stream)
+    G = g.standard_normal((count, n, n))
+    S = G - np.transpose(G, (0, 2, 1))
+    nr = np.abs(S).sum(axis=1).max(axis=1)
+    nr[nr == 0] = 1.0
+    target = np.exp(g.uniform(np.log(norm_range[0]), np.log(norm_range[1]), count))
+    return np.ascontiguousarray(S * (target / nr)[:, None, None])
