@@ -13,6 +13,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "coefs.h"
 #include "expm_fused.h"
 #include "expm_internal.h"
@@ -136,49 +138,91 @@ __device__ inline void t_store(double *E, int n, int nin, int cx, const TLane &l
   }
 }
 
+// Plain rule (eq. theta, Table 2) on bit patterns: for finite eta >= 0 and theta > 0 the
+// order of the doubles is the order of their bit patterns, and the smallest s >= 0 with
+// eta <= theta 2^s is 0 when eta <= theta, else the exponent difference plus one when eta's
+// mantissa exceeds theta's.  Integer work on wave-uniform values; cost products + s, the
+// cheapest degree wins, ties to the smaller s.
+__device__ inline void t_select_plain(const Consts &K, double eta, int *m_out, int *s_out) {
+  const unsigned long long be = __builtin_bit_cast(unsigned long long, eta);
+  const unsigned long long kFrac = (1ull << 52) - 1;
+  int bm = kDeg[kNumDeg - 1], bs = 0, bc = 1 << 30;
+#pragma unroll
+  for (int i = 0; i < kNumDeg; ++i) {
+    const unsigned long long bt = __builtin_bit_cast(unsigned long long, K.theta[i]);
+    const int si = be <= bt ? 0
+                            : (int)((be >> 52) & 0x7ff) - (int)((bt >> 52) & 0x7ff) + ((be & kFrac) > (bt & kFrac) ? 1 : 0);
+    const int ci = kProducts[i] + si;
+    if (ci < bc || (ci == bc && si < bs)) { bm = kDeg[i]; bs = si; bc = ci; }
+  }
+  *m_out = bm;
+  *s_out = bs;
+}
+
 // Selection (eq. theta; Table 2), then T_m(A / 2^s) (eqs. Algorithm83eA, poly12, poly.18) and
-// s squarings, all within the wave.  X0 = A on entry; the result is left in AC.  Returns false
-// when only (m, s) was asked for.
+// s squarings, all within the wave.  X0 = A on entry; the result is left in AC.  The scaling
+// is applied to the matrices (X = 2^-s A exactly, X^2 = 2^-2s A^2, ...), so the polynomial
+// coefficients are the constants themselves.  Returns false when only (m, s) was asked for.
 template <int SEL>
-__device__ bool t_expm(const Consts &K, double *L, const TLane &ln, const q4 &X0, double eta, int select_only,
+__device__ bool t_expm(const Consts &K, double *L, const TLane &ln, q4 &X0, double eta, int select_only,
                        int *m_out, int *s_out, q4 &AC) {
   int m, s;
-  select_ms(K.theta, 0, eta, -1.0, -1.0, &m, &s);
+  t_select_plain(K, eta, &m, &s);
   m = __builtin_amdgcn_readfirstlane(m);
   s = __builtin_amdgcn_readfirstlane(s);
   const int m_plain = m;
   q4 X1, X2;
+  if (SEL == EXPM_SEL_PLAIN) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) X0[r] = ldexp(X0[r], -s);
+  }
   if (m_plain >= 2) {
     t_put(L, ln, X0);
     t_zero(X1);
-    t_gemm(L, ln, X0, X1);  // A^2
+    t_gemm(L, ln, X0, X1);  // X^2 (A^2 under the alpha rule)
   }
   if (m_plain >= 12) {
     t_zero(X2);
-    t_gemm(L, ln, X1, X2);  // A^3
+    t_gemm(L, ln, X1, X2);  // X^3
   }
-  if (SEL == EXPM_SEL_ALPHA && m_plain >= 2) {
-    // a plain degree below 12 means s = 0 and an alpha degree of at most 8: A^3 is not needed
-    const double n2 = t_norm1(X1), n3 = m_plain >= 12 ? t_norm1(X2) : -1.0;
-    select_ms(K.theta, 1, eta, n2, n3, &m, &s);
-    m = __builtin_amdgcn_readfirstlane(m);
-    s = __builtin_amdgcn_readfirstlane(s);
+  if (SEL == EXPM_SEL_ALPHA) {
+    if (m_plain >= 2) {
+      // a plain degree below 12 means s = 0 and an alpha degree of at most 8: A^3 is not needed
+      const double n2 = t_norm1(X1), n3 = m_plain >= 12 ? t_norm1(X2) : -1.0;
+      select_ms(K.theta, 1, eta, n2, n3, &m, &s);
+      m = __builtin_amdgcn_readfirstlane(m);
+      s = __builtin_amdgcn_readfirstlane(s);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      X0[r] = ldexp(X0[r], -s);
+      X1[r] = ldexp(X1[r], -2 * s);
+      X2[r] = ldexp(X2[r], -3 * s);
+    }
   }
   *m_out = m;
   *s_out = s;
   if (select_only) return false;
-  double c[24] = {};
-  make_coefs(K, m, s, c);
-#pragma unroll
-  for (int j = 0; j < 24; ++j) c[j] = tuni(c[j]);
+  // coefficients of the chosen degree only (scalar registers); the scaling is in the matrices
+  auto coefs = [&](auto deg, double *c, int count) {
+    double t[24];
+    make_coefs(K, decltype(deg)::value, 0, t);
+    for (int j = 0; j < count; ++j) c[j] = tuni(t[j]);
+  };
   if (m == 1) {
+    double c[1];
+    coefs(std::integral_constant<int, 1>(), c, 1);
 #pragma unroll
     for (int r = 0; r < 4; ++r) AC[r] = ln.delta(r) + c[0] * X0[r];
   } else if (m == 2) {
+    double c[2];
+    coefs(std::integral_constant<int, 2>(), c, 2);
 #pragma unroll
     for (int r = 0; r < 4; ++r) AC[r] = ln.delta(r) + c[0] * X0[r] + c[1] * X1[r];
   } else if (m == 4) {
     // T = I + c0 A + c1 (A^2 W), A^2 W = (c3 A + c4 A^2) A^2 + c2 A^2
+    double c[5];
+    coefs(std::integral_constant<int, 4>(), c, 5);
     q4 W;
 #pragma unroll
     for (int r = 0; r < 4; ++r) W[r] = c[3] * X0[r] + c[4] * X1[r];
@@ -190,6 +234,8 @@ __device__ bool t_expm(const Consts &K, double *L, const TLane &ln, const q4 &X0
   } else if (m == 8) {
     // V = (c0 A + c1 A^2) A^2; A_4 = c2 V; T = (c3 A^2 + A_4)(c4 I + c5 A + c6 A^2 + c7 A_4)
     //   + c8 I + c9 A + c10 A^2
+    double c[11];
+    coefs(std::integral_constant<int, 8>(), c, 11);
     q4 W, V, R;
 #pragma unroll
     for (int r = 0; r < 4; ++r) W[r] = c[0] * X0[r] + c[1] * X1[r];
@@ -207,6 +253,8 @@ __device__ bool t_expm(const Consts &K, double *L, const TLane &ln, const q4 &X0
     t_gemm(L, ln, R, AC);
   } else if (m == 12) {
     // B_j over (I, A, A^2, A^3); A_6 = B_3 + B_4 B_4; T = B_1 + (B_2 + A_6) A_6
+    double c[16];
+    coefs(std::integral_constant<int, 12>(), c, 16);
     q4 B1, B2, B3, B4;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -226,6 +274,8 @@ __device__ bool t_expm(const Consts &K, double *L, const TLane &ln, const q4 &X0
   } else {
     // A^6 = A^3 A^3; B_1 over (I, A, A^2, A^3), B_2..B_5 over (I, A, A^2, A^3, A^6);
     // A_9 = B_1 B_5 + B_4; T = B_2 + (B_3 + A_9) A_9
+    double c[24];
+    coefs(std::integral_constant<int, 18>(), c, 24);
     q4 X6, B2, B3, B4, B5;
     t_put(L, ln, X2);
     t_zero(X6);
@@ -298,49 +348,77 @@ struct TSweep {
   }
 };
 
+// Matrix of a queue entry: index, orders and element offset, read by the whole wave.
+struct TItem {
+  int64_t b, off;
+  int nin, n;
+};
+
+__device__ inline TItem t_item(const FusedArgs &a, int64_t idx) {
+  TItem it;
+  it.b = a.order ? (int64_t)__builtin_amdgcn_readfirstlane(a.order[idx]) : idx;
+  it.nin = __builtin_amdgcn_readfirstlane(a.ns ? a.ns[it.b] : a.n_uniform);
+  it.n = a.cplx ? 2 * it.nin : it.nin;
+  it.off = (a.offs ? a.offs[it.b] : it.b * (int64_t)it.nin * it.nin) * (a.cplx ? 2 : 1);
+  return it;
+}
+
+// Persistent: each wave takes matrices from its sweep until the range is empty.  The next
+// matrix's load is issued before the current one is computed, so every wave keeps an HBM
+// read in flight while its MFMA chain runs.
 template <int SEL>
-__global__ __launch_bounds__(64 * kTinyW) void expm_tiny_kernel(FusedArgs a) {
+__global__ __launch_bounds__(64 * kTinyW, SEL == EXPM_SEL_PLAIN ? 4 : 2) void expm_tiny_kernel(FusedArgs a) {
   __shared__ double tiles[kTinyW * kTinyTile];
   __shared__ Consts K;
   copy_consts(a.k, &K);
   double *L = tiles + (threadIdx.x >> 6) * kTinyTile;
   const TLane ln;
+  const int cx = a.cplx;
   TSweep sw(a);
-  for (;;) {
-    const int64_t idx = sw.pop();
-    if (idx >= sw.hi) break;
-    const int64_t b = a.order ? (int64_t)__builtin_amdgcn_readfirstlane(a.order[idx]) : idx;
-    const int nin = __builtin_amdgcn_readfirstlane(a.ns ? a.ns[b] : a.n_uniform);
-    const int cx = a.cplx;
-    const int n = cx ? 2 * nin : nin;
-    const int64_t off = (a.offs ? a.offs[b] : b * (int64_t)nin * nin) * (cx ? 2 : 1);
+  int64_t idx = sw.pop();
+  TItem cur;
+  q4 Xc;
+  if (idx < sw.hi) {
+    cur = t_item(a, idx);
+    if (cur.nin >= 1 && cur.n <= 16) t_load(a.A + cur.off, cur.n, cur.nin, cx, ln, Xc);
+  }
+  while (idx < sw.hi) {
+    const int64_t nidx = sw.pop();
+    TItem nxt;
+    q4 Xn;
+    if (nidx < sw.hi) {
+      nxt = t_item(a, nidx);
+      if (nxt.nin >= 1 && nxt.n <= 16) t_load(a.A + nxt.off, nxt.n, nxt.nin, cx, ln, Xn);
+    }
+    const int64_t b = cur.b;
+    const int nin = cur.nin, n = cur.n;
+    const int64_t off = cur.off;
     const bool head = lane_id() == 0;
     if (nin < 1 || n > 16) {
       if (head) {
         a.m_out[b] = -1; a.s_out[b] = -1;
         if (a.status) a.status[b] = (nin < 1 || n > a.np_max) ? EXPM_E_INVALID_ARG : EXPM_E_UNSUPPORTED;
       }
-      continue;
-    }
-    q4 X0, AC;
-    t_load(a.A + off, n, nin, cx, ln, X0);
-    const bool bad = __any(!isfinite(X0[0]) || !isfinite(X0[1]) || !isfinite(X0[2]) || !isfinite(X0[3]));
-    if (bad) {
+    } else if (__any(!isfinite(Xc[0]) || !isfinite(Xc[1]) || !isfinite(Xc[2]) || !isfinite(Xc[3]))) {
       if (a.E)
         for (int e = lane_id(); e < nin * nin * (cx ? 2 : 1); e += 64) a.E[off + e] = __builtin_nan("");
       if (head) {
         a.m_out[b] = -1; a.s_out[b] = -1;
         if (a.status) a.status[b] = EXPM_E_NONFINITE;
       }
-      continue;
+    } else {
+      q4 AC;
+      int m, s;
+      const bool full = t_expm<SEL>(K, L, ln, Xc, t_norm1(Xc), a.select_only, &m, &s, AC);
+      if (head) {
+        a.m_out[b] = m; a.s_out[b] = s;
+        if (a.status) a.status[b] = EXPM_OK;
+      }
+      if (full) t_store(a.E + off, n, nin, cx, ln, AC);
     }
-    int m, s;
-    const bool full = t_expm<SEL>(K, L, ln, X0, t_norm1(X0), a.select_only, &m, &s, AC);
-    if (head) {
-      a.m_out[b] = m; a.s_out[b] = s;
-      if (a.status) a.status[b] = EXPM_OK;
-    }
-    if (full) t_store(a.E + off, n, nin, cx, ln, AC);
+    idx = nidx;
+    cur = nxt;
+    t_copy(Xc, Xn);
   }
 }
 
@@ -359,7 +437,7 @@ struct MagnusArgs {
 //   Omega = h S0 + (h/2)(u1 + u2) S1 + (sqrt(3) h^2 / 12)(u1 - u2)(S0 S1 - S1 S0),
 //   Y <- e^Omega Y.
 template <int SEL>
-__global__ __launch_bounds__(64 * kTinyW) void expm_magnus4_kernel(MagnusArgs a) {
+__global__ __launch_bounds__(64 * kTinyW, SEL == EXPM_SEL_PLAIN ? 4 : 2) void expm_magnus4_kernel(MagnusArgs a) {
   __shared__ double tiles[kTinyW * kTinyTile];
   __shared__ Consts K;
   copy_consts(a.k, &K);
