@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <initializer_list>
 #include <map>
 #include <mutex>
 
@@ -201,9 +202,9 @@ size_t expm_workspace_bytes(int64_t n_max, int64_t batch, const expm_opts_t *opt
 // stage: -1 all phases; 0 sort the batch into the work queue; 1 sweep of the 8-wave resident
 // kernel (real orders 112..128); 2 sweeps of every other order, i.e. stages 3, 4, 5 in turn:
 // 3 np 144..256 on the 8-wave global-memory kernel, 4 np 80..96 on the split-row resident
-// kernel, 5 np 32..64 on the 4-wave resident kernel and np 16 on the one-wave kernel.  Stages 1..5 need stage 0 first and are
-// independent of each other.  Feature rows (learned selector) run on the global-memory
-// kernels.
+// kernel, 5 np 32..64 on the 4-wave resident kernel and np 16 on the one-wave kernel.
+// Stages 1..5 need stage 0 first and are independent of each other.  Feature rows (learned
+// selector) run on the global-memory kernels.
 static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, const int32_t *ns,
                                int64_t batch, int64_t n_uniform, int64_t n_max,
                                const expm_opts_t *opts, double u, int32_t *m_dev, int32_t *s_dev,
@@ -287,22 +288,27 @@ static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, cons
     // runs the 8-wave resident sweep on the caller's stream and the other sweeps beside it on
     // a second stream (fork after the sort, join before return), so the sweeps share the CUs
     // instead of each waiting for the previous one's last matrices.
+    // sub-sweeps: 3 np 144..256, 4 np 80..96, 5 np 32..64 (np <= 64 without the one-wave
+    // kernel), 6 np 16 on the one-wave kernel
     auto sub = [&](int k) -> bool {
       switch (k) {
         case 3: return tmax <= kResT || go(K_FUSED8, f8, 0, 0, 1);
         case 4: return tmax < kSplitT || go(K_RES6, r6, 2, 2, 3);
-        default: return tiny ? go(K_RES4, r4, 3, 3, 4) && go(K_TINY, tn, 5, 4, 5) : go(K_RES4, r4, 3, 3, 5);
+        case 5: return tiny ? go(K_RES4, r4, 3, 3, 4) : go(K_RES4, r4, 3, 3, 5);
+        default: return !tiny || go(K_TINY, tn, 5, 4, 5);
       }
     };
-    auto stage2 = [&](hipStream_t s2) -> bool {
+    auto on = [&](hipStream_t s2, std::initializer_list<int> ks) -> bool {
       const hipStream_t keep = st;
       st = s2;
-      const bool ok = sub(3) && sub(4) && sub(5);
+      bool ok = true;
+      for (int k : ks) ok = ok && sub(k);
       st = keep;
       return ok;
     };
     if (stage == 1) return (tmax <= kRes6T || go(K_RES8, r8, 1, 1, 2)) ? EXPM_OK : EXPM_E_HIP;
-    if (stage == 2) return stage2(st) ? EXPM_OK : EXPM_E_HIP;
+    if (stage == 2) return on(st, {3, 4, 5, 6}) ? EXPM_OK : EXPM_E_HIP;
+    if (stage == 5) return on(st, {5, 6}) ? EXPM_OK : EXPM_E_HIP;
     if (stage >= 3) return sub(stage) ? EXPM_OK : EXPM_E_HIP;
     if (stage == -1) {
       std::lock_guard<std::mutex> lk(g_fj_mu);
@@ -310,8 +316,9 @@ static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, cons
       if (!fork_join_for_device(&fj)) return EXPM_E_HIP;
       if (hipEventRecord(fj.fork, st) != hipSuccess || hipStreamWaitEvent(fj.side, fj.fork, 0) != hipSuccess)
         return EXPM_E_HIP;
-      const bool ok2 = stage2(fj.side);
-      const bool ok1 = tmax <= kRes6T || go(K_RES8, r8, 1, 1, 2);
+      // the second stream takes the longer chain; the order-16 sweep follows the 8-wave one
+      const bool ok2 = on(fj.side, {3, 4, 5});
+      const bool ok1 = (tmax <= kRes6T || go(K_RES8, r8, 1, 1, 2)) && sub(6);
       if (hipEventRecord(fj.join, fj.side) != hipSuccess || hipStreamWaitEvent(st, fj.join, 0) != hipSuccess)
         return EXPM_E_HIP;
       if (!ok1 || !ok2) return EXPM_E_HIP;

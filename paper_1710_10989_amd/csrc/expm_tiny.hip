@@ -312,39 +312,28 @@ __device__ inline void copy_consts(const Consts &src, Consts *dst) {
   __syncthreads();
 }
 
-// Next matrix of this wave: from the work queue (one atomic per matrix) or, without a queue,
-// a static stride over [lo, hi).
+// Matrices of this wave: a static stride over the sweep's range [lo, hi), read from the
+// work queue's bounds when there is a queue.  Matrices of one padded order cost about the
+// same, and one atomic per matrix on a counter shared by thousands of waves would serialise
+// in L2, so this sweep takes no counter.
 struct TSweep {
   int64_t lo, hi, next, stride;
-  unsigned long long *ctr;
   __device__ explicit TSweep(const FusedArgs &a) {
     const int64_t wave = (int64_t)blockIdx.x * kTinyW + (threadIdx.x >> 6);
     if (a.queue) {
       lo = (int64_t)a.queue[kQBound + a.q_lo];
       hi = (int64_t)a.queue[kQBound + a.q_hi];
-      ctr = &a.queue[a.q_ctr];
     } else {
       lo = a.lo;
       hi = a.hi;
-      ctr = nullptr;
     }
     next = lo + wave;
     stride = (int64_t)gridDim.x * kTinyW;
   }
   __device__ int64_t pop() {
-    int64_t idx;
-    if (ctr) {
-      unsigned long long v = 0;
-      if (lane_id() == 0) v = atomicAdd(ctr, 1ull);
-      v = __shfl(v, 0);
-      idx = lo + (int64_t)v;
-    } else {
-      idx = next;
-      next += stride;
-    }
-    const unsigned long long u = (unsigned long long)idx;
-    return (int64_t)(((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(u >> 32)) << 32) |
-                     (unsigned)__builtin_amdgcn_readfirstlane((int)u));
+    const int64_t idx = next;
+    next += stride;
+    return idx;
   }
 };
 
