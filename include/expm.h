@@ -123,10 +123,10 @@ EXPM_API expm_status_t expm_taylor(const void *A_dev, void *E_dev, int64_t n, co
  * of A_dev and E_dev (elements of the dtype, not bytes).  n_dev[b] = n_b (int32).  Outputs per
  * matrix: m_dev[b], s_dev[b], status_dev[b].  A device kernel sorts the batch largest order
  * first; persistent launches walk that work queue; no host synchronisation
- * (graph-capturable).  The sweep of real orders 112..128 runs on `stream`, the other sweeps
- * on a second stream of the device that the library creates once (default priority); it
- * waits for the sort and `stream` waits for it before the call's work ends, so the call
- * behaves as one operation on `stream` (also under graph capture).  Larger orders:
+ * (graph-capturable).  The sweeps of real orders 112..128 and <= 16 run on `stream`, the
+ * other sweeps on a second stream of the device that the library creates once (default
+ * priority); it waits for the sort and `stream` waits for it before the call's work ends, so
+ * the call behaves as one operation on `stream` (also under graph capture).  Larger orders:
  * EXPM_E_UNSUPPORTED (use expm_batched_uniform). */
 EXPM_API expm_status_t expm_batched(const void *A_dev, void *E_dev, const int64_t *offsets_dev,
                            const int32_t *n_dev, int64_t batch, int64_t n_max,
@@ -137,12 +137,13 @@ EXPM_API expm_status_t expm_batched(const void *A_dev, void *E_dev, const int64_
  * the device work queue (largest real order first); stage 1 runs the 8-wave on-chip kernel
  * over the real orders 112..128 of the queue; stage 2 runs the sweeps of every other order,
  * which are stages 3, 4 and 5 in turn: 3 the real orders 144..256 on the 8-wave global-memory
- * kernel, 4 the orders 80..96 on the split-row on-chip kernel, 5 the orders up to 64 on the
- * 4-wave on-chip kernel.  Stages 1..5 need stage 0 to have completed and are independent of
- * each other (separate workspace slots and queue counters, so they may run on different
- * streams).  Calling 0, 1, 2 (or 0, 1, 3, 4, 5) in order on one stream gives exactly the
- * results of expm_batched, which itself runs stage 1 beside stage 2 on a second stream.
- * Arguments as expm_batched; stage outside 0..5 is EXPM_E_INVALID_ARG. */
+ * kernel, 4 the orders 80..96 on the split-row on-chip kernel, 5 the orders up to 64 (17..64
+ * on the 4-wave on-chip kernel, up to 16 on one wave per matrix, or all on the 4-wave kernel
+ * under the learned selector).  Stages 1..5 need stage 0 to have completed and are
+ * independent of each other (separate workspace slots and queue ranges, so they may run on
+ * different streams).  Calling 0, 1, 2 (or 0, 1, 3, 4, 5) in order on one stream gives
+ * exactly the results of expm_batched.  Arguments as expm_batched; stage outside 0..5 is
+ * EXPM_E_INVALID_ARG. */
 EXPM_API expm_status_t expm_batched_stage(const void *A_dev, void *E_dev, const int64_t *offsets_dev,
                                  const int32_t *n_dev, int64_t batch, int64_t n_max,
                                  const expm_opts_t *opts, int32_t *m_dev, int32_t *s_dev,
