@@ -62,9 +62,17 @@ typedef enum { EXPM_F64 = 0, EXPM_C128 = 1 } expm_dtype_t;
  * comparison and the linear combinations stay FP64.  EXPM_PREC_FP32: operands rounded to
  * FP32, FP32 accumulation.  EXPM_PREC_BF16X3: each FP64 operand is split into three bfloat16
  * terms (hi + mid + lo), six of the nine cross products (lo*lo, mid*lo, lo*mid dropped) are
- * accumulated in FP32.  Default u: 2^-24 for FP32, 2^-53 for FP64 and BF16X3.  Reduced forms
- * always run the tiled path (any order). */
-typedef enum { EXPM_PREC_FP64 = 0, EXPM_PREC_FP32 = 1, EXPM_PREC_BF16X3 = 2 } expm_prec_t;
+ * accumulated in FP32.  EXPM_PREC_FP32_ALL: the single-precision form of the paper's second
+ * theta row (Table 2, u = 2^-24): every product, the last one of the stage and the squarings
+ * included, in FP32 (operands rounded to FP32, FP32 accumulation); norms, selection, linear
+ * combinations and storage stay FP64 (O(n^2) work).  Default u: 2^-24 for FP32 and FP32_ALL,
+ * 2^-53 for FP64 and BF16X3.  Reduced forms always run the tiled path (any order). */
+typedef enum {
+  EXPM_PREC_FP64 = 0,
+  EXPM_PREC_FP32 = 1,
+  EXPM_PREC_BF16X3 = 2,
+  EXPM_PREC_FP32_ALL = 3
+} expm_prec_t;
 
 /* How (m, s) is chosen.
  *  PLAIN:   from eta = ||A||_1 (Sec. 4: an estimate of the norm drives the choice).

@@ -36,12 +36,12 @@ int np_max_t(int64_t n) { return (int)(pad16(n) >> 4); }
 
 // FP64 and BF16X3 target the double row of the thresholds (truncation below 1e-15, so the
 // split's FP32 accumulation dominates the error); FP32 uses the single row.
-double default_u(int prec) { return prec == EXPM_PREC_FP32 ? 0x1p-24 : 0x1p-53; }
+double default_u(int prec) { return prec == EXPM_PREC_FP32 || prec == EXPM_PREC_FP32_ALL ? 0x1p-24 : 0x1p-53; }
 
 expm_status_t check_opts(const expm_opts_t *o, double *u) {
   if (!o) return EXPM_E_INVALID_ARG;
   if (o->dtype != EXPM_F64 && o->dtype != EXPM_C128) return EXPM_E_INVALID_ARG;
-  if (o->prec < EXPM_PREC_FP64 || o->prec > EXPM_PREC_BF16X3) return EXPM_E_INVALID_ARG;
+  if (o->prec < EXPM_PREC_FP64 || o->prec > EXPM_PREC_FP32_ALL) return EXPM_E_INVALID_ARG;
   if (o->sel < EXPM_SEL_PLAIN || o->sel > EXPM_SEL_LEARNED) return EXPM_E_INVALID_ARG;
   if (o->flags != 0) return EXPM_E_INVALID_ARG;
   double uu = o->u == 0.0 ? default_u(o->prec) : o->u;

@@ -333,7 +333,9 @@ struct Launcher {
     a.kind = kind; a.p = p; a.q = q; a.dst = dst; a.in0 = in0; a.in1 = in1; a.round = round;
     for (int j = 0; j < 5; ++j) a.o[j] = j < (int)o.size() ? o[j] : SEL_NONE;
     const int tiles = (int)((L.np / kLargeTile) * (L.np / kLargeTile));
-    const int pr = reduced ? prec : PREC_F64;
+    // EXPM_PREC_FP32_ALL: every product in FP32; otherwise the reduced form covers the powers
+    // and the first product of the stage, and the rest stays FP64
+    const int pr = prec == EXPM_PREC_FP32_ALL ? PREC_F32 : reduced ? prec : PREC_F64;
     if (pr == PREC_F32) hipLaunchKernelGGL(lg_gemm_kernel<PREC_F32>, dim3(tiles, (unsigned)idx.size()), dim3(512), 0, st, a);
     else if (pr == PREC_BF16X3)
       hipLaunchKernelGGL(lg_gemm_kernel<PREC_BF16X3>, dim3(tiles, (unsigned)idx.size()), dim3(512), 0, st, a);

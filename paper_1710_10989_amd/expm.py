@@ -10,7 +10,8 @@ import torch
 
 from . import _native as N
 
-_PREC = {"fp64": N.EXPM_PREC_FP64, "fp32": N.EXPM_PREC_FP32, "bf16x3": N.EXPM_PREC_BF16X3}
+_PREC = {"fp64": N.EXPM_PREC_FP64, "fp32": N.EXPM_PREC_FP32, "bf16x3": N.EXPM_PREC_BF16X3,
+         "fp32all": N.EXPM_PREC_FP32_ALL}
 _SEL = {"plain": N.EXPM_SEL_PLAIN, "alpha": N.EXPM_SEL_ALPHA, "learned": N.EXPM_SEL_LEARNED}
 
 

@@ -67,3 +67,24 @@ def test_reduced_forms_uniform_batch(P, orc):
         torch.cuda.synchronize()
         for i in range(3):
             assert orc.rel_err_1(E[i].cpu().numpy(), refs[i]) <= 1e-6
+
+
+@pytest.mark.parametrize("norm", [0.5, 8.0, 50.0])
+def test_all_single_form(P, orc, norm):
+    # every product (squarings included) in FP32 with the u = 2^-24 thresholds: the error is
+    # that of FP32 products, about sqrt(n) 2^-24 per product, doubled by each squaring
+    from paper_1710_10989_amd import workloads as W
+    n = 320
+    A = W.large_dense(1, n, norm_range=(norm, norm), seed_stream=int(norm * 10))[0]
+    ref, _ = orc.expm_taylor(A, prec="d")
+    for sel in ("plain", "alpha"):
+        E, m, s, st = P.taylor(torch.from_numpy(A).cuda(), prec="fp32all", selector=sel)
+        torch.cuda.synchronize()
+        assert int(st.item()) == 0
+        m, s = int(m.item()), int(s.item())
+        err = orc.rel_err_1(E.cpu().numpy(), ref)
+        bound = 4.0 * np.sqrt(n) * 2.0 ** -24 * 2.0 ** s
+        say("  fp32all %s (m, s)=(%d, %d) rel err %.3e bound %.3e" % (sel, m, s, err, bound))
+        assert err <= bound
+        if sel == "plain":
+            assert (m, s) == orc.select_plain(orc.norm1(A), 2.0 ** -24)
