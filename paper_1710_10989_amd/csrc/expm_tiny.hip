@@ -105,6 +105,11 @@ __device__ inline double t_norm1(const q4 &x) {
 __device__ inline void t_load(const double *A, int n, int nin, int cx, const TLane &ln, q4 &x) {
   cgdouble *Ag = gptr(A);
   const int c = ln.lr;
+  if (!cx && n == 16) {  // full tile: no bounds to check
+#pragma unroll
+    for (int r = 0; r < 4; ++r) x[r] = Ag[ln.row(r) * 16 + c];
+    return;
+  }
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int row = ln.row(r);
@@ -126,6 +131,11 @@ __device__ inline void t_load(const double *A, int n, int nin, int cx, const TLa
 __device__ inline void t_store(double *E, int n, int nin, int cx, const TLane &ln, const q4 &x) {
   gdouble *Eg = gptr(E);
   const int c = ln.lr;
+  if (!cx && n == 16) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Eg[ln.row(r) * 16 + c] = x[r];
+    return;
+  }
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int row = ln.row(r);
@@ -143,13 +153,17 @@ __device__ inline void t_store(double *E, int n, int nin, int cx, const TLane &l
 // eta <= theta 2^s is 0 when eta <= theta, else the exponent difference plus one when eta's
 // mantissa exceeds theta's.  Integer work on wave-uniform values; cost products + s, the
 // cheapest degree wins, ties to the smaller s.
-__device__ inline void t_select_plain(const Consts &K, double eta, int *m_out, int *s_out) {
+struct Theta {
+  double t[kNumDeg];
+};
+
+__device__ inline void t_select_plain(const Theta &th, double eta, int *m_out, int *s_out) {
   const unsigned long long be = __builtin_bit_cast(unsigned long long, eta);
   const unsigned long long kFrac = (1ull << 52) - 1;
   int bm = kDeg[kNumDeg - 1], bs = 0, bc = 1 << 30;
 #pragma unroll
   for (int i = 0; i < kNumDeg; ++i) {
-    const unsigned long long bt = __builtin_bit_cast(unsigned long long, K.theta[i]);
+    const unsigned long long bt = __builtin_bit_cast(unsigned long long, th.t[i]);
     const int si = be <= bt ? 0
                             : (int)((be >> 52) & 0x7ff) - (int)((bt >> 52) & 0x7ff) + ((be & kFrac) > (bt & kFrac) ? 1 : 0);
     const int ci = kProducts[i] + si;
@@ -164,10 +178,10 @@ __device__ inline void t_select_plain(const Consts &K, double eta, int *m_out, i
 // is applied to the matrices (X = 2^-s A exactly, X^2 = 2^-2s A^2, ...), so the polynomial
 // coefficients are the constants themselves.  Returns false when only (m, s) was asked for.
 template <int SEL>
-__device__ bool t_expm(const Consts &K, double *L, const TLane &ln, q4 &X0, double eta, int select_only,
-                       int *m_out, int *s_out, q4 &AC) {
+__device__ bool t_expm(const Consts &K, const Theta &th, double *L, const TLane &ln, q4 &X0, double eta,
+                       int select_only, int *m_out, int *s_out, q4 &AC) {
   int m, s;
-  t_select_plain(K, eta, &m, &s);
+  t_select_plain(th, eta, &m, &s);
   m = __builtin_amdgcn_readfirstlane(m);
   s = __builtin_amdgcn_readfirstlane(s);
   const int m_plain = m;
@@ -360,6 +374,9 @@ __global__ __launch_bounds__(64 * kTinyW, SEL == EXPM_SEL_PLAIN ? 4 : 2) void ex
   __shared__ double tiles[kTinyW * kTinyTile];
   __shared__ Consts K;
   copy_consts(a.k, &K);
+  Theta th;
+#pragma unroll
+  for (int i = 0; i < kNumDeg; ++i) th.t[i] = a.k.theta[i];
   double *L = tiles + (threadIdx.x >> 6) * kTinyTile;
   const TLane ln;
   const int cx = a.cplx;
@@ -398,7 +415,7 @@ __global__ __launch_bounds__(64 * kTinyW, SEL == EXPM_SEL_PLAIN ? 4 : 2) void ex
     } else {
       q4 AC;
       int m, s;
-      const bool full = t_expm<SEL>(K, L, ln, Xc, t_norm1(Xc), a.select_only, &m, &s, AC);
+      const bool full = t_expm<SEL>(K, th, L, ln, Xc, t_norm1(Xc), a.select_only, &m, &s, AC);
       if (head) {
         a.m_out[b] = m; a.s_out[b] = s;
         if (a.status) a.status[b] = EXPM_OK;
@@ -430,6 +447,9 @@ __global__ __launch_bounds__(64 * kTinyW, SEL == EXPM_SEL_PLAIN ? 4 : 2) void ex
   __shared__ double tiles[kTinyW * kTinyTile];
   __shared__ Consts K;
   copy_consts(a.k, &K);
+  Theta th;
+#pragma unroll
+  for (int i = 0; i < kNumDeg; ++i) th.t[i] = a.k.theta[i];
   double *L = tiles + (threadIdx.x >> 6) * kTinyTile;
   const TLane ln;
   const int n = a.n;
@@ -465,7 +485,7 @@ __global__ __launch_bounds__(64 * kTinyW, SEL == EXPM_SEL_PLAIN ? 4 : 2) void ex
 #pragma unroll
     for (int r = 0; r < 4; ++r) W[r] = ca * S0[r] + cb * S1[r] + cc * (P[r] - C[r]);
     int m, s;
-    t_expm<SEL>(K, L, ln, W, t_norm1(W), 0, &m, &s, AC);
+    t_expm<SEL>(K, th, L, ln, W, t_norm1(W), 0, &m, &s, AC);
     t_put(L, ln, AC);
     t_zero(C);
     t_gemm(L, ln, Y, C);
