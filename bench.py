@@ -40,6 +40,7 @@ import time
 import numpy as np
 
 PRODUCTS = {1: 0, 2: 1, 4: 2, 8: 3, 12: 4, 18: 5}
+PS_PRODUCTS = {1: 0, 2: 1, 4: 2, 6: 3, 9: 4, 12: 5, 16: 6}  # Paterson-Stockmeyer (Table 3)
 PEAK_FP64 = 78.6e12
 PEAK_FP32 = 157.3e12
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -75,8 +76,8 @@ def measured_traffic(tag):
     return d.get("bytes_per_launch")
 
 
-def executed_flops(ms, ss, ns):
-    return float(sum((PRODUCTS[int(m)] + int(s)) * 2.0 * float(n) ** 3 for m, s, n in zip(ms, ss, ns) if m > 0))
+def executed_flops(ms, ss, ns, prods=PRODUCTS):
+    return float(sum((prods[int(m)] + int(s)) * 2.0 * float(n) ** 3 for m, s, n in zip(ms, ss, ns) if m > 0))
 
 
 def cpu_oracle(mats, seconds, label):
@@ -195,13 +196,14 @@ def run_precision(args, torch, P, W):
     A1 = torch.from_numpy(np.stack(mats1)).cuda()
     A4 = torch.from_numpy(np.stack(mats4)).cuda()
     del mats4
-    ws1 = torch.empty(P.workspace_bytes(1024, 256, prec=args.prec), dtype=torch.uint8, device="cuda")
-    ws4 = torch.empty(P.workspace_bytes(4096, 16, prec=args.prec), dtype=torch.uint8, device="cuda")
+    mt = args.method
+    ws1 = torch.empty(P.workspace_bytes(1024, 256, prec=args.prec, method=mt), dtype=torch.uint8, device="cuda")
+    ws4 = torch.empty(P.workspace_bytes(4096, 16, prec=args.prec, method=mt), dtype=torch.uint8, device="cuda")
     E1, E4 = torch.empty_like(A1), torch.empty_like(A4)
 
     def step():
-        r1 = P.batched_uniform(A1, prec=args.prec, selector=args.selector, workspace=ws1, out=E1)
-        r4 = P.batched_uniform(A4, prec=args.prec, selector=args.selector, workspace=ws4, out=E4)
+        r1 = P.batched_uniform(A1, prec=args.prec, selector=args.selector, workspace=ws1, out=E1, method=mt)
+        r4 = P.batched_uniform(A4, prec=args.prec, selector=args.selector, workspace=ws4, out=E4, method=mt)
         return r1, r4
 
     for _ in range(args.warmup):
@@ -215,9 +217,10 @@ def run_precision(args, torch, P, W):
     torch.cuda.synchronize()
     ms_step = t0.elapsed_time(t1) / args.steps
     m1, s1, m4, s4 = (x.cpu().numpy() for x in (m1, s1, m4, s4))
-    flops = executed_flops(m1, s1, [1024] * 256) + executed_flops(m4, s4, [4096] * 16)
+    prods = PS_PRODUCTS if mt == "ps" else PRODUCTS
+    flops = executed_flops(m1, s1, [1024] * 256, prods) + executed_flops(m4, s4, [4096] * 16, prods)
     err = None
-    if args.prec != "fp64":  # error of the form against the FP64 path (itself pinned to the oracle)
+    if args.prec != "fp64" or mt != "reduced":  # error against the FP64 path (pinned to the oracle)
         R1 = P.batched_uniform(A1, selector=args.selector)[0]
         R4 = P.batched_uniform(A4, selector=args.selector)[0]
         torch.cuda.synchronize()
@@ -234,10 +237,11 @@ def run_precision(args, torch, P, W):
             "frac": flops / (ms_step * 1e-3) / peak, "traffic": None, "note": note}
     config = {"workload": "256 FP64 n=1024 + 16 FP64 n=4096, N(0,1)/sqrt(n) scaled to ||A||_1 ~ U[0.5,50]; two "
                           "expm_batched_uniform calls per step", "selector": args.selector, "prec": args.prec,
-              "max_rel_err_vs_fp64_path": err,
-              "mean_products_plus_squarings": float(np.mean([PRODUCTS[int(a)] + int(b) for a, b in
+              "method": mt, "max_rel_err_vs_fp64_path": err,
+              "mean_products_plus_squarings": float(np.mean([prods[int(a)] + int(b) for a, b in
                                                              zip(np.r_[m1, m4], np.r_[s1, s4])]))}
-    return line(args, "expm matrices/s (precision workload, %s)" % args.prec, 272 / (ms_step * 1e-3), ms_step,
+    name = args.prec if mt == "reduced" else "%s, Paterson-Stockmeyer" % args.prec
+    return line(args, "expm matrices/s (precision workload, %s)" % name, 272 / (ms_step * 1e-3), ms_step,
                 {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3+f32", "fp32all": "f32"}[args.prec], config, roof,
                 cpu)
 
@@ -480,6 +484,8 @@ def main():
                                                              "small", "magnus", "copy"])
     ap.add_argument("--selector", default="plain", choices=["plain", "alpha"])
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3", "fp32all"])
+    ap.add_argument("--method", default="reduced", choices=["reduced", "ps"],
+                    help="precision workload: the paper's T_m or the Paterson-Stockmeyer comparison method")
     ap.add_argument("--count", type=int, default=4096)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")

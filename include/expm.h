@@ -83,13 +83,23 @@ typedef enum {
  *           ALPHA bound holds for it, otherwise the PLAIN rule decides (expm_learned_set). */
 typedef enum { EXPM_SEL_PLAIN = 0, EXPM_SEL_ALPHA = 1, EXPM_SEL_LEARNED = 2 } expm_sel_t;
 
+/* Evaluation method of T_m (expm_opts_t.flags).  0: the product-reduced sequences of the
+ * paper (T_8, T_12, T_18 with 3, 4, 5 products).  EXPM_FLAG_PS: the comparison method of
+ * Sec. 4, the plain Taylor polynomial T_m = sum_k A^k / k! evaluated by the Paterson-Stockmeyer
+ * rule in Horner form (eq. poli9), m in {1, 2, 4, 6, 9, 12, 16} with 0..6 products (Table 3)
+ * and thresholds theta_m(u) of the same definition (Table 2); (m, s) by the same cheapest-cost
+ * rule from ||A||_1.  Runs the tiled path (any order) with FP64 products and EXPM_SEL_PLAIN;
+ * other combinations, and the calls that only run the fused kernels (expm_batched,
+ * expm_batched_stage, expm_features, expm_magnus4_step), return EXPM_E_UNSUPPORTED. */
+#define EXPM_FLAG_PS 1
+
 typedef struct {
   int32_t dtype;  /* expm_dtype_t */
   int32_t prec;   /* expm_prec_t */
   int32_t sel;    /* expm_sel_t */
-  int32_t flags;  /* reserved, must be 0 */
-  double u;       /* target relative backward error; 0 = the form's default (2^-53 for FP64,
-                     2^-24 for FP32 / BF16X3) */
+  int32_t flags;  /* 0 or EXPM_FLAG_PS; other bits: EXPM_E_INVALID_ARG */
+  double u;       /* target relative backward error; 0 = the form's default (2^-24 for FP32
+                     and FP32_ALL, 2^-53 otherwise) */
 } expm_opts_t;
 
 /* Human-readable name of a status code (static storage). */
@@ -97,7 +107,7 @@ EXPM_API const char *expm_status_string(expm_status_t st);
 
 /* theta_m(u) (eq. eq.theta): the largest ||X|| for which T_m(X) = e^{X+E} with
  * ||E|| / ||X|| <= u, from the series of log(e^{-x} T_m(x)) cut after 150 terms (Sec. 1).
- * Host-only, no GPU needed.  m in {1, 2, 4, 8, 12, 18}; u in [2^-53, 2^-10]. */
+ * Host-only, no GPU needed.  m in {1, 2, 4, 6, 8, 9, 12, 16, 18}; u in [2^-53, 2^-10]. */
 EXPM_API expm_status_t expm_theta(int32_t m, double u, double *theta_out);
 
 /* The selection rule on the host, identical to the device's (for tests and planning).

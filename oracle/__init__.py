@@ -236,3 +236,47 @@ def magnus4_step(S0, S1, Y, u1, u2, h, prec="ld"):
     Om = magnus4_omega(S0, S1, u1, u2, h)
     E, _ = expm_taylor(Om, prec=prec)
     return E @ np.asarray(Y, dtype=np.float64), Om
+
+
+# ---- Paterson-Stockmeyer comparison method (Sec. 4, eq. poli9, Table 3) ----
+
+PS_DEGREES = (1, 2, 4, 6, 9, 12, 16)
+PS_PRODUCTS = (0, 1, 2, 3, 4, 5, 6)
+
+
+def taylor_poly(X, m):
+    """T_m(X) = sum_{k=0}^{m} X^k / k!, the truncated Taylor series itself (Sec. 1), summed
+    term by term in long double.  Returns a long-double array."""
+    X = np.asarray(X, dtype=np.longdouble)
+    P = np.eye(X.shape[0], dtype=np.longdouble)
+    S = P.copy()
+    for k in range(1, m + 1):
+        P = (P @ X) / k
+        S = S + P
+    return S
+
+
+def select_ps(eta, u=2.0 ** -53):
+    """(m, s) of the comparison method: over the Paterson-Stockmeyer degrees and their product
+    counts (Table 3), s = the smallest s >= 0 with eta <= theta_m 2^s (eq. eq.theta, thresholds
+    of Table 2 recomputed by theta.py), the cheapest products + s, ties to the smaller s."""
+    from . import theta as _theta
+    best = None
+    for m, p in zip(PS_DEGREES, PS_PRODUCTS):
+        th = float(_theta.taylor_theta(m, u))
+        s = 0
+        while eta > np.ldexp(th, s):
+            s += 1
+        if best is None or p + s < best[0] or (p + s == best[0] and s < best[2]):
+            best = (p + s, m, s)
+    return best[1], best[2]
+
+
+def expm_ps(A, m, s):
+    """T_m(A / 2^s)^(2^s) with the plain truncated series, in long double: the comparison
+    method's output for a given (m, s)."""
+    X = np.asarray(A, dtype=np.longdouble) * np.ldexp(np.longdouble(1.0), -s)
+    T = taylor_poly(X, m)
+    for _ in range(s):
+        T = T @ T
+    return np.asarray(T, dtype=np.float64)

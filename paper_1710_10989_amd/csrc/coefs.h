@@ -46,4 +46,24 @@ __host__ __device__ inline void make_coefs(const Consts &k, int m, int s, double
   }
 }
 
+// Coefficients of the Paterson-Stockmeyer evaluation of degree m in {6, 9, 12, 16} (eq. poli9)
+// at X = A / 2^s, a_k = 2^(-s k) / k!, in blocks of four per Horner step: block j holds the
+// coefficients of I, A, A^2, A^3 in F_j = sum_i a_(q j + i) A^i (q the base; with q = 3 the
+// fourth slot is 0, except in the innermost block, where it carries a_m of the term a_m A^3);
+// with q = 4, c[16] = a_16 multiplies A^4 in the innermost block.  Then
+// T = F_0 + (F_1 + (... + F_(r-1) ...) A^q) A^q, r = m / q.
+__host__ __device__ inline void make_ps_coefs(int m, int s, double *c) {
+  // 1/k! for k <= 16: every k! there is an exact double, so each quotient is correctly rounded
+  constexpr double kInvFact[17] = {1.0, 1.0, 1.0 / 2.0, 1.0 / 6.0, 1.0 / 24.0, 1.0 / 120.0, 1.0 / 720.0,
+                                   1.0 / 5040.0, 1.0 / 40320.0, 1.0 / 362880.0, 1.0 / 3628800.0,
+                                   1.0 / 39916800.0, 1.0 / 479001600.0, 1.0 / 6227020800.0,
+                                   1.0 / 87178291200.0, 1.0 / 1307674368000.0, 1.0 / 20922789888000.0};
+  const int q = ps_base(m), r = m / q;
+  for (int i = 0; i < 17; ++i) c[i] = 0.0;
+  for (int j = 0; j < r; ++j)
+    for (int i = 0; i < q; ++i) c[4 * j + i] = ldexp(kInvFact[q * j + i], -s * (q * j + i));
+  if (q == 3) c[4 * (r - 1) + 3] = ldexp(kInvFact[m], -s * m);
+  else c[16] = ldexp(kInvFact[16], -s * 16);
+}
+
 }  // namespace expm

@@ -43,7 +43,7 @@ expm_status_t check_opts(const expm_opts_t *o, double *u) {
   if (o->dtype != EXPM_F64 && o->dtype != EXPM_C128) return EXPM_E_INVALID_ARG;
   if (o->prec < EXPM_PREC_FP64 || o->prec > EXPM_PREC_FP32_ALL) return EXPM_E_INVALID_ARG;
   if (o->sel < EXPM_SEL_PLAIN || o->sel > EXPM_SEL_LEARNED) return EXPM_E_INVALID_ARG;
-  if (o->flags != 0) return EXPM_E_INVALID_ARG;
+  if (o->flags & ~EXPM_FLAG_PS) return EXPM_E_INVALID_ARG;
   double uu = o->u == 0.0 ? default_u(o->prec) : o->u;
   if (!(uu >= 0x1p-53 && uu <= 0x1p-10)) return EXPM_E_INVALID_ARG;
   *u = uu;
@@ -188,6 +188,9 @@ expm_status_t expm_select_rule(const double *norms, int32_t sel, double u, int32
   return EXPM_OK;
 }
 
+// The comparison method (Paterson-Stockmeyer) and the reduced forms run the tiled path.
+static bool tiled_only(const expm_opts_t *o) { return o->prec != EXPM_PREC_FP64 || (o->flags & EXPM_FLAG_PS); }
+
 // Order of the real matrix the method runs on: complex inputs use their real form.
 static int64_t real_order(const expm_opts_t *o, int64_t n) { return o->dtype == EXPM_C128 ? 2 * n : n; }
 
@@ -195,7 +198,7 @@ size_t expm_workspace_bytes(int64_t n_max, int64_t batch, const expm_opts_t *opt
   double u;
   if (n_max < 1 || batch < 1 || check_opts(opts, &u) != EXPM_OK) return 0;
   const int64_t nr = real_order(opts, n_max);
-  if (nr <= kFusedNMax && opts->prec == EXPM_PREC_FP64) return fused_layout(nr, batch).total;
+  if (nr <= kFusedNMax && !tiled_only(opts)) return fused_layout(nr, batch).total;
   return large_layout(nr, batch).total;
 }
 
@@ -339,6 +342,8 @@ static expm_status_t run_large_call(const void *A, void *E, int64_t n, int64_t b
                                     double u, int32_t *m_dev, int32_t *s_dev, int32_t *status_dev, void *ws,
                                     size_t ws_bytes, void *stream, int select_only) {
   if (((uintptr_t)ws) % kAlign) return EXPM_E_INVALID_ARG;
+  const bool ps = (opts->flags & EXPM_FLAG_PS) != 0;
+  if (ps && (opts->prec != EXPM_PREC_FP64 || opts->sel != EXPM_SEL_PLAIN)) return EXPM_E_UNSUPPORTED;
   LargeCall c;
   memset(&c, 0, sizeof(c));
   if (!make_consts(u, &c.k)) return EXPM_E_INVALID_ARG;
@@ -350,6 +355,7 @@ static expm_status_t run_large_call(const void *A, void *E, int64_t n, int64_t b
   c.sel = opts->sel == EXPM_SEL_LEARNED ? EXPM_SEL_ALPHA : opts->sel;
   c.prec = opts->prec;  // expm_prec_t values match PREC_F64 / PREC_F32 / PREC_BF16X3
   c.select_only = select_only;
+  c.ps = ps ? 1 : 0;
   c.m_out = m_dev;
   c.s_out = s_dev;
   c.status = status_dev;
@@ -364,7 +370,7 @@ expm_status_t expm_select(const void *A_dev, int64_t n, const expm_opts_t *opts,
   expm_status_t st = check_opts(opts, &u);
   if (st != EXPM_OK) return st;
   if (!A_dev || !m_dev || !s_dev || n < 1) return EXPM_E_INVALID_ARG;
-  if (real_order(opts, n) > kFusedNMax || opts->prec != EXPM_PREC_FP64)
+  if (real_order(opts, n) > kFusedNMax || tiled_only(opts))
     return run_large_call(A_dev, nullptr, n, 1, opts, u, m_dev, s_dev, nullptr, ws_dev, ws_bytes, stream, 1);
   return run_fused(A_dev, nullptr, nullptr, nullptr, 1, n, n, opts, u, m_dev, s_dev, nullptr,
                    ws_dev, ws_bytes, stream, 1);
@@ -377,7 +383,7 @@ expm_status_t expm_taylor(const void *A_dev, void *E_dev, int64_t n, const expm_
   expm_status_t st = check_opts(opts, &u);
   if (st != EXPM_OK) return st;
   if (!A_dev || !E_dev || !m_dev || !s_dev || n < 1 || A_dev == E_dev) return EXPM_E_INVALID_ARG;
-  if (real_order(opts, n) > kFusedNMax || opts->prec != EXPM_PREC_FP64)
+  if (real_order(opts, n) > kFusedNMax || tiled_only(opts))
     return run_large_call(A_dev, E_dev, n, 1, opts, u, m_dev, s_dev, status_dev, ws_dev, ws_bytes, stream, 0);
   return run_fused(A_dev, E_dev, nullptr, nullptr, 1, n, n, opts, u, m_dev, s_dev, status_dev,
                    ws_dev, ws_bytes, stream, 0);
@@ -393,7 +399,7 @@ expm_status_t expm_batched(const void *A_dev, void *E_dev, const int64_t *offset
   if (!A_dev || !E_dev || !offsets_dev || !n_dev || !m_dev || !s_dev || batch < 1 || n_max < 1 ||
       A_dev == E_dev)
     return EXPM_E_INVALID_ARG;
-  if (real_order(opts, n_max) > kFusedNMax || opts->prec != EXPM_PREC_FP64) return EXPM_E_UNSUPPORTED;
+  if (real_order(opts, n_max) > kFusedNMax || tiled_only(opts)) return EXPM_E_UNSUPPORTED;
   return run_fused(A_dev, E_dev, offsets_dev, n_dev, batch, 0, n_max, opts, u, m_dev, s_dev,
                    status_dev, ws_dev, ws_bytes, stream, 0);
 }
@@ -409,7 +415,7 @@ expm_status_t expm_batched_stage(const void *A_dev, void *E_dev, const int64_t *
   if (!A_dev || !E_dev || !offsets_dev || !n_dev || !m_dev || !s_dev || batch < 1 || n_max < 1 ||
       A_dev == E_dev || stage < 0 || stage > 5)
     return EXPM_E_INVALID_ARG;
-  if (real_order(opts, n_max) > kFusedNMax || opts->prec != EXPM_PREC_FP64) return EXPM_E_UNSUPPORTED;
+  if (real_order(opts, n_max) > kFusedNMax || tiled_only(opts)) return EXPM_E_UNSUPPORTED;
   return run_fused(A_dev, E_dev, offsets_dev, n_dev, batch, 0, n_max, opts, u, m_dev, s_dev,
                    status_dev, ws_dev, ws_bytes, stream, 0, stage);
 }
@@ -421,7 +427,7 @@ expm_status_t expm_batched_uniform(const void *A_dev, void *E_dev, int64_t n, in
   expm_status_t st = check_opts(opts, &u);
   if (st != EXPM_OK) return st;
   if (!A_dev || !E_dev || !m_dev || !s_dev || batch < 1 || n < 1 || A_dev == E_dev) return EXPM_E_INVALID_ARG;
-  if (real_order(opts, n) > kFusedNMax || opts->prec != EXPM_PREC_FP64)
+  if (real_order(opts, n) > kFusedNMax || tiled_only(opts))
     return run_large_call(A_dev, E_dev, n, batch, opts, u, m_dev, s_dev, status_dev, ws_dev, ws_bytes, stream, 0);
   return run_fused(A_dev, E_dev, nullptr, nullptr, batch, n, n, opts, u, m_dev, s_dev, status_dev,
                    ws_dev, ws_bytes, stream, 0);
@@ -437,7 +443,7 @@ expm_status_t expm_magnus4_step(const double *S0_dev, const double *S1_dev, int6
   if (!S0_dev || !S1_dev || !Y_in_dev || !Y_out_dev || !u1_dev || !u2_dev || !m_dev || !s_dev || n < 1 ||
       batch < 1 || s_stride < 0 || !isfinite(h))
     return EXPM_E_INVALID_ARG;
-  if (opts->dtype != EXPM_F64 || opts->prec != EXPM_PREC_FP64 || opts->sel == EXPM_SEL_LEARNED || n > 16)
+  if (opts->dtype != EXPM_F64 || tiled_only(opts) || opts->sel == EXPM_SEL_LEARNED || n > 16)
     return EXPM_E_UNSUPPORTED;
   Consts k;
   if (!make_consts(u, &k)) return EXPM_E_INVALID_ARG;
@@ -456,7 +462,7 @@ expm_status_t expm_features(const void *A_dev, const int64_t *offsets_dev, const
   if (st != EXPM_OK) return st;
   if (!A_dev || !offsets_dev || !n_dev || !features_dev || !m_dev || !s_dev || batch < 1 || n_max < 1)
     return EXPM_E_INVALID_ARG;
-  if (opts->dtype != EXPM_F64 || opts->prec != EXPM_PREC_FP64 || n_max > kFusedNMax) return EXPM_E_UNSUPPORTED;
+  if (opts->dtype != EXPM_F64 || tiled_only(opts) || n_max > kFusedNMax) return EXPM_E_UNSUPPORTED;
   return run_fused(A_dev, nullptr, offsets_dev, n_dev, batch, 0, n_max, opts, u, m_dev, s_dev, nullptr, ws_dev,
                    ws_bytes, stream, 1, -1, features_dev);
 }

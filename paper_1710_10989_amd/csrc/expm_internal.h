@@ -13,6 +13,15 @@ constexpr int kNumDeg = 6;
 constexpr int kDeg[kNumDeg] = {1, 2, 4, 8, 12, 18};
 constexpr int kProducts[kNumDeg] = {0, 1, 2, 3, 4, 5};
 
+// Comparison method of Sec. 4: the plain Taylor polynomial evaluated by the Paterson-Stockmeyer
+// rule in Horner form (eq. poli9), with the degrees k products reach (Table 3).  Degrees 6, 9
+// and 12 use the base A^3, degree 16 the base A^4; degrees 1, 2 and 4 coincide with T_1, T_2,
+// T_4 above.
+constexpr int kNumPs = 7;
+constexpr int kPsDeg[kNumPs] = {1, 2, 4, 6, 9, 12, 16};
+constexpr int kPsProducts[kNumPs] = {0, 1, 2, 3, 4, 5, 6};
+__host__ __device__ inline int ps_base(int m) { return m == 16 ? 4 : 3; }
+
 // Coefficients and thresholds handed to the kernels by value.
 struct Consts {
   double theta[kNumDeg];  // theta_m(u) for m = 1, 2, 4, 8, 12, 18
@@ -24,6 +33,7 @@ struct Consts {
   // (I, A, A^2, A^3, A^6), i.e. t18b[j][*] = b_{*, j+1}.
   double t18a[4];
   double t18b[4][5];
+  double theta_ps[kNumPs];  // theta_m(u) for the Paterson-Stockmeyer degrees (Table 2)
 };
 
 // Builds Consts for accuracy u (host; thresholds cached per u).  Returns false for u outside
@@ -94,6 +104,21 @@ __host__ __device__ inline void select_ms(const double *theta, int alpha, double
     }
   }
   *m_out = kDeg[best];
+  *s_out = best_s;
+}
+
+// (m, s) of the Paterson-Stockmeyer comparison method: the same rule over the degrees and
+// product counts of kPsDeg / kPsProducts, from eta = ||A||_1.
+__host__ __device__ inline void select_ps(const double *theta_ps, double eta, int *m_out, int *s_out) {
+  int best = -1, best_cost = 0, best_s = 0;
+  for (int i = 0; i < kNumPs; ++i) {
+    const int s = scale_exp(eta, theta_ps[i]);
+    const int cost = kPsProducts[i] + s;
+    if (best < 0 || cost < best_cost || (cost == best_cost && s < best_s)) {
+      best = i; best_cost = cost; best_s = s;
+    }
+  }
+  *m_out = kPsDeg[best];
   *s_out = best_s;
 }
 

@@ -30,6 +30,7 @@ struct LargeCall {
   int sel;            // EXPM_SEL_PLAIN or EXPM_SEL_ALPHA
   int prec;           // PREC_F64 / PREC_F32 / PREC_BF16X3 for the reduced steps
   int select_only;
+  int ps;             // Paterson-Stockmeyer comparison method (EXPM_FLAG_PS)
   int32_t *m_out, *s_out, *status;  // device, one per matrix
   void *ws;
   size_t ws_bytes;

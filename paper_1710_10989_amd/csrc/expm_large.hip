@@ -63,22 +63,31 @@ struct LargeArgs {
   const double *coef;      // group coefficients, 64 per matrix
   const int32_t *list;     // matrices (group-relative) of this launch
   int round;               // squaring round (1-based) for SEL_SQ*
+  int ps;                  // Paterson-Stockmeyer comparison method
+  int coff;                // first coefficient of this step in the matrix's 64
   // step description
   int kind;                // epilogue kind (GEMM) or elementwise kind
   int p, q, b0, b1, b2, in0, in1, o[5], dst;
 };
 
-__device__ inline int resolve_t(int m) { return m >= 8 ? 2 : 3; }
+// Buffer of T.  Reduced sequences: 2 for m >= 8, else 3.  Paterson-Stockmeyer (A^2, A^3 in
+// 1, 2, A^4 in 3, Horner partial sums in 6 and 7): 3 with the base A^3, 5 with the base A^4,
+// so that neither operand of the last Horner step is its destination.
+__device__ inline int resolve_t(int m, int ps) {
+  if (ps && m >= 6) return ps_base(m) == 4 ? 5 : 3;
+  return m >= 8 ? 2 : 3;
+}
 
 // Pointer of a selector for matrix (group-relative) mi; returns nullptr for e^A (the caller
 // then writes the output matrix).
 __device__ inline double *sel_ptr(const LargeArgs &a, int mi, int sel, int m, int s) {
   double *base = a.ws + (size_t)mi * a.mstride;
   int k = sel;
-  if (sel == SEL_T) k = resolve_t(m);
-  else if (sel == SEL_TDST) { if (s == 0) return nullptr; k = resolve_t(m); }
-  else if (sel == SEL_SQSRC) k = resolve_t(m) ^ ((a.round - 1) & 1);
-  else if (sel == SEL_SQDST) { if (a.round == s) return nullptr; k = resolve_t(m) ^ ((a.round - 1) & 1) ^ 1; }
+  const int t = resolve_t(m, a.ps);
+  if (sel == SEL_T) k = t;
+  else if (sel == SEL_TDST) { if (s == 0) return nullptr; k = t; }
+  else if (sel == SEL_SQSRC) k = t ^ ((a.round - 1) & 1);
+  else if (sel == SEL_SQDST) { if (a.round == s) return nullptr; k = t ^ ((a.round - 1) & 1) ^ 1; }
   if (k < 0) return nullptr;
   return base + (size_t)k * a.bstride;
 }
@@ -182,6 +191,14 @@ __global__ void lg_select_kernel(LargeArgs a, int count, int stride, const unsig
   }
   const double eta = __longlong_as_double((long long)norms[mi]);
   int m, s;
+  if (a.ps) {
+    select_ps(k.theta_ps, eta, &m, &s);
+    m_arr[gb] = m; s_arr[gb] = s;
+    if (status) status[gb] = EXPM_OK;
+    if (m >= 6) make_ps_coefs(m, s, coef + (size_t)mi * 64);
+    else make_coefs(k, m, s, coef + (size_t)mi * 64);
+    return;
+  }
   select_ms(k.theta, 0, eta, -1.0, -1.0, &m, &s);
   if (alpha && m >= 2) {
     const double n2 = __longlong_as_double((long long)norms[stride + mi]);
@@ -217,7 +234,7 @@ __global__ __launch_bounds__(512, 1) void lg_gemm_kernel(LargeArgs a) {
     }
     d.kind = a.kind;
     d.np = a.np;
-    for (int i = 0; i < 64; ++i) d.c[i] = a.coef[(size_t)mi * 64 + i];
+    for (int i = 0; i < 64; ++i) d.c[i] = i + a.coff < 64 ? a.coef[(size_t)mi * 64 + a.coff + i] : 0.0;
   }
   __syncthreads();
   TileLds<LS> &L = *reinterpret_cast<TileLds<LS> *>(lds_pool<8>());
@@ -241,7 +258,9 @@ __global__ __launch_bounds__(512, 1) void lg_gemm_kernel(LargeArgs a) {
 
 // Elementwise steps (no product), kinds LC1, LC2 (T = I + c0 A [+ c1 A^2]), LC4W, LC8W,
 // LC12.  Grid (np * np / (256 * 4), count).
-enum ElemKind { LC1 = 0, LC2 = 1, LC4W = 2, LC8W = 3, LC12 = 4, LCNAN = 5 };
+// LCPS: innermost Horner term of eq. poli9, F_(r-1) (+ a_16 A^4 for the base A^4), from the
+// coefficient block at coff.
+enum ElemKind { LC1 = 0, LC2 = 1, LC4W = 2, LC8W = 3, LC12 = 4, LCNAN = 5, LCPS = 6 };
 
 __global__ __launch_bounds__(256) void lg_elem_kernel(LargeArgs a) {
   const int mi = a.list[blockIdx.y];
@@ -267,6 +286,12 @@ __global__ __launch_bounds__(256) void lg_elem_kernel(LargeArgs a) {
       case LC4W: gptr(sel_ptr(a, mi, 2, m, s))[e] = c[2] * id + c[3] * B0[e] + c[4] * B1[e]; break;
       case LC8W: gptr(sel_ptr(a, mi, 2, m, s))[e] = c[0] * B0[e] + c[1] * B1[e]; break;
       case LCNAN: put_dst(dst, dld, dnv, dcx, r, cc, __builtin_nan("")); break;
+      case LCPS: {
+        const double *k = c + a.coff;
+        double t = k[0] * id + k[1] * B0[e] + k[2] * B1[e] + k[3] * B2[e];
+        if (m == 16) t += k[4] * gptr(sel_ptr(a, mi, 3, m, s))[e];
+        gptr(dstp)[e] = t;
+      } break;
       case LC12: {
         const double x1 = B0[e], x2 = B1[e], x3 = B2[e];
 #pragma unroll
@@ -326,11 +351,12 @@ struct Launcher {
 
   void gemm(const std::vector<int32_t> &idx, int slot, int kind, int p, int q, int dst,
             int in0 = SEL_NONE, int in1 = SEL_NONE, std::vector<int> o = {}, int round = 0,
-            bool reduced = false) {
+            bool reduced = false, int coff = 0) {
     if (idx.empty() || !ok) return;
     LargeArgs a = base;
     a.list = upload(idx, slot);
     a.kind = kind; a.p = p; a.q = q; a.dst = dst; a.in0 = in0; a.in1 = in1; a.round = round;
+    a.coff = coff;
     for (int j = 0; j < 5; ++j) a.o[j] = j < (int)o.size() ? o[j] : SEL_NONE;
     const int tiles = (int)((L.np / kLargeTile) * (L.np / kLargeTile));
     // EXPM_PREC_FP32_ALL: every product in FP32; otherwise the reduced form covers the powers
@@ -343,11 +369,12 @@ struct Launcher {
     if (hipGetLastError() != hipSuccess) ok = false;
   }
 
-  void elem(const std::vector<int32_t> &idx, int slot, int kind, int dst) {
+  void elem(const std::vector<int32_t> &idx, int slot, int kind, int dst, int coff = 0) {
     if (idx.empty() || !ok) return;
     LargeArgs a = base;
     a.list = upload(idx, slot);
     a.kind = kind; a.dst = dst;
+    a.coff = coff;
     const int64_t blocks = (L.np * L.np + 1023) / 1024;
     hipLaunchKernelGGL(lg_elem_kernel, dim3((unsigned)blocks, (unsigned)idx.size()), dim3(256), 0, st, a);
     if (hipGetLastError() != hipSuccess) ok = false;
@@ -378,6 +405,7 @@ expm_status_t run_large(const LargeCall &c, hipStream_t st) {
   a.io_stride = c.nin * c.nin * (c.cplx ? 2 : 1);
   a.m_arr = c.m_out; a.s_arr = c.s_out;
   a.coef = coef;
+  a.ps = c.ps;
   for (int j = 0; j < 5; ++j) a.o[j] = SEL_NONE;
 
   std::vector<int32_t> mh, sh;
@@ -443,13 +471,14 @@ expm_status_t run_large(const LargeCall &c, hipStream_t st) {
     if (c.select_only) continue;
 
     // ---- powers (the alpha path formed them already) ----
-    std::vector<int32_t> l2, l3, lm[19], lnan;
+    std::vector<int32_t> l2, l3, l4, lm[19], lnan;
     int smax = 0;
     for (int i = 0; i < cnt; ++i) {
       const int m = mh[i];
       if (m < 1) { lnan.push_back(i); continue; }  // non-finite input
       if (m >= 2) l2.push_back(i);
-      if (m >= 12) l3.push_back(i);
+      if (m >= (c.ps ? 6 : 12)) l3.push_back(i);
+      if (c.ps && m == 16) l4.push_back(i);
       lm[m].push_back(i);
       smax = std::max(smax, (int)sh[i]);
     }
@@ -457,21 +486,37 @@ expm_status_t run_large(const LargeCall &c, hipStream_t st) {
       run.gemm(l2, 0, EK_STORE, 0, 0, 1, SEL_NONE, SEL_NONE, {}, 0, true);
       run.gemm(l3, 1, EK_STORE, 1, 0, 2, SEL_NONE, SEL_NONE, {}, 0, true);
     }
+    run.gemm(l4, 20, EK_STORE, 1, 1, 3);  // A^4 = A^2 A^2 (base of the degree-16 rule)
     run.elem(lnan, 1, LCNAN, SEL_NONE);
     // ---- product stage per degree ----
     run.elem(lm[1], 2, LC1, SEL_TDST);
     run.elem(lm[2], 3, LC2, SEL_TDST);
     run.elem(lm[4], 4, LC4W, 2);
     run.gemm(lm[4], 4, EK_M4, 1, 2, SEL_TDST);
-    run.elem(lm[8], 5, LC8W, 2);
-    run.gemm(lm[8], 5, EK_M8A, 1, 2, SEL_NONE, SEL_NONE, SEL_NONE, {3, 4}, 0, true);
-    run.gemm(lm[8], 5, EK_M8B, 3, 4, SEL_TDST);
-    run.elem(lm[12], 6, LC12, SEL_NONE);
-    run.gemm(lm[12], 6, EK_SPLIT2, 6, 6, SEL_NONE, 5, 4, {0, 1}, 0, true);
-    run.gemm(lm[12], 6, EK_ADD1, 1, 0, SEL_TDST, 3);
-    run.gemm(lm[18], 7, EK_M18A, 2, 2, SEL_NONE, SEL_NONE, SEL_NONE, {3, 4, 5, 6, 7}, 0, true);
-    run.gemm(lm[18], 7, EK_SPLIT2, 3, 7, SEL_NONE, 6, 5, {0, 1}, 0, true);
-    run.gemm(lm[18], 7, EK_ADD1, 1, 0, SEL_TDST, 4);
+    if (c.ps) {
+      // eq. poli9: innermost term F_(r-1) (+ a_16 A^4) into buffer 6, then r - 1 Horner steps
+      // R <- F_j + R A^q alternating between buffers 6 and 7; the last one writes T
+      for (int m : {6, 9, 12, 16}) {
+        const int q = m == 16 ? 4 : 3, r = m / q, qb = q == 4 ? 3 : 2, slot = 21 + q + r;
+        run.elem(lm[m], slot, LCPS, 6, 4 * (r - 1));
+        int cur = 6;
+        for (int j = r - 2; j >= 0; --j) {
+          const int dst = j == 0 ? (int)SEL_TDST : (cur == 6 ? 7 : 6);
+          run.gemm(lm[m], slot, EK_PSH, cur, qb, dst, SEL_NONE, SEL_NONE, {}, 0, false, 4 * j);
+          cur = dst;
+        }
+      }
+    } else {
+      run.elem(lm[8], 5, LC8W, 2);
+      run.gemm(lm[8], 5, EK_M8A, 1, 2, SEL_NONE, SEL_NONE, SEL_NONE, {3, 4}, 0, true);
+      run.gemm(lm[8], 5, EK_M8B, 3, 4, SEL_TDST);
+      run.elem(lm[12], 6, LC12, SEL_NONE);
+      run.gemm(lm[12], 6, EK_SPLIT2, 6, 6, SEL_NONE, 5, 4, {0, 1}, 0, true);
+      run.gemm(lm[12], 6, EK_ADD1, 1, 0, SEL_TDST, 3);
+      run.gemm(lm[18], 7, EK_M18A, 2, 2, SEL_NONE, SEL_NONE, SEL_NONE, {3, 4, 5, 6, 7}, 0, true);
+      run.gemm(lm[18], 7, EK_SPLIT2, 3, 7, SEL_NONE, 6, 5, {0, 1}, 0, true);
+      run.gemm(lm[18], 7, EK_ADD1, 1, 0, SEL_TDST, 4);
+    }
     // ---- squarings: round r covers the matrices with s >= r ----
     for (int r = 1; r <= smax; ++r) {
       std::vector<int32_t> lr;

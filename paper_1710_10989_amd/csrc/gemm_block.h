@@ -32,7 +32,8 @@ enum EpiKind {
   EK_M8B = 3,     // dst = v + c8 id + c9 b0 + c10 b1               (T_8)
   EK_ADD1 = 4,    // dst = v + in0
   EK_SPLIT2 = 5,  // o0 = v + in0; o1 = o0 + in1
-  EK_M18A = 6     // o0..o4 = B_1..B_5 of the degree-18 sequence from (id, b0, b1, b2, v)
+  EK_M18A = 6,    // o0..o4 = B_1..B_5 of the degree-18 sequence from (id, b0, b1, b2, v)
+  EK_PSH = 7      // dst = v + c0 id + c1 b0 + c2 b1 + c3 b2   (a Horner step of eq. poli9)
 };
 
 struct EpiDesc {
@@ -181,6 +182,16 @@ __device__ inline void run_epilogue(int row0, int col0, int rows, int cols, int 
         o2[e] = k[9] * id + k[10] * x1 + k[11] * x2 + k[12] * x3 + k[13] * v;
         o3[e] = k[14] * id + k[15] * x1 + k[16] * x2 + k[17] * x3 + k[18] * v;
         o4[e] = k[19] * id + k[20] * x1 + k[21] * x2 + k[22] * x3 + k[23] * v;
+      });
+    } break;
+    case EK_PSH: {
+      gdouble *dst = gptr(g_ep.dst);
+      const int ld = g_ep.dst_ld, nv = g_ep.dst_nvalid, cx = g_ep.cplx;
+      const double c0 = c[0], c1 = c[1], c2 = c[2], c3 = c[3];
+      cgdouble *const in[3] = {gptr(g_ep.b0), gptr(g_ep.b1), gptr(g_ep.b2)};
+      for_chunk<NW, 3>(cbuf, row0, col0, rows, cols, ldc, np, in, [&](int r, int cc, int, double v, const double *x) {
+        const double t = v + (r == cc ? c0 : 0.0) + c1 * x[0] + c2 * x[1] + c3 * x[2];
+        put_dst(dst, ld, nv, cx, r, cc, t);
       });
     } break;
     default: break;

@@ -60,6 +60,7 @@ std::map<std::pair<int, double>, double> g_theta_cache;
 bool theta_of(int m, double u, double *out) {
   bool ok = false;
   for (int i = 0; i < kNumDeg; ++i) ok |= (kDeg[i] == m);
+  for (int i = 0; i < kNumPs; ++i) ok |= (kPsDeg[i] == m);
   if (!ok || !(u >= 0x1p-53 && u <= 0x1p-10)) return false;
   std::lock_guard<std::mutex> lk(g_mu);
   auto key = std::make_pair(m, u);
@@ -83,6 +84,8 @@ bool theta_of(int m, double u, double *out) {
 bool make_consts(double u, Consts *k) {
   for (int i = 0; i < kNumDeg; ++i)
     if (!theta_of(kDeg[i], u, &k->theta[i])) return false;
+  for (int i = 0; i < kNumPs; ++i)
+    if (!theta_of(kPsDeg[i], u, &k->theta_ps[i])) return false;
   // T_8 (eq. Algorithm83eA), free parameter x3 = 2/3, closed forms in sqrt(177).
   const ld r = sqrtl(177.0L), x3 = 2.0L / 3.0L;
   k->t8[0] = (double)(x3 * (1.0L + r) / 88.0L);                 // x1

@@ -15,9 +15,14 @@ _PREC = {"fp64": N.EXPM_PREC_FP64, "fp32": N.EXPM_PREC_FP32, "bf16x3": N.EXPM_PR
 _SEL = {"plain": N.EXPM_SEL_PLAIN, "alpha": N.EXPM_SEL_ALPHA, "learned": N.EXPM_SEL_LEARNED}
 
 
-def _opts(dtype, prec, selector, u):
+_METHOD = {"reduced": 0, "ps": N.EXPM_FLAG_PS}
+
+
+def _opts(dtype, prec, selector, u, method="reduced"):
+    """method: "reduced" (the paper's product-reduced T_m) or "ps" (the Paterson-Stockmeyer
+    comparison method, EXPM_FLAG_PS)."""
     return N.ExpmOpts(N.EXPM_C128 if dtype == torch.complex128 else N.EXPM_F64, _PREC[prec],
-                      _SEL[selector], 0, 0.0 if u is None else float(u))
+                      _SEL[selector], _METHOD[method], 0.0 if u is None else float(u))
 
 
 def _ptr(t):
@@ -45,9 +50,9 @@ def select_rule(norms, selector="plain", u=2.0 ** -53):
     return m.value, s.value
 
 
-def workspace_bytes(n_max, batch=1, dtype=torch.float64, prec="fp64", selector="plain", u=None):
+def workspace_bytes(n_max, batch=1, dtype=torch.float64, prec="fp64", selector="plain", u=None, method="reduced"):
     """Device workspace in bytes for matrices of order up to n_max (expm_workspace_bytes)."""
-    o = _opts(dtype, prec, selector, u)
+    o = _opts(dtype, prec, selector, u, method)
     return N.lib().expm_workspace_bytes(int(n_max), int(batch), ctypes.byref(o))
 
 
@@ -66,13 +71,13 @@ def _check_square(A):
         raise ValueError("A must be float64 or complex128")
 
 
-def taylor(A, u=None, prec="fp64", selector="plain", workspace=None):
+def taylor(A, u=None, prec="fp64", selector="plain", workspace=None, method="reduced"):
     """e^A for one square device matrix.  Returns (E, m, s, status) with m, s, status as
     one-element int32 device tensors."""
     _check_square(A)
     A = A.contiguous()
     n = A.shape[0]
-    o = _opts(A.dtype, prec, selector, u)
+    o = _opts(A.dtype, prec, selector, u, method)
     ws = workspace if workspace is not None else _workspace(
         N.lib().expm_workspace_bytes(n, 1, ctypes.byref(o)), A.device)
     E = torch.empty_like(A)
@@ -83,12 +88,12 @@ def taylor(A, u=None, prec="fp64", selector="plain", workspace=None):
     return E, ms[0:1], ms[1:2], ms[2:3]
 
 
-def select(A, u=None, prec="fp64", selector="plain"):
+def select(A, u=None, prec="fp64", selector="plain", method="reduced"):
     """(m, s) chosen for A, as one-element int32 device tensors."""
     _check_square(A)
     A = A.contiguous()
     n = A.shape[0]
-    o = _opts(A.dtype, prec, selector, u)
+    o = _opts(A.dtype, prec, selector, u, method)
     ws = _workspace(N.lib().expm_workspace_bytes(n, 1, ctypes.byref(o)), A.device)
     ms = torch.empty(2, dtype=torch.int32, device=A.device)
     N.check(N.lib().expm_select(_ptr(A), n, ctypes.byref(o), _ptr(ms[0:1]), _ptr(ms[1:2]), _ptr(ws),
@@ -143,7 +148,8 @@ def batched(batch, u=None, prec="fp64", selector="plain", workspace=None, out=No
     return E, m, s, status
 
 
-def batched_uniform(A, u=None, prec="fp64", selector="plain", workspace=None, out=None, outs=None):
+def batched_uniform(A, u=None, prec="fp64", selector="plain", workspace=None, out=None, outs=None,
+                    method="reduced"):
     """e^A for a stack A of shape (batch, n, n) of same-order matrices (float64 or complex128).
     outs reuses (m, s, status).  Returns (E, m, s, status) device tensors."""
     if A.dim() != 3 or A.shape[1] != A.shape[2]:
@@ -152,7 +158,7 @@ def batched_uniform(A, u=None, prec="fp64", selector="plain", workspace=None, ou
         raise ValueError("A must be a float64 or complex128 device tensor")
     A = A.contiguous()
     nb, n = A.shape[0], A.shape[1]
-    o = _opts(A.dtype, prec, selector, u)
+    o = _opts(A.dtype, prec, selector, u, method)
     ws = workspace if workspace is not None else _workspace(
         N.lib().expm_workspace_bytes(n, nb, ctypes.byref(o)), A.device)
     E = out if out is not None else torch.empty_like(A)

@@ -1,0 +1,109 @@
+"""GPU parity of the Paterson-Stockmeyer comparison method (EXPM_FLAG_PS: the plain Taylor
+polynomial by eq. poli9 on the tiled path) against the CPU oracle.
+
+Tolerances as for the paper's method: relative 1-norm error <= 1e-12 against the oracle's
+long-double direct Taylor e^A, and <= max(1e-12, 64 u 2^s) against the oracle's long-double
+evaluation of the same (m, s) (the comparison method's own output); (m, s) equal to the
+oracle's rule except within a few ulps of a threshold.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1710_10989_amd as P
+    assert torch.cuda.is_available()
+    return P
+
+
+def dev(A):
+    return torch.from_numpy(np.ascontiguousarray(A)).cuda()
+
+
+def check(orc, A, E, m, s):
+    ref, _ = orc.expm_taylor(A)
+    assert orc.rel_err_1(E, ref) <= TOL
+    own = orc.expm_ps(A, m, s)
+    assert orc.rel_err_1(E, own) <= max(TOL, 64 * 2.0 ** -53 * (1 << min(s, 30)))
+
+
+@pytest.mark.parametrize("target,expect", [
+    (1e-17, (1, 0)), (1e-9, (2, 0)), (1e-4, (4, 0)), (5e-3, (6, 0)), (0.05, (9, 0)), (0.2, (12, 0)),
+    (0.5, (16, 0)), (2.0, (16, 2)), (30.0, (16, 6))])
+def test_every_degree(P, orc, target, expect):
+    g = np.random.default_rng(int(target * 1e6) % 1000 + 7)
+    A = g.standard_normal((37, 37))
+    A *= target / np.abs(A).sum(0).max()
+    say("case ps", expect)
+    E, m, s, st = P.taylor(dev(A), method="ps")
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    assert (int(m.item()), int(s.item())) == expect == orc.select_ps(orc.norm1(A))
+    check(orc, A, E.cpu().numpy(), *expect)
+
+
+@pytest.mark.parametrize("n", [1, 16, 129, 200])
+def test_orders(P, orc, n):
+    from paper_1710_10989_amd import workloads as W
+    g = np.random.default_rng(500 + n)
+    for kind in W.STRUCTURES:
+        if n == 1 and kind != "dense":
+            continue
+        A = W.rescale(W.structured(g, n, kind) if n > 1 else g.standard_normal((1, 1)), 3.0)
+        say("case ps n=%d %s" % (n, kind))
+        E, m, s, st = P.taylor(dev(A), method="ps")
+        torch.cuda.synchronize()
+        m, s = int(m.item()), int(s.item())
+        assert (m, s) == orc.select_ps(orc.norm1(A))
+        check(orc, A, E.cpu().numpy(), m, s)
+
+
+def test_uniform_batch_and_complex(P, orc):
+    from paper_1710_10989_amd import workloads as W
+    mats = W.large_dense(3, 150, norm_range=(0.1, 20.0), seed_stream=3)
+    E, m, s, st = P.batched_uniform(dev(np.stack(mats)), method="ps")
+    torch.cuda.synchronize()
+    for i, A in enumerate(mats):
+        assert (int(m[i].item()), int(s[i].item())) == orc.select_ps(orc.norm1(A))
+        check(orc, A, E[i].cpu().numpy(), int(m[i].item()), int(s[i].item()))
+    g = np.random.default_rng(9)
+    Z = (g.standard_normal((24, 24)) + 1j * g.standard_normal((24, 24))) * 0.1
+    E, m, s, st = P.taylor(dev(Z), method="ps")
+    torch.cuda.synchronize()
+    ref, _ = orc.expm_taylor(Z)
+    assert orc.rel_err_1(E.cpu().numpy(), ref) <= TOL
+
+
+def test_select_only_and_rejections(P, orc):
+    from paper_1710_10989_amd import _native as N
+    from paper_1710_10989_amd.expm import Batch
+    g = np.random.default_rng(2)
+    A = g.standard_normal((50, 50)) * 0.02
+    m, s = P.select(dev(A), method="ps")
+    assert (int(m.item()), int(s.item())) == orc.select_ps(orc.norm1(A))
+    with pytest.raises(N.ExpmError) as e:
+        P.taylor(dev(A), method="ps", selector="alpha")
+    assert e.value.code == N.EXPM_E_UNSUPPORTED
+    B = Batch.from_host([A, A[:10, :10]])
+    ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    import ctypes
+    from paper_1710_10989_amd import expm as X
+    o = X._opts(torch.float64, "fp64", "plain", None, "ps")
+    outs = [torch.empty(2, dtype=torch.int32, device="cuda") for _ in range(3)]
+    E = torch.empty_like(B.packed)
+    st = N.lib().expm_batched(X._ptr(B.packed), X._ptr(E), X._ptr(B.offsets), X._ptr(B.ns), 2, B.n_max,
+                              ctypes.byref(o), X._ptr(outs[0]), X._ptr(outs[1]), X._ptr(outs[2]), X._ptr(ws),
+                              ws.numel(), X._stream())
+    assert st == N.EXPM_E_UNSUPPORTED
