@@ -387,29 +387,32 @@ def run_small(args, torch, P, W):
     count, n = 65536, 16
     A = W.small_skew_batch(count=count, n=n)
     Ad = torch.from_numpy(A).cuda()
-    ws = torch.empty(P.workspace_bytes(n, count), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(P.workspace_bytes(n, count, method=args.method), dtype=torch.uint8, device="cuda")
     out = torch.empty_like(Ad)
     outs = tuple(torch.empty(count, dtype=torch.int32, device="cuda") for _ in range(3))
 
+    mt = args.method
+
     def step():
-        P.batched_uniform(Ad, selector=args.selector, workspace=ws, out=out, outs=outs)
+        P.batched_uniform(Ad, selector=args.selector, workspace=ws, out=out, outs=outs, method=mt)
 
     ms = timed(torch, args, step)
     m, s, st = (x.cpu().numpy() for x in outs)
     assert np.all(st == 0)
+    prods = {"reduced": PRODUCTS, "ps": PS_PRODUCTS, "pade": {10: 3 + 4.0 / 3.0, 26: 6 + 4.0 / 3.0}}[mt]
     nbytes = count * (16 * n * n + 12)  # A in, e^A out, (m, s, status) out
     achieved = nbytes / (ms * 1e-3)
     roof = {"bound": "hbm", "kernel": "expm_tiny_kernel (one wave per matrix)", "achieved": achieved / 1e9,
             "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": achieved / PEAK_HBM,
             "traffic": measured_traffic("expm_tiny_kernel_65536_n16"), "kernel_ms": ms,
-            "step_tflops": executed_flops(m, s, [n] * count) / (ms * 1e-3) / 1e12}
+            "step_tflops": executed_flops(m, s, [n] * count, prods) / (ms * 1e-3) / 1e12}
     cpu = None
     if not args.no_cpu:
         cpu = cpu_oracle([A[i] for i in range(4096)], args.cpu_seconds, "4096 of the matrices")
     config = {"workload": "%d FP64 skew-symmetric matrices of order %d (Magnus-integrator exponents), "
                           "||A||_1 log-uniform [0.05, 1]; one expm_batched_uniform call per step" % (count, n),
-              "selector": args.selector,
-              "mean_products_plus_squarings": float(np.mean([PRODUCTS[int(a)] + int(b) for a, b in zip(m, s)]))}
+              "selector": args.selector, "method": mt,
+              "mean_products_plus_squarings": float(np.mean([prods[int(a)] + int(b) for a, b in zip(m, s)]))}
     return line(args, "expm matrices/s (rel err <= 1e-12, FP64)", count / (ms * 1e-3), ms, "f64", config, roof, cpu)
 
 
@@ -484,8 +487,9 @@ def main():
                                                              "small", "magnus", "copy"])
     ap.add_argument("--selector", default="plain", choices=["plain", "alpha"])
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3", "fp32all"])
-    ap.add_argument("--method", default="reduced", choices=["reduced", "ps"],
-                    help="precision workload: the paper's T_m or the Paterson-Stockmeyer comparison method")
+    ap.add_argument("--method", default="reduced", choices=["reduced", "ps", "pade"],
+                    help="the paper's T_m or a comparison method (ps: precision and small workloads; "
+                         "pade: small workload)")
     ap.add_argument("--count", type=int, default=4096)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")

@@ -83,21 +83,30 @@ typedef enum {
  *           ALPHA bound holds for it, otherwise the PLAIN rule decides (expm_learned_set). */
 typedef enum { EXPM_SEL_PLAIN = 0, EXPM_SEL_ALPHA = 1, EXPM_SEL_LEARNED = 2 } expm_sel_t;
 
-/* Evaluation method of T_m (expm_opts_t.flags).  0: the product-reduced sequences of the
- * paper (T_8, T_12, T_18 with 3, 4, 5 products).  EXPM_FLAG_PS: the comparison method of
- * Sec. 4, the plain Taylor polynomial T_m = sum_k A^k / k! evaluated by the Paterson-Stockmeyer
- * rule in Horner form (eq. poli9), m in {1, 2, 4, 6, 9, 12, 16} with 0..6 products (Table 3)
- * and thresholds theta_m(u) of the same definition (Table 2); (m, s) by the same cheapest-cost
- * rule from ||A||_1.  Runs the tiled path (any order) with FP64 products and EXPM_SEL_PLAIN;
- * other combinations, and the calls that only run the fused kernels (expm_batched,
- * expm_batched_stage, expm_features, expm_magnus4_step), return EXPM_E_UNSUPPORTED. */
+/* Evaluation method (expm_opts_t.flags, at most one bit).  0: the product-reduced sequences
+ * of the paper (T_8, T_12, T_18 with 3, 4, 5 products).  The two comparison methods, with FP64
+ * products and the plain ||A||_1 rule only:
+ *  EXPM_FLAG_PS:   the plain Taylor polynomial T_m = sum_k A^k / k! by the Paterson-Stockmeyer
+ *                  rule in Horner form (Sec. 4, eq. poli9), m in {1, 2, 4, 6, 9, 12, 16} with
+ *                  0..6 products (Table 3), thresholds theta_m(u) of the same definition
+ *                  (Table 2), (m, s) by the same cheapest-cost rule.  Any order: real order
+ *                  <= 16 on one wave per matrix, larger on the tiled path.
+ *  EXPM_FLAG_PADE: diagonal Pade r_10 or r_26 (Sec. 2, eqs. eq.pade10 and eq.pade26): 3 or 6
+ *                  products and one linear solve (costed 4/3 of a product), thresholds of
+ *                  Table 1 (u = 2^-53 or 2^-24 only); m_dev receives the order 2m (10 or 26).
+ *                  Real order <= 16 (one wave per matrix; the solve is Gauss-Jordan with
+ *                  partial pivoting).
+ * Unsupported combinations, and the calls that only run the product-reduced kernels
+ * (expm_batched, expm_batched_stage, expm_features, expm_magnus4_step), return
+ * EXPM_E_UNSUPPORTED. */
 #define EXPM_FLAG_PS 1
+#define EXPM_FLAG_PADE 2
 
 typedef struct {
   int32_t dtype;  /* expm_dtype_t */
   int32_t prec;   /* expm_prec_t */
   int32_t sel;    /* expm_sel_t */
-  int32_t flags;  /* 0 or EXPM_FLAG_PS; other bits: EXPM_E_INVALID_ARG */
+  int32_t flags;  /* 0, EXPM_FLAG_PS or EXPM_FLAG_PADE; anything else: EXPM_E_INVALID_ARG */
   double u;       /* target relative backward error; 0 = the form's default (2^-24 for FP32
                      and FP32_ALL, 2^-53 otherwise) */
 } expm_opts_t;

@@ -41,6 +41,7 @@ def lib():
         L.or_expm_taylor_z.argtypes = [i64, vp, vp, ip]; L.or_expm_taylor_z.restype = i32
         L.or_expm_taylor_batch.argtypes = [i64, vp, vp, vp, vp, i32, vp]; L.or_expm_taylor_batch.restype = i32
         L.or_expm_pade26.argtypes = [i64, vp, vp, dbl, ip]; L.or_expm_pade26.restype = i32
+        L.or_pade_ms.argtypes = [i64, vp, i32, i32, vp]; L.or_pade_ms.restype = i32
         L.or_reduced_Tm.argtypes = [i64, vp, i32, vp]; L.or_reduced_Tm.restype = i32
         L.or_expm_reduced.argtypes = [i64, vp, i32, i32, vp]; L.or_expm_reduced.restype = i32
         L.or_select_plain.argtypes = [dbl, vp, ip, ip]; L.or_select_plain.restype = None
@@ -280,3 +281,33 @@ def expm_ps(A, m, s):
     for _ in range(s):
         T = T @ T
     return np.asarray(T, dtype=np.float64)
+
+
+# ---- diagonal Pade comparison method (Sec. 2, eqs. eq.24, eq.pade10, eq.pade26, Table 1) ----
+
+# theta_10 and theta_26 of Table 1, one unit of the third printed digit below the printed
+# value (a printed value may be rounded up); only the two printed rows of u
+PADE_THETA = {2.0 ** -53: (2.53e-1, 5.36), 2.0 ** -24: (1.87, 11.1)}
+
+
+def select_pade(eta, u=2.0 ** -53):
+    """(2m, s) of the Pade comparison: r_10 (3 products) or r_26 (6 products), one solve costed
+    4/3 of a product; s the smallest with eta <= theta_2m 2^s; the cheaper, ties to the smaller s."""
+    best = None
+    for deg, prods, th in zip((10, 26), (3, 6), PADE_THETA[u]):
+        s = 0
+        while eta > np.ldexp(th, s):
+            s += 1
+        cost3 = 3 * prods + 4 + 3 * s
+        if best is None or cost3 < best[0] or (cost3 == best[0] and s < best[2]):
+            best = (cost3, deg, s)
+    return best[1], best[2]
+
+
+def expm_pade(A, deg, s):
+    """r_deg(A / 2^s)^(2^s), deg = 2m, from the definition p_m(X) / p_m(-X) (long double)."""
+    A = _f64(A)
+    E = np.empty_like(A)
+    if lib().or_pade_ms(A.shape[0], _p(A), int(deg) // 2, int(s), _p(E)) < 0:
+        raise ValueError("singular denominator")
+    return E

@@ -334,6 +334,42 @@ int or_expm_pade26(int64_t n, const double *A, double *E, double theta26, int *s
   return rc;
 }
 
+/* r_2m(A / 2^s)^(2^s) for a given (m, s), r_2m = p_m(X) / p_m(-X) with p_m of eq. eq.24
+ * summed term by term over plain powers X^j (not the grouped forms of eqs. eq.pade10 /
+ * eq.pade26), one LU solve with partial pivoting, s squarings; long double.  Returns 0, or -1
+ * for a singular denominator. */
+int or_pade_ms(int64_t n, const double *A, int m, int s, double *E) {
+  ld b[32];
+  for (int j = 0; j <= m; ++j) {
+    ld v = 1.0L;
+    for (int t = 0; t < j; ++t) v *= (ld)(m - t) / (ld)(2 * m - t);
+    for (int t = 2; t <= j; ++t) v /= (ld)t;
+    b[j] = v;
+  }
+  ld *X = ld_alloc(n), *P = ld_alloc(n), *T = ld_alloc(n), *Pp = ld_alloc(n), *Q = ld_alloc(n);
+  for (int64_t i = 0; i < n * n; ++i) X[i] = ldexpl((ld)A[i], -s);
+  for (int64_t i = 0; i < n; ++i) P[i * n + i] = 1.0L; /* X^0 */
+  for (int j = 0; j <= m; ++j) {
+    if (j > 0) {
+      mm_ld(n, P, X, T);
+      memcpy(P, T, sizeof(ld) * (size_t)(n * n));
+    }
+    const ld sg = (j % 2) ? -1.0L : 1.0L;
+    for (int64_t i = 0; i < n * n; ++i) {
+      Pp[i] += b[j] * P[i];
+      Q[i] += sg * b[j] * P[i];
+    }
+  }
+  int rc = lu_solve_ld(n, Q, Pp); /* Pp <- Q^{-1} Pp */
+  for (int r = 0; r < s && rc == 0; ++r) {
+    mm_ld(n, Pp, Pp, T);
+    memcpy(Pp, T, sizeof(ld) * (size_t)(n * n));
+  }
+  for (int64_t i = 0; i < n * n; ++i) E[i] = (double)Pp[i];
+  free(X); free(P); free(T); free(Pp); free(Q);
+  return rc;
+}
+
 /* ------------------------------------------------------------------------------------ */
 /* The product-reduced Taylor sequences (Sec. 3).                                        */
 /* ------------------------------------------------------------------------------------ */

@@ -43,7 +43,7 @@ expm_status_t check_opts(const expm_opts_t *o, double *u) {
   if (o->dtype != EXPM_F64 && o->dtype != EXPM_C128) return EXPM_E_INVALID_ARG;
   if (o->prec < EXPM_PREC_FP64 || o->prec > EXPM_PREC_FP32_ALL) return EXPM_E_INVALID_ARG;
   if (o->sel < EXPM_SEL_PLAIN || o->sel > EXPM_SEL_LEARNED) return EXPM_E_INVALID_ARG;
-  if (o->flags & ~EXPM_FLAG_PS) return EXPM_E_INVALID_ARG;
+  if (o->flags != 0 && o->flags != EXPM_FLAG_PS && o->flags != EXPM_FLAG_PADE) return EXPM_E_INVALID_ARG;
   double uu = o->u == 0.0 ? default_u(o->prec) : o->u;
   if (!(uu >= 0x1p-53 && uu <= 0x1p-10)) return EXPM_E_INVALID_ARG;
   *u = uu;
@@ -188,8 +188,21 @@ expm_status_t expm_select_rule(const double *norms, int32_t sel, double u, int32
   return EXPM_OK;
 }
 
-// The comparison method (Paterson-Stockmeyer) and the reduced forms run the tiled path.
-static bool tiled_only(const expm_opts_t *o) { return o->prec != EXPM_PREC_FP64 || (o->flags & EXPM_FLAG_PS); }
+// The reduced forms and the Paterson-Stockmeyer comparison above real order 16 run the tiled
+// path (the Pade comparison exists for real orders <= 16 only).
+static int64_t real_order(const expm_opts_t *o, int64_t n);
+static bool tiled_only(const expm_opts_t *o, int64_t n = 0) {
+  return o->prec != EXPM_PREC_FP64 || ((o->flags & EXPM_FLAG_PS) && real_order(o, n) > 16);
+}
+// Comparison methods on the fused kernels: FP64, plain rule, real order <= 16 (one wave per
+// matrix), Pade only for the two printed rows of u.
+static expm_status_t method_check(const expm_opts_t *o, int64_t n, double u) {
+  if (o->flags == 0) return EXPM_OK;
+  if (o->prec != EXPM_PREC_FP64 || o->sel != EXPM_SEL_PLAIN) return EXPM_E_UNSUPPORTED;
+  if ((o->flags & EXPM_FLAG_PADE) && (real_order(o, n) > 16 || (u != 0x1p-53 && u != 0x1p-24)))
+    return EXPM_E_UNSUPPORTED;
+  return EXPM_OK;
+}
 
 // Order of the real matrix the method runs on: complex inputs use their real form.
 static int64_t real_order(const expm_opts_t *o, int64_t n) { return o->dtype == EXPM_C128 ? 2 * n : n; }
@@ -198,7 +211,7 @@ size_t expm_workspace_bytes(int64_t n_max, int64_t batch, const expm_opts_t *opt
   double u;
   if (n_max < 1 || batch < 1 || check_opts(opts, &u) != EXPM_OK) return 0;
   const int64_t nr = real_order(opts, n_max);
-  if (nr <= kFusedNMax && !tiled_only(opts)) return fused_layout(nr, batch).total;
+  if (nr <= kFusedNMax && !tiled_only(opts, n_max)) return fused_layout(nr, batch).total;
   return large_layout(nr, batch).total;
 }
 
@@ -235,6 +248,7 @@ static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, cons
   a.np_max = (int)pad16(nr_max);
   a.cplx = cplx;
   a.sel = opts->sel;  // every kernel runs all three rules
+  a.method = (opts->flags & EXPM_FLAG_PS) ? 1 : (opts->flags & EXPM_FLAG_PADE) ? 2 : 0;
   a.select_only = select_only;
   a.features = features;
   a.lo = 0;
@@ -331,7 +345,7 @@ static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, cons
     const bool ok = t > kResT    ? go(K_FUSED8, f8, 0, 0, 0)
                     : t > kRes6T  ? go(K_RES8, r8, 1, 0, 0)
                     : t >= kSplitT ? go(K_RES6, r6, 2, 0, 0)
-                    : (t == 1 && tiny) ? go(K_TINY, tn, 5, 0, 0)
+                    : (t == 1 && (tiny || a.method)) ? go(K_TINY, tn, 5, 0, 0)
                                    : go(K_RES4, r4, 3, 0, 0);
     if (!ok) return EXPM_E_HIP;
   }
@@ -370,7 +384,8 @@ expm_status_t expm_select(const void *A_dev, int64_t n, const expm_opts_t *opts,
   expm_status_t st = check_opts(opts, &u);
   if (st != EXPM_OK) return st;
   if (!A_dev || !m_dev || !s_dev || n < 1) return EXPM_E_INVALID_ARG;
-  if (real_order(opts, n) > kFusedNMax || tiled_only(opts))
+  if ((st = method_check(opts, n, u)) != EXPM_OK) return st;
+  if (real_order(opts, n) > kFusedNMax || tiled_only(opts, n))
     return run_large_call(A_dev, nullptr, n, 1, opts, u, m_dev, s_dev, nullptr, ws_dev, ws_bytes, stream, 1);
   return run_fused(A_dev, nullptr, nullptr, nullptr, 1, n, n, opts, u, m_dev, s_dev, nullptr,
                    ws_dev, ws_bytes, stream, 1);
@@ -383,7 +398,8 @@ expm_status_t expm_taylor(const void *A_dev, void *E_dev, int64_t n, const expm_
   expm_status_t st = check_opts(opts, &u);
   if (st != EXPM_OK) return st;
   if (!A_dev || !E_dev || !m_dev || !s_dev || n < 1 || A_dev == E_dev) return EXPM_E_INVALID_ARG;
-  if (real_order(opts, n) > kFusedNMax || tiled_only(opts))
+  if ((st = method_check(opts, n, u)) != EXPM_OK) return st;
+  if (real_order(opts, n) > kFusedNMax || tiled_only(opts, n))
     return run_large_call(A_dev, E_dev, n, 1, opts, u, m_dev, s_dev, status_dev, ws_dev, ws_bytes, stream, 0);
   return run_fused(A_dev, E_dev, nullptr, nullptr, 1, n, n, opts, u, m_dev, s_dev, status_dev,
                    ws_dev, ws_bytes, stream, 0);
@@ -399,7 +415,7 @@ expm_status_t expm_batched(const void *A_dev, void *E_dev, const int64_t *offset
   if (!A_dev || !E_dev || !offsets_dev || !n_dev || !m_dev || !s_dev || batch < 1 || n_max < 1 ||
       A_dev == E_dev)
     return EXPM_E_INVALID_ARG;
-  if (real_order(opts, n_max) > kFusedNMax || tiled_only(opts)) return EXPM_E_UNSUPPORTED;
+  if (real_order(opts, n_max) > kFusedNMax || tiled_only(opts) || opts->flags) return EXPM_E_UNSUPPORTED;
   return run_fused(A_dev, E_dev, offsets_dev, n_dev, batch, 0, n_max, opts, u, m_dev, s_dev,
                    status_dev, ws_dev, ws_bytes, stream, 0);
 }
@@ -415,7 +431,7 @@ expm_status_t expm_batched_stage(const void *A_dev, void *E_dev, const int64_t *
   if (!A_dev || !E_dev || !offsets_dev || !n_dev || !m_dev || !s_dev || batch < 1 || n_max < 1 ||
       A_dev == E_dev || stage < 0 || stage > 5)
     return EXPM_E_INVALID_ARG;
-  if (real_order(opts, n_max) > kFusedNMax || tiled_only(opts)) return EXPM_E_UNSUPPORTED;
+  if (real_order(opts, n_max) > kFusedNMax || tiled_only(opts) || opts->flags) return EXPM_E_UNSUPPORTED;
   return run_fused(A_dev, E_dev, offsets_dev, n_dev, batch, 0, n_max, opts, u, m_dev, s_dev,
                    status_dev, ws_dev, ws_bytes, stream, 0, stage);
 }
@@ -427,7 +443,8 @@ expm_status_t expm_batched_uniform(const void *A_dev, void *E_dev, int64_t n, in
   expm_status_t st = check_opts(opts, &u);
   if (st != EXPM_OK) return st;
   if (!A_dev || !E_dev || !m_dev || !s_dev || batch < 1 || n < 1 || A_dev == E_dev) return EXPM_E_INVALID_ARG;
-  if (real_order(opts, n) > kFusedNMax || tiled_only(opts))
+  if ((st = method_check(opts, n, u)) != EXPM_OK) return st;
+  if (real_order(opts, n) > kFusedNMax || tiled_only(opts, n))
     return run_large_call(A_dev, E_dev, n, batch, opts, u, m_dev, s_dev, status_dev, ws_dev, ws_bytes, stream, 0);
   return run_fused(A_dev, E_dev, nullptr, nullptr, batch, n, n, opts, u, m_dev, s_dev, status_dev,
                    ws_dev, ws_bytes, stream, 0);
@@ -443,7 +460,7 @@ expm_status_t expm_magnus4_step(const double *S0_dev, const double *S1_dev, int6
   if (!S0_dev || !S1_dev || !Y_in_dev || !Y_out_dev || !u1_dev || !u2_dev || !m_dev || !s_dev || n < 1 ||
       batch < 1 || s_stride < 0 || !isfinite(h))
     return EXPM_E_INVALID_ARG;
-  if (opts->dtype != EXPM_F64 || tiled_only(opts) || opts->sel == EXPM_SEL_LEARNED || n > 16)
+  if (opts->dtype != EXPM_F64 || tiled_only(opts) || opts->flags || opts->sel == EXPM_SEL_LEARNED || n > 16)
     return EXPM_E_UNSUPPORTED;
   Consts k;
   if (!make_consts(u, &k)) return EXPM_E_INVALID_ARG;
@@ -462,7 +479,7 @@ expm_status_t expm_features(const void *A_dev, const int64_t *offsets_dev, const
   if (st != EXPM_OK) return st;
   if (!A_dev || !offsets_dev || !n_dev || !features_dev || !m_dev || !s_dev || batch < 1 || n_max < 1)
     return EXPM_E_INVALID_ARG;
-  if (opts->dtype != EXPM_F64 || tiled_only(opts) || n_max > kFusedNMax) return EXPM_E_UNSUPPORTED;
+  if (opts->dtype != EXPM_F64 || tiled_only(opts) || opts->flags || n_max > kFusedNMax) return EXPM_E_UNSUPPORTED;
   return run_fused(A_dev, nullptr, offsets_dev, n_dev, batch, 0, n_max, opts, u, m_dev, s_dev, nullptr, ws_dev,
                    ws_bytes, stream, 1, -1, features_dev);
 }

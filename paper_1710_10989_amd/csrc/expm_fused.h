@@ -43,6 +43,7 @@ struct FusedArgs {
   int np_max;             // largest padded order the slots can hold
   int sel;                // expm_sel_t
   int select_only;
+  int method;             // 0 product-reduced T_m; 1 Paterson-Stockmeyer; 2 Pade (one-wave kernel)
   int cplx;               // inputs / outputs are interleaved complex (run on the real form)
   double *features;       // feature rows of the learned selector (kFeatRow doubles per
                           // matrix); when set no e^A is computed

@@ -22,6 +22,12 @@ constexpr int kPsDeg[kNumPs] = {1, 2, 4, 6, 9, 12, 16};
 constexpr int kPsProducts[kNumPs] = {0, 1, 2, 3, 4, 5, 6};
 __host__ __device__ inline int ps_base(int m) { return m == 16 ? 4 : 3; }
 
+// Comparison method of Sec. 2: diagonal Pade r_10 and r_26 (eqs. eq.pade10, eq.pade26) with
+// 3 and 6 products plus one solve, costed as 4/3 of a product (so costs are kept in thirds).
+constexpr int kNumPade = 2;
+constexpr int kPadeDeg[kNumPade] = {10, 26};
+constexpr int kPadeCost3[kNumPade] = {3 * 3 + 4, 3 * 6 + 4};
+
 // Coefficients and thresholds handed to the kernels by value.
 struct Consts {
   double theta[kNumDeg];  // theta_m(u) for m = 1, 2, 4, 8, 12, 18
@@ -34,6 +40,11 @@ struct Consts {
   double t18a[4];
   double t18b[4][5];
   double theta_ps[kNumPs];  // theta_m(u) for the Paterson-Stockmeyer degrees (Table 2)
+  // Pade r_10, r_26: b_j of p_m (eq. eq.24, m = 5 and 13) and theta_10, theta_26 (Table 1;
+  // zero when u is not one of the two printed rows: the method is then unavailable)
+  double pade5[6];
+  double pade13[14];
+  double theta_pade[kNumPade];
 };
 
 // Builds Consts for accuracy u (host; thresholds cached per u).  Returns false for u outside
@@ -119,6 +130,21 @@ __host__ __device__ inline void select_ps(const double *theta_ps, double eta, in
     }
   }
   *m_out = kPsDeg[best];
+  *s_out = best_s;
+}
+
+// (2m, s) of the Pade comparison method: the smallest s with eta <= theta_2m 2^s for 2m = 10,
+// 26; the cheaper of the two (products + 4/3 + s), ties to the smaller s.
+__host__ __device__ inline void select_pade(const double *theta_pade, double eta, int *m_out, int *s_out) {
+  int best = -1, best_cost = 0, best_s = 0;
+  for (int i = 0; i < kNumPade; ++i) {
+    const int s = scale_exp(eta, theta_pade[i]);
+    const int cost = kPadeCost3[i] + 3 * s;
+    if (best < 0 || cost < best_cost || (cost == best_cost && s < best_s)) {
+      best = i; best_cost = cost; best_s = s;
+    }
+  }
+  *m_out = kPadeDeg[best];
   *s_out = best_s;
 }
 

@@ -319,6 +319,223 @@ __device__ bool t_expm(const Consts &K, const Theta &th, double *L, const TLane 
   return true;
 }
 
+
+__device__ inline void t_squarings(double *L, const TLane &ln, int s, q4 &AC) {
+  for (int q = 0; q < s; ++q) {
+    t_put(L, ln, AC);
+    t_zero(AC);
+    t_gemm_sq(L, ln, AC);
+  }
+}
+
+// 1/k!, k <= 16 (every k! there is an exact double, so each quotient is correctly rounded).
+constexpr double kTInvFact[17] = {1.0, 1.0, 1.0 / 2.0, 1.0 / 6.0, 1.0 / 24.0, 1.0 / 120.0, 1.0 / 720.0,
+                                  1.0 / 5040.0, 1.0 / 40320.0, 1.0 / 362880.0, 1.0 / 3628800.0,
+                                  1.0 / 39916800.0, 1.0 / 479001600.0, 1.0 / 6227020800.0,
+                                  1.0 / 87178291200.0, 1.0 / 1307674368000.0, 1.0 / 20922789888000.0};
+
+// Innermost term and Horner steps of eq. poli9, degree M = Q R with base X^Q: X0..X3 hold X,
+// X^2, X^3 (and X^4 when Q = 4), X = 2^-s A, so the coefficients are c_k = 1/k! themselves
+// (compile-time constants).  F_j = sum_(i < Q) c_(Q j + i) X^i;
+// T = F_0 + (F_1 + (... + (F_(R-1) + c_M X^Q) X^Q ...) X^Q) X^Q.
+template <int Q, int R>
+__device__ inline void t_ps_horner(double *L, const TLane &ln, const q4 &X0, const q4 &X1, const q4 &X2,
+                                   const q4 &X3, q4 &AC) {
+  auto F = [&](auto jc, int r) {
+    constexpr int j = decltype(jc)::value;
+    double v = kTInvFact[Q * j] * ln.delta(r) + kTInvFact[Q * j + 1] * X0[r] + kTInvFact[Q * j + 2] * X1[r];
+    if constexpr (Q == 4) v += kTInvFact[Q * j + 3] * X2[r];
+    return v;
+  };
+  q4 Rm;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    Rm[r] = F(std::integral_constant<int, R - 1>(), r);
+    if constexpr (Q == 4) Rm[r] += kTInvFact[Q * R] * X3[r];
+    else Rm[r] += kTInvFact[Q * R] * X2[r];
+  }
+  auto step = [&](auto jc) {
+    t_put(L, ln, Rm);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) AC[r] = F(jc, r);
+    if constexpr (Q == 4) t_gemm(L, ln, X3, AC);  // F_j + R_(j+1) X^4
+    else t_gemm(L, ln, X2, AC);                   // F_j + R_(j+1) X^3
+    t_copy(Rm, AC);
+  };
+  if constexpr (R >= 4) step(std::integral_constant<int, 2>());
+  if constexpr (R >= 3) step(std::integral_constant<int, 1>());
+  step(std::integral_constant<int, 0>());
+}
+
+// The Paterson-Stockmeyer comparison (Sec. 4, eq. poli9): (m, s) over the degrees of Table 3,
+// then the plain Taylor polynomial in Horner form, then s squarings.
+__device__ bool t_expm_ps(const Consts &K, double *L, const TLane &ln, q4 &X0, double eta, int select_only,
+                          int *m_out, int *s_out, q4 &AC) {
+  int m, s;
+  select_ps(K.theta_ps, eta, &m, &s);
+  m = __builtin_amdgcn_readfirstlane(m);
+  s = __builtin_amdgcn_readfirstlane(s);
+  *m_out = m;
+  *s_out = s;
+  if (select_only) return false;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) X0[r] = ldexp(X0[r], -s);
+  q4 X1, X2, X3;
+  if (m >= 2) {
+    t_put(L, ln, X0);
+    t_zero(X1);
+    t_gemm(L, ln, X0, X1);  // X^2
+  }
+  if (m >= 6) {
+    t_zero(X2);
+    t_gemm(L, ln, X1, X2);  // X^3
+  }
+  if (m == 16) {
+    t_put(L, ln, X1);
+    t_zero(X3);
+    t_gemm(L, ln, X1, X3);  // X^4 = X^2 X^2
+  }
+  if (m <= 4) {
+    double c[5];
+    make_coefs(K, m, 0, c);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) c[j] = tuni(c[j]);
+    if (m == 1) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) AC[r] = ln.delta(r) + c[0] * X0[r];
+    } else if (m == 2) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) AC[r] = ln.delta(r) + c[0] * X0[r] + c[1] * X1[r];
+    } else {
+      q4 W;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) W[r] = c[3] * X0[r] + c[4] * X1[r];
+      t_put(L, ln, W);
+      t_zero(AC);
+      t_gemm(L, ln, X1, AC);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) AC[r] = ln.delta(r) + c[0] * X0[r] + c[1] * (AC[r] + c[2] * X1[r]);
+    }
+  } else {
+    if (m == 6) t_ps_horner<3, 2>(L, ln, X0, X1, X2, X3, AC);
+    else if (m == 9) t_ps_horner<3, 3>(L, ln, X0, X1, X2, X3, AC);
+    else if (m == 12) t_ps_horner<3, 4>(L, ln, X0, X1, X2, X3, AC);
+    else t_ps_horner<4, 4>(L, ln, X0, X1, X2, X3, AC);
+  }
+  t_squarings(L, ln, s, AC);
+  return true;
+}
+
+constexpr int kGjLd = 33;  // row stride of the wave's 16 x 32 elimination tile
+
+// Solves M R = B in place on the wave's tile G = [M | B] (16 rows, columns 0..15 and 16..31):
+// Gauss-Jordan elimination with partial pivoting (row k takes the largest |M[i][k]|, i >= k).
+// Lane l eliminates row l / 4 over columns 8 (l % 4) .. 8 (l % 4) + 7.
+__device__ inline void t_gauss_jordan(double *G) {
+  const int lane = lane_id();
+  const int gi = lane >> 2, gc = (lane & 3) * 8;
+  for (int k = 0; k < 16; ++k) {
+    wsync();
+    double v = (lane >= k && lane < 16) ? fabs(G[lane * kGjLd + k]) : -1.0;
+    int idx = lane;
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) {
+      const double ov = __shfl_xor(v, o);
+      const int oi = __shfl_xor(idx, o);
+      if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+    }
+    const int p = __builtin_amdgcn_readfirstlane(idx);  // lane 0 holds the argmax of lanes 0..15
+    if (p != k && lane < 32) {
+      const double x = G[k * kGjLd + lane], y = G[p * kGjLd + lane];
+      G[k * kGjLd + lane] = y;
+      G[p * kGjLd + lane] = x;
+    }
+    wsync();
+    const double piv = G[k * kGjLd + k];
+    wsync();
+    if (lane < 32) G[k * kGjLd + lane] = G[k * kGjLd + lane] / piv;
+    wsync();
+    const double f = G[gi * kGjLd + k];
+    wsync();
+    if (gi != k) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) G[gi * kGjLd + gc + t] -= f * G[k * kGjLd + gc + t];
+    }
+  }
+  wsync();
+}
+
+// The Pade comparison (Sec. 2): (2m, s) by select_pade, r_10 (eq. eq.pade10) or r_26
+// (eq. eq.pade26) at X = 2^-s A, the solve (-U + V) R = U + V, then s squarings.
+__device__ bool t_expm_pade(const Consts &K, double *L, double *G, const TLane &ln, q4 &X0, double eta,
+                            int select_only, int *m_out, int *s_out, q4 &AC) {
+  int m, s;
+  select_pade(K.theta_pade, eta, &m, &s);
+  m = __builtin_amdgcn_readfirstlane(m);
+  s = __builtin_amdgcn_readfirstlane(s);
+  *m_out = m;
+  *s_out = s;
+  if (select_only) return false;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) X0[r] = ldexp(X0[r], -s);
+  q4 A2, A4, U, V;
+  t_put(L, ln, X0);
+  t_zero(A2);
+  t_gemm(L, ln, X0, A2);  // A_2
+  t_put(L, ln, A2);
+  t_zero(A4);
+  t_gemm(L, ln, A2, A4);  // A_4
+  if (m == 10) {
+    double b[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) b[j] = tuni(K.pade5[j]);
+    q4 W;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double d = ln.delta(r);
+      W[r] = b[5] * A4[r] + b[3] * A2[r] + b[1] * d;
+      V[r] = b[4] * A4[r] + b[2] * A2[r] + b[0] * d;
+    }
+    t_put(L, ln, X0);
+    t_zero(U);
+    t_gemm(L, ln, W, U);  // u_5 = A (b5 A_4 + b3 A_2 + b1 I)
+  } else {
+    double b[14];
+#pragma unroll
+    for (int j = 0; j < 14; ++j) b[j] = tuni(K.pade13[j]);
+    q4 A6, W, Z;
+    t_zero(A6);
+    t_gemm(L, ln, A4, A6);  // A_6 = A_2 A_4 (A_2 still in L)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) W[r] = b[13] * A6[r] + b[11] * A4[r] + b[9] * A2[r];
+    t_put(L, ln, A6);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      Z[r] = b[7] * A6[r] + b[5] * A4[r] + b[3] * A2[r] + b[1] * ln.delta(r);
+    t_gemm(L, ln, W, Z);  // A_6 (b13 A_6 + b11 A_4 + b9 A_2) + b7 A_6 + b5 A_4 + b3 A_2 + b1 I
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      W[r] = b[12] * A6[r] + b[10] * A4[r] + b[8] * A2[r];
+      V[r] = b[6] * A6[r] + b[4] * A4[r] + b[2] * A2[r] + b[0] * ln.delta(r);
+    }
+    t_gemm(L, ln, W, V);  // v_13 (A_6 still in L)
+    t_put(L, ln, X0);
+    t_zero(U);
+    t_gemm(L, ln, Z, U);  // u_13 = A ( ... )
+  }
+  wsync();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    G[ln.row(r) * kGjLd + ln.lr] = V[r] - U[r];
+    G[ln.row(r) * kGjLd + 16 + ln.lr] = V[r] + U[r];
+  }
+  t_gauss_jordan(G);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) AC[r] = G[ln.row(r) * kGjLd + 16 + ln.lr];
+  t_squarings(L, ln, s, AC);
+  return true;
+}
+
 __device__ inline void copy_consts(const Consts &src, Consts *dst) {
   const double *s = reinterpret_cast<const double *>(&src);
   double *d = reinterpret_cast<double *>(dst);
@@ -369,9 +586,10 @@ __device__ inline TItem t_item(const FusedArgs &a, int64_t idx) {
 // Persistent: each wave takes matrices from its sweep until the range is empty.  The next
 // matrix's load is issued before the current one is computed, so every wave keeps an HBM
 // read in flight while its MFMA chain runs.
-template <int SEL>
+template <int SEL, int METHOD>
 __global__ __launch_bounds__(64 * kTinyW, SEL == EXPM_SEL_PLAIN ? 4 : 2) void expm_tiny_kernel(FusedArgs a) {
   __shared__ double tiles[kTinyW * kTinyTile];
+  __shared__ double gj[METHOD == 2 ? kTinyW * 16 * kGjLd : 1];
   __shared__ Consts K;
   copy_consts(a.k, &K);
   Theta th;
@@ -415,7 +633,12 @@ __global__ __launch_bounds__(64 * kTinyW, SEL == EXPM_SEL_PLAIN ? 4 : 2) void ex
     } else {
       q4 AC;
       int m, s;
-      const bool full = t_expm<SEL>(K, th, L, ln, Xc, t_norm1(Xc), a.select_only, &m, &s, AC);
+      bool full;
+      if constexpr (METHOD == 1) full = t_expm_ps(K, L, ln, Xc, t_norm1(Xc), a.select_only, &m, &s, AC);
+      else if constexpr (METHOD == 2)
+        full = t_expm_pade(K, L, gj + (threadIdx.x >> 6) * 16 * kGjLd, ln, Xc, t_norm1(Xc), a.select_only, &m, &s,
+                           AC);
+      else full = t_expm<SEL>(K, th, L, ln, Xc, t_norm1(Xc), a.select_only, &m, &s, AC);
       if (head) {
         a.m_out[b] = m; a.s_out[b] = s;
         if (a.status) a.status[b] = EXPM_OK;
@@ -501,17 +724,21 @@ __global__ __launch_bounds__(64 * kTinyW, SEL == EXPM_SEL_PLAIN ? 4 : 2) void ex
 
 int tiny_max_blocks_per_cu() {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, expm_tiny_kernel<EXPM_SEL_PLAIN>, 64 * kTinyW, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, expm_tiny_kernel<EXPM_SEL_PLAIN, 0>, 64 * kTinyW, 0) !=
       hipSuccess)
     return 1;
   return nb < 1 ? 1 : nb;
 }
 
 hipError_t launch_tiny(const FusedArgs &a, int grid, hipStream_t st) {
-  if (a.sel == EXPM_SEL_ALPHA)
-    hipLaunchKernelGGL(expm_tiny_kernel<EXPM_SEL_ALPHA>, dim3(grid), dim3(64 * kTinyW), 0, st, a);
+  if (a.method == 1)
+    hipLaunchKernelGGL((expm_tiny_kernel<EXPM_SEL_PLAIN, 1>), dim3(grid), dim3(64 * kTinyW), 0, st, a);
+  else if (a.method == 2)
+    hipLaunchKernelGGL((expm_tiny_kernel<EXPM_SEL_PLAIN, 2>), dim3(grid), dim3(64 * kTinyW), 0, st, a);
+  else if (a.sel == EXPM_SEL_ALPHA)
+    hipLaunchKernelGGL((expm_tiny_kernel<EXPM_SEL_ALPHA, 0>), dim3(grid), dim3(64 * kTinyW), 0, st, a);
   else
-    hipLaunchKernelGGL(expm_tiny_kernel<EXPM_SEL_PLAIN>, dim3(grid), dim3(64 * kTinyW), 0, st, a);
+    hipLaunchKernelGGL((expm_tiny_kernel<EXPM_SEL_PLAIN, 0>), dim3(grid), dim3(64 * kTinyW), 0, st, a);
   return hipGetLastError();
 }
 

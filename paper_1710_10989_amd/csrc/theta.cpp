@@ -86,6 +86,26 @@ bool make_consts(double u, Consts *k) {
     if (!theta_of(kDeg[i], u, &k->theta[i])) return false;
   for (int i = 0; i < kNumPs; ++i)
     if (!theta_of(kPsDeg[i], u, &k->theta_ps[i])) return false;
+  // Pade: b_j = (2m - j)! m! / ((2m)! (m - j)! j!) (eq. eq.24), as running products
+  auto pade_b = [](int m, double *b) {
+    for (int j = 0; j <= m; ++j) {
+      ld v = 1.0L;
+      for (int t = 0; t < j; ++t) v *= (ld)(m - t) / (ld)(2 * m - t);
+      for (int t = 2; t <= j; ++t) v /= (ld)t;
+      b[j] = (double)v;
+    }
+  };
+  pade_b(5, k->pade5);
+  pade_b(13, k->pade13);
+  // theta_10, theta_26 of Table 1, one unit of the third printed digit below the printed value
+  // (a printed value may be rounded up; this one is not above the true threshold)
+  if (u == 0x1p-53) {
+    k->theta_pade[0] = 2.53e-1; k->theta_pade[1] = 5.36;
+  } else if (u == 0x1p-24) {
+    k->theta_pade[0] = 1.87; k->theta_pade[1] = 11.1;
+  } else {
+    k->theta_pade[0] = k->theta_pade[1] = 0.0;
+  }
   // T_8 (eq. Algorithm83eA), free parameter x3 = 2/3, closed forms in sqrt(177).
   const ld r = sqrtl(177.0L), x3 = 2.0L / 3.0L;
   k->t8[0] = (double)(x3 * (1.0L + r) / 88.0L);                 // x1

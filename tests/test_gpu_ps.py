@@ -1,5 +1,6 @@
-"""GPU parity of the Paterson-Stockmeyer comparison method (EXPM_FLAG_PS: the plain Taylor
-polynomial by eq. poli9 on the tiled path) against the CPU oracle.
+"""GPU parity of the comparison methods against the CPU oracle: Paterson-Stockmeyer
+(EXPM_FLAG_PS: the plain Taylor polynomial by eq. poli9; tiled path above real order 16, one
+wave per matrix up to 16) and diagonal Pade r_10 / r_26 (EXPM_FLAG_PADE, one wave per matrix).
 
 Tolerances as for the paper's method: relative 1-norm error <= 1e-12 against the oracle's
 long-double direct Taylor e^A, and <= max(1e-12, 64 u 2^s) against the oracle's long-double
@@ -107,3 +108,67 @@ def test_select_only_and_rejections(P, orc):
                               ctypes.byref(o), X._ptr(outs[0]), X._ptr(outs[1]), X._ptr(outs[2]), X._ptr(ws),
                               ws.numel(), X._stream())
     assert st == N.EXPM_E_UNSUPPORTED
+
+
+# ---- the comparison methods on the one-wave kernel (real order <= 16) ----
+
+@pytest.mark.parametrize("target", [1e-17, 1e-9, 1e-4, 5e-3, 0.05, 0.2, 0.5, 2.0, 30.0])
+def test_ps_small_orders(P, orc, target):
+    g = np.random.default_rng(int(target * 1e7) % 997)
+    mats = []
+    for n in (3, 9, 16):
+        A = g.standard_normal((n, n))
+        mats.append(A * (target / np.abs(A).sum(0).max()))
+    for A in mats:
+        E, m, s, st = P.taylor(dev(A), method="ps")
+        torch.cuda.synchronize()
+        m, s = int(m.item()), int(s.item())
+        assert int(st.item()) == 0
+        assert (m, s) == orc.select_ps(orc.norm1(A))
+        check(orc, A, E.cpu().numpy(), m, s)
+
+
+@pytest.mark.parametrize("target,expect", [(0.1, (10, 0)), (1.0, (10, 2)), (4.0, (26, 0)), (10.0, (26, 1)),
+                                           (100.0, (26, 5))])
+def test_pade_small_orders(P, orc, target, expect):
+    g = np.random.default_rng(int(target * 100) + 3)
+    for n in (2, 7, 16):
+        A = g.standard_normal((n, n))
+        A *= target / np.abs(A).sum(0).max()
+        say("case pade n=%d" % n, expect)
+        E, m, s, st = P.taylor(dev(A), method="pade")
+        torch.cuda.synchronize()
+        m, s = int(m.item()), int(s.item())
+        assert int(st.item()) == 0
+        assert (m, s) == expect == orc.select_pade(orc.norm1(A))
+        ref, _ = orc.expm_taylor(A)
+        assert orc.rel_err_1(E.cpu().numpy(), ref) <= TOL
+        own = orc.expm_pade(A, m, s)
+        assert orc.rel_err_1(E.cpu().numpy(), own) <= max(TOL, 64 * 2.0 ** -53 * (1 << s))
+
+
+def test_comparisons_uniform_small_batch(P, orc):
+    from paper_1710_10989_amd import workloads as W
+    A = W.small_skew_batch(count=257, n=16, seed_stream=5)
+    for method, rule, own in (("ps", orc.select_ps, orc.expm_ps), ("pade", orc.select_pade, orc.expm_pade)):
+        say("case uniform small", method)
+        E, m, s, st = P.batched_uniform(dev(A), method=method)
+        torch.cuda.synchronize()
+        E, m, s = E.cpu().numpy(), m.cpu().numpy(), s.cpu().numpy()
+        assert bool((st == 0).all())
+        for i in range(0, 257, 16):
+            assert (m[i], s[i]) == rule(orc.norm1(A[i]))
+            ref, _ = orc.expm_taylor(A[i])
+            assert orc.rel_err_1(E[i], ref) <= TOL
+            assert np.abs(E[i].T @ E[i] - np.eye(16)).max() <= 1e-13
+
+
+def test_pade_rejections(P):
+    from paper_1710_10989_amd import _native as N
+    g = np.random.default_rng(4)
+    with pytest.raises(N.ExpmError) as e:
+        P.taylor(dev(g.standard_normal((17, 17))), method="pade")
+    assert e.value.code == N.EXPM_E_UNSUPPORTED
+    with pytest.raises(N.ExpmError) as e:
+        P.taylor(dev(g.standard_normal((5, 5))), method="pade", u=2.0 ** -40)
+    assert e.value.code == N.EXPM_E_UNSUPPORTED
