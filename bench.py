@@ -22,6 +22,8 @@ Other workloads (one JSON line each, selected with --workload):
              (the exponents of a Magnus integrator; one wave per matrix)
   magnus     one fourth-order Magnus step for 65536 linear systems Y' = (S0 + u(t) S1) Y of
              order 16 (expm_magnus4_step: exponent, e^Omega and its product with Y on chip)
+  triangular 64 upper triangular FP64 matrices of order 512 with a widely spread diagonal, with
+             and without the triangular refinement (EXPM_FLAG_TRI)
   copy       device-to-device copy of a 1 GiB buffer (the known-size calibration kernel
              for HBM byte counters; not a matrix-exponential figure)
 
@@ -458,6 +460,37 @@ def run_magnus(args, torch, P, W):
                 unit="steps/s")
 
 
+def run_triangular(args, torch, P, W):
+    count, n = 64, 512
+    A = W.triangular_batch(count=count, n=n)
+    Ad = torch.from_numpy(A).cuda()
+    ws = torch.empty(P.workspace_bytes(n, count, method="tri"), dtype=torch.uint8, device="cuda")
+    out = torch.empty_like(Ad)
+    outs = tuple(torch.empty(count, dtype=torch.int32, device="cuda") for _ in range(3))
+    d = torch.from_numpy(np.exp(A[:, np.arange(n), np.arange(n)])).cuda()
+    res = {}
+    for mt in ("reduced", "tri"):  # both on the tiled path (n = 512)
+        ms = timed(torch, args, lambda: P.batched_uniform(Ad, workspace=ws, out=out, outs=outs, method=mt))
+        diag = torch.diagonal(out, dim1=1, dim2=2)
+        res[mt] = {"ms": ms, "max_rel_err_diagonal": float(((diag - d).abs() / d).max())}
+    m, s, st = (x.cpu().numpy() for x in outs)
+    assert np.all(st == 0)
+    ms = res["tri"]["ms"]
+    flops = executed_flops(m, s, [n] * count)
+    roof = {"bound": "mfma", "kernel": "lg_gemm_kernel (tiled 128x128, all GEMM steps) + lg_tri_fix_kernel",
+            "achieved": flops / (ms * 1e-3) / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+            "frac": flops / (ms * 1e-3) / PEAK_FP64, "traffic": None, "kernel_ms": ms}
+    cpu = None if args.no_cpu else cpu_oracle([A[0]], args.cpu_seconds, "1 of the 64 matrices")
+    config = {"workload": "%d upper triangular FP64 matrices of order %d, diagonal uniform in [-40, 0], strictly "
+                          "upper N(0,1)/sqrt(n); one expm_batched_uniform call per step with the triangular "
+                          "refinement (EXPM_FLAG_TRI)" % (count, n),
+              "unrefined_ms": res["reduced"]["ms"], "refined_ms": ms,
+              "max_rel_err_diagonal": {k: v["max_rel_err_diagonal"] for k, v in res.items()},
+              "mean_products_plus_squarings": float(np.mean([PRODUCTS[int(a)] + int(b) for a, b in zip(m, s)]))}
+    return line(args, "expm matrices/s (triangular refinement, FP64)", count / (ms * 1e-3), ms, "f64", config, roof,
+                cpu)
+
+
 def run_copy(args, torch, P, W):
     nbytes = 1 << 30
     src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
@@ -484,7 +517,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="batched", choices=["batched", "single", "precision", "complex", "learned",
-                                                             "small", "magnus", "copy"])
+                                                             "small", "magnus", "triangular", "copy"])
     ap.add_argument("--selector", default="plain", choices=["plain", "alpha"])
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3", "fp32all"])
     ap.add_argument("--method", default="reduced", choices=["reduced", "ps", "pade"],
@@ -503,7 +536,8 @@ def main():
     import paper_1710_10989_amd as P
     from paper_1710_10989_amd import workloads as W
     fn = {"batched": run_batched, "single": run_single, "precision": run_precision, "complex": run_complex,
-          "learned": run_learned, "small": run_small, "magnus": run_magnus, "copy": run_copy}
+          "learned": run_learned, "small": run_small, "magnus": run_magnus,
+          "triangular": run_triangular, "copy": run_copy}
     print(json.dumps(fn[args.workload](args, torch, P, W)), flush=True)
 
 

@@ -102,11 +102,21 @@ typedef enum { EXPM_SEL_PLAIN = 0, EXPM_SEL_ALPHA = 1, EXPM_SEL_LEARNED = 2 } ex
 #define EXPM_FLAG_PS 1
 #define EXPM_FLAG_PADE 2
 
+/* Triangular refinement (expm_opts_t.flags = EXPM_FLAG_TRI, on its own; concluding remarks,
+ * after the alpha_p paper it cites): when a real input is upper triangular, the diagonal and
+ * the first superdiagonal of T_m(2^-s A) and of every squared iterate are overwritten with the
+ * exact values of the exponential (exp(2^(r-s) a_ii), and the (1, 2) entry of the exponential
+ * of each 2 x 2 diagonal block); other inputs are unaffected.  Real FP64 inputs, any order, on
+ * the tiled path (expm_taylor, expm_batched_uniform, expm_select); complex inputs and the other
+ * calls return EXPM_E_UNSUPPORTED. */
+#define EXPM_FLAG_TRI 4
+
 typedef struct {
   int32_t dtype;  /* expm_dtype_t */
   int32_t prec;   /* expm_prec_t */
   int32_t sel;    /* expm_sel_t */
-  int32_t flags;  /* 0, EXPM_FLAG_PS or EXPM_FLAG_PADE; anything else: EXPM_E_INVALID_ARG */
+  int32_t flags;  /* 0 or one of EXPM_FLAG_PS, EXPM_FLAG_PADE, EXPM_FLAG_TRI; anything else:
+                     EXPM_E_INVALID_ARG */
   double u;       /* target relative backward error; 0 = the form's default (2^-24 for FP32
                      and FP32_ALL, 2^-53 otherwise) */
 } expm_opts_t;

@@ -311,3 +311,36 @@ def expm_pade(A, deg, s):
     if lib().or_pade_ms(A.shape[0], _p(A), int(deg) // 2, int(s), _p(E)) < 0:
         raise ValueError("singular denominator")
     return E
+
+
+# ---- triangular refinement (concluding remarks) ----
+
+def _tri_fix(T, A, f):
+    """Replaces the diagonal and first superdiagonal of T (long double, in place) by those of
+    e^(f A) for upper triangular A: exp(f a_ii), and for each 2 x 2 diagonal block
+    [[x1, y], [0, x2]] of f A the (1, 2) entry y (e^x2 - e^x1) / (x2 - x1), written as
+    y e^((x1 + x2) / 2) sinh(d) / d with d = (x2 - x1) / 2 (y e^x1 when x1 = x2)."""
+    n = T.shape[0]
+    for i in range(n):
+        x1 = f * A[i, i]
+        T[i, i] = np.exp(x1)
+        if i + 1 < n:
+            x2, y = f * A[i + 1, i + 1], f * A[i, i + 1]
+            d = (x2 - x1) / 2
+            T[i, i + 1] = y * np.exp((x1 + x2) / 2) * (np.sinh(d) / d if d != 0 else 1)
+
+
+def expm_reduced_tri(A, m, s):
+    """The method's output with the triangular refinement for an upper triangular A, long
+    double: T_m(2^-s A) by the product-reduced sequences, its diagonal and first superdiagonal
+    replaced by those of e^(2^-s A), then s squarings, each followed by the same replacement
+    for e^(2^(r-s) A)."""
+    A = _f64(A)
+    Al = A.astype(np.longdouble)
+    T, _ = reduced_Tm(np.ldexp(A, -s), m)
+    T = T.astype(np.longdouble)
+    _tri_fix(T, Al, np.ldexp(np.longdouble(1.0), -s))
+    for r in range(1, s + 1):
+        T = T @ T
+        _tri_fix(T, Al, np.ldexp(np.longdouble(1.0), r - s))
+    return np.asarray(T, dtype=np.float64)

@@ -14,7 +14,7 @@ EXPM_OK, EXPM_E_INVALID_ARG, EXPM_E_NONFINITE, EXPM_E_WORKSPACE, EXPM_E_HIP, EXP
 EXPM_F64, EXPM_C128 = 0, 1
 EXPM_PREC_FP64, EXPM_PREC_FP32, EXPM_PREC_BF16X3, EXPM_PREC_FP32_ALL = 0, 1, 2, 3
 EXPM_SEL_PLAIN, EXPM_SEL_ALPHA, EXPM_SEL_LEARNED = 0, 1, 2
-EXPM_FLAG_PS, EXPM_FLAG_PADE = 1, 2
+EXPM_FLAG_PS, EXPM_FLAG_PADE, EXPM_FLAG_TRI = 1, 2, 4
 
 EXPORTED = ("expm_status_string", "expm_theta", "expm_select_rule", "expm_workspace_bytes",
             "expm_select", "expm_taylor", "expm_batched", "expm_batched_stage", "expm_batched_uniform",

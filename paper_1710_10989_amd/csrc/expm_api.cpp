@@ -43,7 +43,8 @@ expm_status_t check_opts(const expm_opts_t *o, double *u) {
   if (o->dtype != EXPM_F64 && o->dtype != EXPM_C128) return EXPM_E_INVALID_ARG;
   if (o->prec < EXPM_PREC_FP64 || o->prec > EXPM_PREC_FP32_ALL) return EXPM_E_INVALID_ARG;
   if (o->sel < EXPM_SEL_PLAIN || o->sel > EXPM_SEL_LEARNED) return EXPM_E_INVALID_ARG;
-  if (o->flags != 0 && o->flags != EXPM_FLAG_PS && o->flags != EXPM_FLAG_PADE) return EXPM_E_INVALID_ARG;
+  if (o->flags != 0 && o->flags != EXPM_FLAG_PS && o->flags != EXPM_FLAG_PADE && o->flags != EXPM_FLAG_TRI)
+    return EXPM_E_INVALID_ARG;
   double uu = o->u == 0.0 ? default_u(o->prec) : o->u;
   if (!(uu >= 0x1p-53 && uu <= 0x1p-10)) return EXPM_E_INVALID_ARG;
   *u = uu;
@@ -188,16 +189,17 @@ expm_status_t expm_select_rule(const double *norms, int32_t sel, double u, int32
   return EXPM_OK;
 }
 
-// The reduced forms and the Paterson-Stockmeyer comparison above real order 16 run the tiled
-// path (the Pade comparison exists for real orders <= 16 only).
+// The reduced forms, the triangular refinement and the Paterson-Stockmeyer comparison above
+// real order 16 run the tiled path (the Pade comparison exists for real orders <= 16 only).
 static int64_t real_order(const expm_opts_t *o, int64_t n);
 static bool tiled_only(const expm_opts_t *o, int64_t n = 0) {
-  return o->prec != EXPM_PREC_FP64 || ((o->flags & EXPM_FLAG_PS) && real_order(o, n) > 16);
+  return o->prec != EXPM_PREC_FP64 || (o->flags & EXPM_FLAG_TRI) || ((o->flags & EXPM_FLAG_PS) && real_order(o, n) > 16);
 }
 // Comparison methods on the fused kernels: FP64, plain rule, real order <= 16 (one wave per
 // matrix), Pade only for the two printed rows of u.
 static expm_status_t method_check(const expm_opts_t *o, int64_t n, double u) {
   if (o->flags == 0) return EXPM_OK;
+  if (o->flags == EXPM_FLAG_TRI) return o->dtype == EXPM_F64 ? EXPM_OK : EXPM_E_UNSUPPORTED;
   if (o->prec != EXPM_PREC_FP64 || o->sel != EXPM_SEL_PLAIN) return EXPM_E_UNSUPPORTED;
   if ((o->flags & EXPM_FLAG_PADE) && (real_order(o, n) > 16 || (u != 0x1p-53 && u != 0x1p-24)))
     return EXPM_E_UNSUPPORTED;
@@ -370,6 +372,7 @@ static expm_status_t run_large_call(const void *A, void *E, int64_t n, int64_t b
   c.prec = opts->prec;  // expm_prec_t values match PREC_F64 / PREC_F32 / PREC_BF16X3
   c.select_only = select_only;
   c.ps = ps ? 1 : 0;
+  c.tri = (opts->flags & EXPM_FLAG_TRI) ? 1 : 0;
   c.m_out = m_dev;
   c.s_out = s_dev;
   c.status = status_dev;

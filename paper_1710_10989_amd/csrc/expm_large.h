@@ -31,6 +31,7 @@ struct LargeCall {
   int prec;           // PREC_F64 / PREC_F32 / PREC_BF16X3 for the reduced steps
   int select_only;
   int ps;             // Paterson-Stockmeyer comparison method (EXPM_FLAG_PS)
+  int tri;            // triangular refinement (EXPM_FLAG_TRI)
   int32_t *m_out, *s_out, *status;  // device, one per matrix
   void *ws;
   size_t ws_bytes;

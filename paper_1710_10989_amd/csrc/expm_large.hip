@@ -64,6 +64,7 @@ struct LargeArgs {
   const int32_t *list;     // matrices (group-relative) of this launch
   int round;               // squaring round (1-based) for SEL_SQ*
   int ps;                  // Paterson-Stockmeyer comparison method
+  const int *flags;        // per matrix: bit 0 non-finite input, bit 1 not upper triangular
   int coff;                // first coefficient of this step in the matrix's 64
   // step description
   int kind;                // epilogue kind (GEMM) or elementwise kind
@@ -109,7 +110,7 @@ __global__ __launch_bounds__(256) void lg_load_kernel(LargeArgs a, double *parti
   cgdouble *A = gptr(a.A + (a.g0 + mi) * a.io_stride);
   gdouble *B0 = gptr(a.ws + (size_t)mi * a.mstride);
   double acc = 0.0;
-  int bad = 0;
+  int bad = 0, lower = 0;
   for (int r0 = rb * kLargeRB; r0 < (rb + 1) * kLargeRB; r0 += 16) {
     double v[16];
 #pragma unroll
@@ -131,12 +132,45 @@ __global__ __launch_bounds__(256) void lg_load_kernel(LargeArgs a, double *parti
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       bad |= !isfinite(v[u]);
+      lower |= (r0 + u > col) && v[u] != 0.0;
       acc += fabs(v[u]);
       B0[(size_t)(r0 + u) * np + col] = v[u];
     }
   }
   partial[((size_t)mi * nrb + rb) * np + col] = acc;
-  if (bad) atomicOr(&flags[mi], 1);
+  if (bad || lower) atomicOr(&flags[mi], (bad ? 1 : 0) | (lower ? 2 : 0));
+}
+
+// Triangular refinement (concluding remarks; the technique of the alpha_p paper it cites): for
+// an upper triangular input, the current iterate approximates e^(2^(r - s) A) after round r of
+// the squarings (r = 0: T_m itself).  Its diagonal is set to exp(2^(r-s) a_ii) and its first
+// superdiagonal to the exact (1, 2) entry of the exponential of the 2 x 2 block
+// [[x1, y], [0, x2]] = 2^(r-s) [[a_ii, a_i,i+1], [0, a_i+1,i+1]]:
+//   y exp((x1 + x2) / 2) sinh(d) / d,  d = (x2 - x1) / 2   (y exp(x1) when d = 0).
+// The iterate lives where that round wrote it (a work buffer, or e^A after the last round).
+// Grid (ceil(n / 256), count).
+__global__ __launch_bounds__(256) void lg_tri_fix_kernel(LargeArgs a) {
+  const int mi = a.list[blockIdx.y];
+  const int64_t gb = a.g0 + mi;
+  const int m = a.m_arr[gb], s = a.s_arr[gb];
+  if (m < 1 || (a.flags[mi] & 2)) return;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int n = a.n, np = a.np;
+  if (i >= n) return;
+  // the caller's input (real, n x n): the product stage reuses the work buffer that held A
+  cgdouble *A = gptr(a.A + gb * a.io_stride);
+  double *dstp = sel_ptr(a, mi, a.round == 0 ? SEL_TDST : SEL_SQDST, m, s);
+  gdouble *dst = dstp ? gptr(dstp) : gptr(a.E + gb * a.io_stride);
+  const int ld = dstp ? np : n;
+  const double f = ldexp(1.0, a.round - s);
+  const double x1 = f * A[(size_t)i * n + i];
+  dst[(size_t)i * ld + i] = exp(x1);
+  if (i + 1 < n) {
+    const double x2 = f * A[(size_t)(i + 1) * n + i + 1], y = f * A[(size_t)i * n + i + 1];
+    const double d = 0.5 * (x2 - x1);
+    const double sh = d == 0.0 ? 1.0 : sinh(d) / d;
+    dst[(size_t)i * ld + i + 1] = y * exp(0.5 * (x1 + x2)) * sh;
+  }
 }
 
 // Partial column sums of |buffer sel| for the listed matrices.  Grid (np / 256, nrb, count).
@@ -184,7 +218,7 @@ __global__ void lg_select_kernel(LargeArgs a, int count, int stride, const unsig
   if (mi >= count) return;
   const int64_t gb = a.g0 + mi;
   int32_t *m_arr = const_cast<int32_t *>(a.m_arr), *s_arr = const_cast<int32_t *>(a.s_arr);
-  if (flags[mi]) {
+  if (flags[mi] & 1) {
     m_arr[gb] = -1; s_arr[gb] = -1;
     if (status) status[gb] = EXPM_E_NONFINITE;
     return;
@@ -369,6 +403,17 @@ struct Launcher {
     if (hipGetLastError() != hipSuccess) ok = false;
   }
 
+  // triangular refinement of the iterate after squaring round `round` (0: T_m)
+  void tri(const std::vector<int32_t> &idx, int slot, int round) {
+    if (idx.empty() || !ok) return;
+    LargeArgs a = base;
+    a.list = upload(idx, slot);
+    a.round = round;
+    hipLaunchKernelGGL(lg_tri_fix_kernel, dim3((unsigned)((L.n + 255) / 256), (unsigned)idx.size()), dim3(256), 0, st,
+                       a);
+    if (hipGetLastError() != hipSuccess) ok = false;
+  }
+
   void elem(const std::vector<int32_t> &idx, int slot, int kind, int dst, int coff = 0) {
     if (idx.empty() || !ok) return;
     LargeArgs a = base;
@@ -406,6 +451,7 @@ expm_status_t run_large(const LargeCall &c, hipStream_t st) {
   a.m_arr = c.m_out; a.s_arr = c.s_out;
   a.coef = coef;
   a.ps = c.ps;
+  a.flags = flags;
   for (int j = 0; j < 5; ++j) a.o[j] = SEL_NONE;
 
   std::vector<int32_t> mh, sh;
@@ -488,6 +534,9 @@ expm_status_t run_large(const LargeCall &c, hipStream_t st) {
     }
     run.gemm(l4, 20, EK_STORE, 1, 1, 3);  // A^4 = A^2 A^2 (base of the degree-16 rule)
     run.elem(lnan, 1, LCNAN, SEL_NONE);
+    std::vector<int32_t> lvalid;
+    for (int i = 0; i < cnt; ++i)
+      if (mh[i] >= 1) lvalid.push_back(i);
     // ---- product stage per degree ----
     run.elem(lm[1], 2, LC1, SEL_TDST);
     run.elem(lm[2], 3, LC2, SEL_TDST);
@@ -518,11 +567,13 @@ expm_status_t run_large(const LargeCall &c, hipStream_t st) {
       run.gemm(lm[18], 7, EK_ADD1, 1, 0, SEL_TDST, 4);
     }
     // ---- squarings: round r covers the matrices with s >= r ----
+    if (c.tri) run.tri(lvalid, 30, 0);
     for (int r = 1; r <= smax; ++r) {
       std::vector<int32_t> lr;
       for (int i = 0; i < cnt; ++i)
         if (mh[i] >= 1 && sh[i] >= r) lr.push_back(i);
       run.gemm(lr, 8 + (r & 1) * 8, EK_STORE, SEL_SQSRC, SEL_SQSRC, SEL_SQDST, SEL_NONE, SEL_NONE, {}, r);
+      if (c.tri) run.tri(lr, 8 + (r & 1) * 8, r);
     }
     if (!run.ok) return EXPM_E_HIP;
     // lists are uploaded asynchronously from host vectors that die here: finish the group

@@ -15,12 +15,13 @@ _PREC = {"fp64": N.EXPM_PREC_FP64, "fp32": N.EXPM_PREC_FP32, "bf16x3": N.EXPM_PR
 _SEL = {"plain": N.EXPM_SEL_PLAIN, "alpha": N.EXPM_SEL_ALPHA, "learned": N.EXPM_SEL_LEARNED}
 
 
-_METHOD = {"reduced": 0, "ps": N.EXPM_FLAG_PS, "pade": N.EXPM_FLAG_PADE}
+_METHOD = {"reduced": 0, "ps": N.EXPM_FLAG_PS, "pade": N.EXPM_FLAG_PADE, "tri": N.EXPM_FLAG_TRI}
 
 
 def _opts(dtype, prec, selector, u, method="reduced"):
     """method: "reduced" (the paper's product-reduced T_m), "ps" (the Paterson-Stockmeyer
-    comparison, EXPM_FLAG_PS) or "pade" (diagonal Pade r_10 / r_26, EXPM_FLAG_PADE)."""
+    comparison, EXPM_FLAG_PS), "pade" (diagonal Pade r_10 / r_26, EXPM_FLAG_PADE) or "tri"
+    (the paper's T_m with the triangular refinement, EXPM_FLAG_TRI)."""
     return N.ExpmOpts(N.EXPM_C128 if dtype == torch.complex128 else N.EXPM_F64, _PREC[prec],
                       _SEL[selector], _METHOD[method], 0.0 if u is None else float(u))
 

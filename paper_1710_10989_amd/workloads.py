@@ -140,3 +140,15 @@ def small_skew_batch(count=65536, n=16, norm_range=(0.05, 1.0), config_id=7, see
     nr[nr == 0] = 1.0
     target = np.exp(g.uniform(np.log(norm_range[0]), np.log(norm_range[1]), count))
     return np.ascontiguousarray(S * (target / nr)[:, None, None])
+
+
+def triangular_batch(count=64, n=512, spread=40.0, config_id=8, seed_stream=0):
+    """count upper triangular n x n matrices whose diagonal spreads over [-spread, 0]
+    (uniform) with strictly upper entries N(0, 1) / sqrt(n): the inputs where overwriting the
+    diagonal of the squared iterates with exact values matters (many squarings, entries of very
+    different size).  Returns a (count, n, n) array."""
+    g = rng(config_id, seed_stream)
+    A = np.triu(g.standard_normal((count, n, n)), 1) / np.sqrt(n)
+    idx = np.arange(n)
+    A[:, idx, idx] = -g.uniform(0.0, spread, (count, n))
+    return np.ascontiguousarray(A)
