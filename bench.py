@@ -183,7 +183,7 @@ def run_single(args, torch, P, W):
     fl = executed_flops([int(m.item())], [int(s.item())], [64])
     cpu = None if args.no_cpu else cpu_oracle([A.cpu().numpy()] * 64, args.cpu_seconds, "64 copies of the matrix")
     one_cu = PEAK_FP64 / 256
-    roof = {"bound": "mfma", "kernel": "expm_fused_kernel<4> (one workgroup, latency-bound)",
+    roof = {"bound": "mfma", "kernel": "expm_resident_kernel<4> (one workgroup of four waves, latency-bound)",
             "achieved": fl / (ms * 1e-3) / 1e12, "peak": one_cu / 1e12, "unit": "TFLOP/s",
             "frac": fl / (ms * 1e-3) / one_cu, "traffic": None, "note": "peak of the one CU a single matrix runs on"}
     config = {"workload": "one 64x64 FP64 matrix, N(0,1) scaled to ||A||_1 = 2, one expm_taylor call per step "
