@@ -304,9 +304,9 @@ static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, cons
       return EXPM_OK;
     }
     // largest orders first; each sweep drains its own range of the sorted queue.  A full call
-    // runs the 8-wave resident sweep on the caller's stream and the other sweeps beside it on
-    // a second stream (fork after the sort, join before return), so the sweeps share the CUs
-    // instead of each waiting for the previous one's last matrices.
+    // runs the sweeps as two chains on the caller's stream and a second stream (fork after
+    // the sort, join before return), so the sweeps share the CUs instead of each waiting for
+    // the previous one's last matrices.
     // sub-sweeps: 3 np 144..256, 4 np 80..96, 5 np 32..64 (np <= 64 without the one-wave
     // kernel), 6 np 16 on the one-wave kernel
     auto sub = [&](int k) -> bool {
@@ -335,9 +335,10 @@ static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, cons
       if (!fork_join_for_device(&fj)) return EXPM_E_HIP;
       if (hipEventRecord(fj.fork, st) != hipSuccess || hipStreamWaitEvent(fj.side, fj.fork, 0) != hipSuccess)
         return EXPM_E_HIP;
-      // the second stream takes the longer chain; the order-16 sweep follows the 8-wave one
-      const bool ok2 = on(fj.side, {3, 4, 5});
-      const bool ok1 = (tmax <= kRes6T || go(K_RES8, r8, 1, 1, 2)) && sub(6);
+      // two chains side by side: np 144..256 then 80..96 on the second stream; 112..128, then
+      // 32..64 and 16 on the caller's (measured best of the arrangements of the four sweeps)
+      const bool ok2 = on(fj.side, {3, 4});
+      const bool ok1 = (tmax <= kRes6T || go(K_RES8, r8, 1, 1, 2)) && sub(5) && sub(6);
       if (hipEventRecord(fj.join, fj.side) != hipSuccess || hipStreamWaitEvent(st, fj.join, 0) != hipSuccess)
         return EXPM_E_HIP;
       if (!ok1 || !ok2) return EXPM_E_HIP;
