@@ -81,7 +81,27 @@ bool theta_of(int m, double u, double *out) {
   return true;
 }
 
+static bool build_consts(double u, Consts *k);
+
+// Consts per u, built once (every call of the library needs them; the thresholds alone take
+// thirteen cached lookups).
 bool make_consts(double u, Consts *k) {
+  static std::mutex mu;
+  static std::map<double, Consts> cache;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(u);
+    if (it != cache.end()) { *k = it->second; return true; }
+  }
+  Consts c;
+  if (!build_consts(u, &c)) return false;
+  std::lock_guard<std::mutex> lk(mu);
+  cache.emplace(u, c);
+  *k = c;
+  return true;
+}
+
+static bool build_consts(double u, Consts *k) {
   for (int i = 0; i < kNumDeg; ++i)
     if (!theta_of(kDeg[i], u, &k->theta[i])) return false;
   for (int i = 0; i < kNumPs; ++i)
