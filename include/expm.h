@@ -160,8 +160,8 @@ EXPM_API expm_status_t expm_taylor(const void *A_dev, void *E_dev, int64_t n, co
  * of A_dev and E_dev (elements of the dtype, not bytes).  n_dev[b] = n_b (int32).  Outputs per
  * matrix: m_dev[b], s_dev[b], status_dev[b].  A device kernel sorts the batch largest order
  * first; persistent launches walk that work queue; no host synchronisation
- * (graph-capturable).  The sweeps of real orders 112..128 and <= 64 run on `stream`, those
- * of 80..96 and 144..256 on a second stream of the device that the library creates once
+ * (graph-capturable).  The sweeps of real orders 112..128 and 17..64 run on `stream`, those
+ * of 144..256, 80..96 and <= 16 on a second stream of the device that the library creates once
  * (default priority); it waits for the sort and `stream` waits for it before the call's work
  * ends, so the call behaves as one operation on `stream` (also under graph capture).  Larger orders:
  * EXPM_E_UNSUPPORTED (use expm_batched_uniform). */

@@ -335,10 +335,10 @@ static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, cons
       if (!fork_join_for_device(&fj)) return EXPM_E_HIP;
       if (hipEventRecord(fj.fork, st) != hipSuccess || hipStreamWaitEvent(fj.side, fj.fork, 0) != hipSuccess)
         return EXPM_E_HIP;
-      // two chains side by side: np 144..256 then 80..96 on the second stream; 112..128, then
-      // 32..64 and 16 on the caller's (measured best of the arrangements of the four sweeps)
-      const bool ok2 = on(fj.side, {3, 4});
-      const bool ok1 = (tmax <= kRes6T || go(K_RES8, r8, 1, 1, 2)) && sub(5) && sub(6);
+      // two chains side by side: np 144..256, 80..96 and 16 on the second stream; 112..128 then
+      // 32..64 on the caller's (the best of the arrangements measured)
+      const bool ok2 = on(fj.side, {3, 4, 6});
+      const bool ok1 = (tmax <= kRes6T || go(K_RES8, r8, 1, 1, 2)) && sub(5);
       if (hipEventRecord(fj.join, fj.side) != hipSuccess || hipStreamWaitEvent(st, fj.join, 0) != hipSuccess)
         return EXPM_E_HIP;
       if (!ok1 || !ok2) return EXPM_E_HIP;
