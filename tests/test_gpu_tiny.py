@@ -258,3 +258,59 @@ def test_magnus_nonfinite_system(P):
     torch.cuda.synchronize()
     assert list(st.cpu().numpy()) == [0, 2, 0]
     assert torch.isnan(Yg[1]).all() and torch.isfinite(Yg[0]).all()
+
+
+def test_graph_capture_of_one_wave_calls(P, orc):
+    # both entry points are graph-capturable: every replay must equal the eager result
+    from paper_1710_10989_amd import workloads as W
+    A = dev(W.small_skew_batch(count=1000, n=16, seed_stream=11))
+    ws = torch.empty(P.workspace_bytes(16, 1000), dtype=torch.uint8, device="cuda")
+    out = torch.empty_like(A)
+    outs = tuple(torch.empty(1000, dtype=torch.int32, device="cuda") for _ in range(3))
+    E0 = P.batched_uniform(A, workspace=ws)[0]
+    h = 0.1
+    S0, S1, Y0, u1, u2, _ = _magnus_inputs(500, 12, h, seed_stream=12)
+    S0d, S1d, Y0d, u1d, u2d = dev(S0), dev(S1), dev(Y0), dev(u1), dev(u2)
+    Yo = torch.empty_like(Y0d)
+    mouts = tuple(torch.empty(500, dtype=torch.int32, device="cuda") for _ in range(3))
+    Y1 = P.magnus4_step(S0d, S1d, Y0d, u1d, u2d, h)[0]
+    P.batched_uniform(A, workspace=ws, out=out, outs=outs)  # warm-up outside capture
+    P.magnus4_step(S0d, S1d, Y0d, u1d, u2d, h, out=Yo, outs=mouts)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        P.batched_uniform(A, workspace=ws, out=out, outs=outs)
+        P.magnus4_step(S0d, S1d, Y0d, u1d, u2d, h, out=Yo, outs=mouts)
+    for rep in range(3):
+        out.fill_(3.0)
+        Yo.fill_(3.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, E0) and torch.equal(Yo, Y1), rep
+        _ = (A * 2).sum().item()  # eager work between replays
+
+
+def test_learned_selector_keeps_small_orders_on_workgroup_kernel(P, orc):
+    # under the learned rule orders <= 16 run on the 4-wave kernel (the network lives there);
+    # with a network that always proposes (1, 0) every choice falls back to the plain rule
+    from paper_1710_10989_amd import learned as LS
+    from paper_1710_10989_amd.expm import Batch
+    net = LS.MLP(batch=8)
+    net.params.zero_()
+    net.params[5760] = 10.0  # b3[0]: constant logits, the argmax is class 0 = (1, 0)
+    net.norm = np.concatenate([np.zeros(8), np.ones(8)])
+    LS.install(net)
+    g = np.random.default_rng(21)
+    mats = [g.standard_normal((n, n)) * (s / n) for n, s in ((4, 0.5), (16, 3.0), (9, 40.0), (30, 2.0), (16, 1e-3))]
+    B = Batch.from_host(mats)
+    E, m, s, st = P.batched(B, selector="learned")
+    torch.cuda.synchronize()
+    outs = B.unpack(E)
+    m, s = m.cpu().numpy(), s.cpu().numpy()
+    assert bool((st == 0).all())
+    for i, A in enumerate(mats):
+        mp, sp = orc.select_plain(orc.norm1(A))
+        assert (m[i], s[i]) == (mp, sp) or (mp, sp) == (1, 0), i
+        ref, _ = orc.expm_taylor(A)
+        assert orc.rel_err_1(outs[i], ref) <= TOL
