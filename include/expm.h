@@ -158,8 +158,10 @@ EXPM_API expm_status_t expm_taylor(const void *A_dev, void *E_dev, int64_t n, co
 /* e^A for `batch` independent matrices of uneven order n_b <= n_max, real order <= 256
  * (complex <= 128), packed: matrix b occupies elements [offsets_dev[b], offsets_dev[b] + n_b^2)
  * of A_dev and E_dev (elements of the dtype, not bytes).  n_dev[b] = n_b (int32).  Outputs per
- * matrix: m_dev[b], s_dev[b], status_dev[b].  A device kernel sorts the batch largest order
- * first; persistent launches walk that work queue; no host synchronisation
+ * matrix: m_dev[b], s_dev[b], status_dev[b].  Device kernels sort the batch largest order
+ * first and, within an order, by a cost estimate from four sampled rows of each matrix
+ * (largest first; the order of the work only, every result is computed from its own exact
+ * norm); persistent launches walk that work queue; no host synchronisation
  * (graph-capturable).  The sweeps of real orders 112..128 and 17..64 run on `stream`, those
  * of 144..256, 80..96 and <= 16 on a second stream of the device that the library creates once
  * (default priority); it waits for the sort and `stream` waits for it before the call's work
@@ -171,7 +173,7 @@ EXPM_API expm_status_t expm_batched(const void *A_dev, void *E_dev, const int64_
                            int32_t *status_dev, void *ws_dev, size_t ws_bytes, void *stream);
 
 /* expm_batched in phases, for callers that time or overlap them: stage 0 sorts the batch into
- * the device work queue (largest real order first); stage 1 runs the 8-wave on-chip kernel
+ * the device work queue (largest real order first, then largest cost estimate); stage 1 runs the 8-wave on-chip kernel
  * over the real orders 112..128 of the queue; stage 2 runs the sweeps of every other order,
  * which are stages 3, 4 and 5 in turn: 3 the real orders 144..256 on the 8-wave global-memory
  * kernel, 4 the orders 80..96 on the split-row on-chip kernel, 5 the orders up to 64 (17..64

@@ -98,7 +98,7 @@ int grid_for(Kern k, int64_t batch) {
 }
 
 struct FusedLayout {
-  size_t queue_off, order_off, slots8_off, slots4_off, slotsr_off, total;
+  size_t queue_off, order_off, key_off, slots8_off, slots4_off, slotsr_off, total;
   size_t slot8_doubles, slot4_doubles, slotr_doubles;
   int slots8, slots4, slotsr;
 };
@@ -121,7 +121,8 @@ FusedLayout fused_layout(int64_t n_max, int64_t batch) {
   L.slotr_doubles = (size_t)kResParkDoublesPerT * tr;
   L.queue_off = 0;
   L.order_off = kAlign;
-  L.slots8_off = L.order_off + align_up(sizeof(int32_t) * (size_t)batch);
+  L.key_off = L.order_off + align_up(sizeof(int32_t) * (size_t)batch);
+  L.slots8_off = L.key_off + align_up((size_t)batch);
   L.slots4_off = L.slots8_off + align_up((size_t)L.slots8 * L.slot8_doubles * sizeof(double));
   L.slotsr_off = L.slots4_off + align_up((size_t)L.slots4 * L.slot4_doubles * sizeof(double));
   L.total = L.slotsr_off + (size_t)L.slotsr * L.slotr_doubles * sizeof(double);
@@ -295,7 +296,9 @@ static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, cons
     unsigned long long *queue = (unsigned long long *)(base + L.queue_off);
     f8.order = f4.order = r8.order = r6.order = r4.order = tn.order = order;
     f8.queue = f4.queue = r8.queue = r6.queue = r4.queue = tn.queue = queue;
-    if ((stage == -1 || stage == 0) && launch_order(ns, batch, cplx, order, queue, st) != hipSuccess)
+    uint8_t *key = (uint8_t *)(base + L.key_off);
+    if ((stage == -1 || stage == 0) &&
+        launch_order(a.A, offs, ns, (int)n_uniform, batch, cplx, key, order, queue, st) != hipSuccess)
       return EXPM_E_HIP;
     if (features) {
       // global-memory kernels: np >= 80 on 8 waves, the rest on 4 waves

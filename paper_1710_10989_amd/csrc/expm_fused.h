@@ -24,6 +24,10 @@ constexpr int kRes6T = 6;
 // 0, first entry with np <= 128, with np <= 96, with np <= 64, with np = 16, batch.
 constexpr int kQBound = 8;
 constexpr int kQWords = 16;
+// Cost keys (one byte per matrix) order the entries of one order largest first: binary
+// exponent of a sampled mean row sum plus kKeyBias, clamped to 1..kKeyBins-1.
+constexpr int kKeyBins = 64;
+constexpr int kKeyBias = 32;
 
 struct FusedArgs {
   const double *A;        // packed inputs
@@ -74,7 +78,9 @@ hipError_t launch_magnus4(const double *S0, const double *S1, int64_t s_stride, 
                           const Consts &k, int32_t *m_out, int32_t *s_out, int32_t *status, int grid,
                           hipStream_t st);
 hipError_t launch_resident(const FusedArgs &a, int nw, int grid, hipStream_t st);  // nw = 8, 12, 4
-hipError_t launch_order(const int32_t *ns, int64_t batch, int cplx, int32_t *order,
-                        unsigned long long *queue, hipStream_t st);
+// Work-queue order of a batch: cost keys of every matrix (into key, batch bytes; skipped when
+// key is null), then the counting sort by (real order, key) into order and the queue words.
+hipError_t launch_order(const double *A, const int64_t *offs, const int32_t *ns, int n_uniform, int64_t batch,
+                        int cplx, uint8_t *key, int32_t *order, unsigned long long *queue, hipStream_t st);
 
 }  // namespace expm

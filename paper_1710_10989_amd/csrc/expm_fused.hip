@@ -1,10 +1,10 @@
 // Persistent fused kernels: e^A for matrices of order n <= 256, one workgroup per matrix.
 //
-// Each workgroup pops matrices from a device work queue (largest order first) and runs the
-// whole method for it: copy A into a zero-padded np x np buffer (np = n rounded up to 16)
-// while taking the 1-norm, choose (m, s), form the powers A^2, A^3 with MFMA GEMMs, build
-// the linear combinations of the product-reduced sequence in GEMM epilogues, run the
-// product stage and the s squarings, and write e^A.  Zero padding is exact: every polynomial
+// Each workgroup pops matrices from a device work queue (largest order first, then largest
+// cost estimate first) and runs the whole method for it: copy A into a zero-padded np x np
+// buffer (np = n rounded up to 16) while taking the 1-norm, choose (m, s), form the powers
+// A^2, A^3 with MFMA GEMMs, build the linear combinations of the product-reduced sequence in
+// GEMM epilogues, run the product stage and the s squarings, and write e^A.  Zero padding is exact: every polynomial
 // in the padded matrix is block diagonal, so the leading n x n block is p(A).
 //
 // Scaling (Sec. 1, eq. eses) is folded into the coefficients: X^k = 2^(-sk) A^k, so the
@@ -534,35 +534,92 @@ __global__ __launch_bounds__(64 * kSrNW, 3) void expm_sr_kernel(FusedArgs a) {
 
 }  // namespace
 
-// Counting sort of the batch by padded order, largest first (the work-queue order); resets
-// the counters and records the range bounds.  One workgroup.
-__global__ void expm_order_kernel(const int32_t *ns, int64_t batch, int cplx, int32_t *order,
-                                  unsigned long long *queue) {
-  __shared__ int hist[18], start[18];
+// Cost key of each matrix for the work-queue order: the binary exponent of the mean absolute
+// row sum of four sampled rows of the real form (an estimate of the mean column sum, a cheap
+// stand-in for ||A||_1, which decides m and s), biased into 1..kKeyBins-1; 0 when the sample
+// is empty, zero or not finite.  One wave per matrix reads at most four rows of it.  The key
+// only orders the work: every matrix is still evaluated from its exact norm.
+__global__ __launch_bounds__(256) void expm_cost_key_kernel(const double *A, const int64_t *offs, const int32_t *ns,
+                                                            int n_uniform, int64_t batch, int cplx, uint8_t *key) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); b < batch; b += (int64_t)gridDim.x * 4) {
+    const int nin = ns ? ns[b] : n_uniform;
+    const int n = cplx ? 2 * nin : nin;
+    double acc = 0.0;
+    int rows = 0;
+    if (nin >= 1 && n <= kNpMax) {
+      const int64_t off = (offs ? offs[b] : b * (int64_t)nin * nin) * (cplx ? 2 : 1);
+      const int len = cplx ? 2 * nin : nin;  // doubles per input row; a complex row's |re| + |im|
+                                             // is the row sum of its row of the real form
+      rows = nin < 4 ? nin : 4;
+      for (int k = 0; k < rows; ++k) {
+        const double *row = A + off + (int64_t)(((2 * k + 1) * nin) / (2 * rows)) * len;
+        for (int j = lane; j < len; j += 64) acc += fabs(row[j]);
+      }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (lane == 0) {
+      int k = 0;
+      if (rows > 0 && acc > 0.0 && isfinite(acc)) {
+        const int e = ilogb(acc / rows) + kKeyBias;
+        k = e < 1 ? 1 : (e > kKeyBins - 1 ? kKeyBins - 1 : e);
+      }
+      key[b] = (uint8_t)k;
+    }
+  }
+}
+
+// Counting sort of the batch into the work-queue order: by padded real order, largest first,
+// and within an order by cost key, largest first (the longest jobs are claimed first, so a
+// sweep does not end on a few expensive matrices claimed late); resets the counters and
+// records the range bounds.  One workgroup of 1024 threads; key may be null (all keys 0).
+__global__ __launch_bounds__(1024) void expm_order_kernel(const int32_t *ns, int n_uniform, const uint8_t *key,
+                                                          int64_t batch, int cplx, int32_t *order,
+                                                          unsigned long long *queue) {
+  constexpr int kCls = 18, kBins = kCls * kKeyBins;
+  static_assert(kBins <= 2 * 1024, "two bins per thread in the scan");
+  __shared__ int hist[kBins], start[kBins], part[1024];
   const int tid = threadIdx.x;
-  if (tid < 18) hist[tid] = 0;
+  for (int i = tid; i < kBins; i += 1024) hist[i] = 0;
   __syncthreads();
-  auto key = [&](int64_t b) {
-    const int n = cplx ? 2 * ns[b] : ns[b];  // order of the real matrix the method runs on
-    if (n < 1 || n > kNpMax) return 17;
-    return 16 - ((n + 15) >> 4);  // 0 for np = 256 ... 15 for np = 16
+  auto bin = [&](int64_t b) {
+    const int nin = ns ? ns[b] : n_uniform;
+    const int n = cplx ? 2 * nin : nin;  // order of the real matrix the method runs on
+    const int cls = (nin < 1 || n > kNpMax) ? 17 : 16 - ((n + 15) >> 4);  // 0 for np = 256 ... 15 for np = 16
+    const int k = key ? (int)key[b] : 0;
+    return cls * kKeyBins + (kKeyBins - 1 - k);
   };
-  for (int64_t b = tid; b < batch; b += blockDim.x) atomicAdd(&hist[key(b)], 1);
+  for (int64_t b = tid; b < batch; b += 1024) atomicAdd(&hist[bin(b)], 1);
+  __syncthreads();
+  // exclusive scan of the bins: thread t owns bins 2t and 2t + 1
+  const int b0 = 2 * tid, b1 = 2 * tid + 1;
+  const int h0 = b0 < kBins ? hist[b0] : 0, h1 = b1 < kBins ? hist[b1] : 0;
+  int v = h0 + h1;
+  part[tid] = v;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int add = tid >= o ? part[tid - o] : 0;
+    __syncthreads();
+    v += add;
+    part[tid] = v;
+    __syncthreads();
+  }
+  if (b0 < kBins) start[b0] = v - h0 - h1;
+  if (b1 < kBins) start[b1] = v - h1;
   __syncthreads();
   if (tid == 0) {
-    int acc = 0;
-    for (int i = 0; i < 18; ++i) { start[i] = acc; acc += hist[i]; }
     for (int i = 0; i < kQBound; ++i) queue[i] = 0ull;
     queue[kQBound + 0] = 0ull;
-    queue[kQBound + 1] = (unsigned long long)start[16 - kResT];       // np <= 128
-    queue[kQBound + 2] = (unsigned long long)start[16 - kRes6T];      // np <= 96
-    queue[kQBound + 3] = (unsigned long long)start[16 - kSplitT + 1];  // np <= 64
-    queue[kQBound + 4] = (unsigned long long)start[15];                // np = 16
+    queue[kQBound + 1] = (unsigned long long)start[(16 - kResT) * kKeyBins];        // np <= 128
+    queue[kQBound + 2] = (unsigned long long)start[(16 - kRes6T) * kKeyBins];       // np <= 96
+    queue[kQBound + 3] = (unsigned long long)start[(16 - kSplitT + 1) * kKeyBins];  // np <= 64
+    queue[kQBound + 4] = (unsigned long long)start[15 * kKeyBins];                  // np = 16
     queue[kQBound + 5] = (unsigned long long)batch;
   }
   __syncthreads();
-  for (int64_t b = tid; b < batch; b += blockDim.x) {
-    const int pos = atomicAdd(&start[key(b)], 1);
+  for (int64_t b = tid; b < batch; b += 1024) {
+    const int pos = atomicAdd(&start[bin(b)], 1);
     order[pos] = (int32_t)b;
   }
 }
@@ -616,9 +673,17 @@ hipError_t launch_resident(const FusedArgs &a, int nw, int grid, hipStream_t st)
   return hipGetLastError();
 }
 
-hipError_t launch_order(const int32_t *ns, int64_t batch, int cplx, int32_t *order,
-                        unsigned long long *queue, hipStream_t st) {
-  hipLaunchKernelGGL(expm_order_kernel, dim3(1), dim3(1024), 0, st, ns, batch, cplx, order, queue);
+hipError_t launch_order(const double *A, const int64_t *offs, const int32_t *ns, int n_uniform, int64_t batch,
+                        int cplx, uint8_t *key, int32_t *order, unsigned long long *queue, hipStream_t st) {
+  if (key) {
+    const int64_t g = (batch + 3) / 4;
+    hipLaunchKernelGGL(expm_cost_key_kernel, dim3((unsigned)(g < 2048 ? g : 2048)), dim3(256), 0, st, A, offs, ns,
+                       n_uniform, batch, cplx, key);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(expm_order_kernel, dim3(1), dim3(1024), 0, st, ns, n_uniform, (const uint8_t *)key, batch, cplx,
+                     order, queue);
   return hipGetLastError();
 }
 

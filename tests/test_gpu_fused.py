@@ -279,3 +279,43 @@ def test_sub_stages_match_full_call(P):
     assert torch.equal(outs[0], E0) and torch.equal(outs[1], m0) and torch.equal(outs[2], s0)
     with pytest.raises(RuntimeError):
         P.batched(B, workspace=ws, outs=outs, stage=6)
+
+
+def test_results_do_not_depend_on_the_queue_order(P, orc):
+    """The work queue orders each order class by a cost estimate from sampled rows; every matrix
+    is still evaluated from its own exact norm, so permuting the batch permutes the results bit
+    for bit.  The batch includes matrices the estimate misjudges (nonzero rows only outside the
+    sampled rows, so key 0 for an expensive matrix), a zero matrix, a non-finite matrix and
+    orders of every sweep."""
+    from paper_1710_10989_amd import workloads as W
+    from paper_1710_10989_amd.expm import Batch
+    mats, _ = W.mixed_batch(count=700, sizes=(16, 40, 64, 96, 112, 128, 200), seed_stream=31)
+    rng = np.random.default_rng(8)
+    for n in (128, 96, 64):
+        A = np.zeros((n, n))
+        A[0] = rng.standard_normal(n) * 30.0  # row 0 is never sampled: key 0, large s
+        mats.append(A)
+    mats.append(np.zeros((128, 128)))
+    bad = rng.standard_normal((96, 96))
+    bad[5, 7] = np.inf
+    mats.append(bad)
+    perm = rng.permutation(len(mats))
+    B1 = Batch.from_host(mats)
+    B2 = Batch.from_host([mats[i] for i in perm])
+    say("case queue order: %d matrices, permuted" % len(mats))
+    E1, m1, s1, st1 = P.batched(B1)
+    E2, m2, s2, st2 = P.batched(B2)
+    torch.cuda.synchronize()
+    L1, L2 = B1.unpack(E1), B2.unpack(E2)
+    m1, s1, st1 = m1.cpu().numpy(), s1.cpu().numpy(), st1.cpu().numpy()
+    m2, s2, st2 = m2.cpu().numpy(), s2.cpu().numpy(), st2.cpu().numpy()
+    for j, i in enumerate(perm):
+        assert (m1[i], s1[i], st1[i]) == (m2[j], s2[j], st2[j]), (i, j)
+        if st1[i] == 0:
+            assert np.array_equal(L1[i], L2[j]), (i, j)
+    assert int((st1 != 0).sum()) == 1
+    # the misjudged matrices are still evaluated with their own (m, s)
+    for k, A in enumerate(mats[-5:-2]):
+        b = len(mats) - 5 + k
+        assert (m1[b], s1[b]) == orc.select_plain(orc.norm1(A)), b
+        assert s1[b] >= 3
