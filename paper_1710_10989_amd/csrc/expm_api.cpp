@@ -348,11 +348,33 @@ static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, cons
     }
   } else {
     const int t = np_max_t(nr_uni);
-    const bool ok = t > kResT    ? go(K_FUSED8, f8, 0, 0, 0)
-                    : t > kRes6T  ? go(K_RES8, r8, 1, 0, 0)
-                    : t >= kSplitT ? go(K_RES6, r6, 2, 0, 0)
-                    : (t == 1 && (tiny || a.method)) ? go(K_TINY, tn, 5, 0, 0)
-                                   : go(K_RES4, r4, 3, 0, 0);
+    const Kern k = t > kResT ? K_FUSED8
+                   : t > kRes6T ? K_RES8
+                   : t >= kSplitT ? K_RES6
+                   : (t == 1 && (tiny || a.method)) ? K_TINY : K_RES4;
+    bool ok;
+    if (k != K_TINY && batch > grid_for(k, batch)) {
+      // more matrices than one round of the persistent grid: walk a queue ordered by the cost
+      // estimate (longest jobs first), the one order class's range of it
+      int32_t *order = (int32_t *)(base + L.order_off);
+      unsigned long long *queue = (unsigned long long *)(base + L.queue_off);
+      uint8_t *key = (uint8_t *)(base + L.key_off);
+      f8.order = r8.order = r6.order = r4.order = order;
+      f8.queue = r8.queue = r6.queue = r4.queue = queue;
+      if (launch_order(a.A, nullptr, nullptr, (int)n_uniform, batch, cplx, key, order, queue, st) != hipSuccess)
+        return EXPM_E_HIP;
+      ok = k == K_FUSED8 ? go(K_FUSED8, f8, 0, 0, 1)
+           : k == K_RES8 ? go(K_RES8, r8, 1, 1, 2)
+           : k == K_RES6 ? go(K_RES6, r6, 2, 2, 3)
+                         : go(K_RES4, r4, 3, 3, 5);
+    } else {
+      // one matrix per workgroup at most (or one wave per matrix): the static range
+      ok = k == K_FUSED8 ? go(K_FUSED8, f8, 0, 0, 0)
+           : k == K_RES8 ? go(K_RES8, r8, 1, 0, 0)
+           : k == K_RES6 ? go(K_RES6, r6, 2, 0, 0)
+           : k == K_TINY ? go(K_TINY, tn, 5, 0, 0)
+                         : go(K_RES4, r4, 3, 0, 0);
+    }
     if (!ok) return EXPM_E_HIP;
   }
   return EXPM_OK;

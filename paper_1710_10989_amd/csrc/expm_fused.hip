@@ -544,11 +544,12 @@ __global__ __launch_bounds__(256) void expm_cost_key_kernel(const double *A, con
   const int lane = threadIdx.x & 63;
   for (int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); b < batch; b += (int64_t)gridDim.x * 4) {
     const int nin = ns ? ns[b] : n_uniform;
+    const int64_t ob = offs ? offs[b] : 0;  // issued beside the order's load, not after it
     const int n = cplx ? 2 * nin : nin;
     double acc = 0.0;
     int rows = 0;
     if (nin >= 1 && n <= kNpMax) {
-      const int64_t off = (offs ? offs[b] : b * (int64_t)nin * nin) * (cplx ? 2 : 1);
+      const int64_t off = (offs ? ob : b * (int64_t)nin * nin) * (cplx ? 2 : 1);
       const int len = cplx ? 2 * nin : nin;  // doubles per input row; a complex row's |re| + |im|
                                              // is the row sum of its row of the real form
       rows = nin < 4 ? nin : 4;
@@ -579,7 +580,7 @@ __global__ __launch_bounds__(1024) void expm_order_kernel(const int32_t *ns, int
                                                           unsigned long long *queue) {
   constexpr int kCls = 18, kBins = kCls * kKeyBins;
   static_assert(kBins <= 2 * 1024, "two bins per thread in the scan");
-  __shared__ int hist[kBins], start[kBins], part[1024];
+  __shared__ int hist[kBins], start[kBins], part[16];
   const int tid = threadIdx.x;
   for (int i = tid; i < kBins; i += 1024) hist[i] = 0;
   __syncthreads();
@@ -590,21 +591,33 @@ __global__ __launch_bounds__(1024) void expm_order_kernel(const int32_t *ns, int
     const int k = key ? (int)key[b] : 0;
     return cls * kKeyBins + (kKeyBins - 1 - k);
   };
-  for (int64_t b = tid; b < batch; b += 1024) atomicAdd(&hist[bin(b)], 1);
+  // each thread's first kHeld bins stay in registers for the scatter below
+  constexpr int kHeld = 8;
+  int held[kHeld];
+#pragma unroll
+  for (int j = 0; j < kHeld; ++j) {
+    const int64_t b = tid + (int64_t)j * 1024;
+    held[j] = b < batch ? bin(b) : 0;
+  }
+#pragma unroll
+  for (int j = 0; j < kHeld; ++j)
+    if (tid + (int64_t)j * 1024 < batch) atomicAdd(&hist[held[j]], 1);
+  for (int64_t b = tid + (int64_t)kHeld * 1024; b < batch; b += 1024) atomicAdd(&hist[bin(b)], 1);
   __syncthreads();
-  // exclusive scan of the bins: thread t owns bins 2t and 2t + 1
+  // exclusive scan of the bins: thread t owns bins 2t and 2t + 1; inclusive scans within each
+  // wave, then each wave adds the totals of the waves before it
   const int b0 = 2 * tid, b1 = 2 * tid + 1;
   const int h0 = b0 < kBins ? hist[b0] : 0, h1 = b1 < kBins ? hist[b1] : 0;
+  const int lane = tid & 63, wv = tid >> 6;
   int v = h0 + h1;
-  part[tid] = v;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const int add = tid >= o ? part[tid - o] : 0;
-    __syncthreads();
-    v += add;
-    part[tid] = v;
-    __syncthreads();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u = __shfl_up(v, o);
+    if (lane >= o) v += u;
   }
+  if (lane == 63) part[wv] = v;
+  __syncthreads();
+  for (int k = 0; k < wv; ++k) v += part[k];
   if (b0 < kBins) start[b0] = v - h0 - h1;
   if (b1 < kBins) start[b1] = v - h1;
   __syncthreads();
@@ -618,10 +631,12 @@ __global__ __launch_bounds__(1024) void expm_order_kernel(const int32_t *ns, int
     queue[kQBound + 5] = (unsigned long long)batch;
   }
   __syncthreads();
-  for (int64_t b = tid; b < batch; b += 1024) {
-    const int pos = atomicAdd(&start[bin(b)], 1);
-    order[pos] = (int32_t)b;
+#pragma unroll
+  for (int j = 0; j < kHeld; ++j) {
+    const int64_t b = tid + (int64_t)j * 1024;
+    if (b < batch) order[atomicAdd(&start[held[j]], 1)] = (int32_t)b;
   }
+  for (int64_t b = tid + (int64_t)kHeld * 1024; b < batch; b += 1024) order[atomicAdd(&start[bin(b)], 1)] = (int32_t)b;
 }
 
 int fused_max_blocks_per_cu(int nw) {

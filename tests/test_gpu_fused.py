@@ -319,3 +319,26 @@ def test_results_do_not_depend_on_the_queue_order(P, orc):
         b = len(mats) - 5 + k
         assert (m1[b], s1[b]) == orc.select_plain(orc.norm1(A)), b
         assert s1[b] >= 3
+
+
+@pytest.mark.parametrize("n,count", [(128, 600), (40, 3000)])
+def test_uniform_batch_queue_order(P, orc, n, count):
+    """A uniform batch larger than one round of the persistent grid walks the cost-ordered
+    queue: results are those of the permuted batch, bit for bit, and match the oracle on a
+    sample (the most and least expensive matrices included)."""
+    rng = np.random.default_rng(n)
+    A = rng.standard_normal((count, n, n))
+    A *= (10.0 ** rng.uniform(-3, 2, size=count))[:, None, None] / np.abs(A).sum(1).max(1)[:, None, None]
+    perm = rng.permutation(count)
+    say("case uniform queue order n=%d count=%d" % (n, count))
+    E1, m1, s1, st1 = P.batched_uniform(dev(A))
+    E2, m2, s2, st2 = P.batched_uniform(dev(A[perm]))
+    torch.cuda.synchronize()
+    assert bool((st1 == 0).all()) and bool((st2 == 0).all())
+    p = torch.from_numpy(perm).cuda()
+    assert torch.equal(E1[p], E2) and torch.equal(m1[p], m2) and torch.equal(s1[p], s2)
+    m1, s1 = m1.cpu().numpy(), s1.cpu().numpy()
+    cost = np.array([{1: 0, 2: 1, 4: 2, 8: 3, 12: 4, 18: 5}[int(a)] + int(b) for a, b in zip(m1, s1)])
+    for i in list(np.argsort(cost)[:3]) + list(np.argsort(cost)[-3:]) + [0, count - 1]:
+        assert (m1[i], s1[i]) == orc.select_plain(orc.norm1(A[i])), i
+        check_one(orc, A[i], E1[i].cpu().numpy(), int(m1[i]), int(s1[i]))
