@@ -342,3 +342,33 @@ def test_uniform_batch_queue_order(P, orc, n, count):
     for i in list(np.argsort(cost)[:3]) + list(np.argsort(cost)[-3:]) + [0, count - 1]:
         assert (m1[i], s1[i]) == orc.select_plain(orc.norm1(A[i])), i
         check_one(orc, A[i], E1[i].cpu().numpy(), int(m1[i]), int(s1[i]))
+
+
+def test_large_ragged_batch_queue(P, orc):
+    """9000 matrices (more than the order kernel keeps in registers per thread, 8 x 1024):
+    every matrix is evaluated once, results equal those of the permuted batch bit for bit, and
+    a sample matches the oracle."""
+    from paper_1710_10989_amd.expm import Batch
+    rng = np.random.default_rng(9000)
+    ns = rng.choice([3, 8, 16, 24, 40], size=9000)
+    mats = []
+    for n in ns:
+        A = rng.standard_normal((n, n))
+        mats.append(A * (10.0 ** rng.uniform(-3, 1.5)) / np.abs(A).sum(0).max())
+    perm = rng.permutation(len(mats))
+    B1 = Batch.from_host(mats)
+    B2 = Batch.from_host([mats[i] for i in perm])
+    say("case large ragged batch: %d matrices" % len(mats))
+    E1, m1, s1, st1 = P.batched(B1)
+    E2, m2, s2, st2 = P.batched(B2)
+    torch.cuda.synchronize()
+    assert bool((st1 == 0).all()) and bool((st2 == 0).all())
+    p = torch.from_numpy(perm).cuda()
+    assert torch.equal(m1[p], m2) and torch.equal(s1[p], s2)
+    L1, L2 = B1.unpack(E1), B2.unpack(E2)
+    for j, i in enumerate(perm):
+        assert np.array_equal(L1[i], L2[j]), (i, j)
+    m1, s1 = m1.cpu().numpy(), s1.cpu().numpy()
+    for i in rng.choice(len(mats), size=24, replace=False):
+        assert (m1[i], s1[i]) == orc.select_plain(orc.norm1(mats[i])), i
+        check_one(orc, mats[i], L1[i], int(m1[i]), int(s1[i]))
