@@ -514,8 +514,12 @@ def run_copy(args, torch, P, W):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 50 for the sub-millisecond workloads batched, small and "
+                         "magnus, else 20)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps before them (default: 50 for batched, small and magnus, whose "
+                         "first few dozen calls run while the GPU's clocks are still rising; else 5)")
     ap.add_argument("--workload", default="batched", choices=["batched", "single", "precision", "complex", "learned",
                                                              "small", "magnus", "triangular", "copy"])
     ap.add_argument("--selector", default="plain", choices=["plain", "alpha"])
@@ -527,6 +531,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
+    fast = args.workload in ("batched", "small", "magnus")
+    if args.steps is None:
+        args.steps = 50 if fast else 20
+    if args.warmup is None:
+        args.warmup = 50 if fast else 5
     if args.gpus != 1:
         print("bench.py measures one GPU: the method runs on a single MI355X (multi-GPU sharding "
               "is a design note, not built); run with --gpus 1", file=sys.stderr)
