@@ -72,17 +72,23 @@ def _check_square(A):
         raise ValueError("A must be float64 or complex128")
 
 
-def taylor(A, u=None, prec="fp64", selector="plain", workspace=None, method="reduced"):
+def taylor(A, u=None, prec="fp64", selector="plain", workspace=None, method="reduced", out=None, outs=None):
     """e^A for one square device matrix.  Returns (E, m, s, status) with m, s, status as
-    one-element int32 device tensors."""
+    one-element int32 device tensors.  out: reuse E (shape and dtype of A); outs: reuse a
+    three-element int32 device tensor for (m, s, status) (callers that repeat the call)."""
     _check_square(A)
     A = A.contiguous()
     n = A.shape[0]
     o = _opts(A.dtype, prec, selector, u, method)
     ws = workspace if workspace is not None else _workspace(
         N.lib().expm_workspace_bytes(n, 1, ctypes.byref(o)), A.device)
-    E = torch.empty_like(A)
-    ms = torch.empty(3, dtype=torch.int32, device=A.device)
+    if out is not None and (out.shape != A.shape or out.dtype != A.dtype or not out.is_contiguous()
+                            or out.device != A.device):
+        raise ValueError("out must be a contiguous tensor of A's shape, dtype and device")
+    if outs is not None and (outs.dtype != torch.int32 or outs.numel() != 3 or outs.device != A.device):
+        raise ValueError("outs must be a three-element int32 tensor on A's device")
+    E = out if out is not None else torch.empty_like(A)
+    ms = outs if outs is not None else torch.empty(3, dtype=torch.int32, device=A.device)
     st = N.lib().expm_taylor(_ptr(A), _ptr(E), n, ctypes.byref(o), _ptr(ms[0:1]), _ptr(ms[1:2]),
                              _ptr(ms[2:3]), _ptr(ws), ws.numel(), _stream())
     N.check(st, "expm_taylor")

@@ -372,3 +372,27 @@ def test_large_ragged_batch_queue(P, orc):
     for i in rng.choice(len(mats), size=24, replace=False):
         assert (m1[i], s1[i]) == orc.select_plain(orc.norm1(mats[i])), i
         check_one(orc, mats[i], L1[i], int(m1[i]), int(s1[i]))
+
+
+def test_taylor_reused_outputs(P):
+    """expm_taylor into caller-owned buffers (out, outs): two calls in a row on different
+    matrices give exactly the results of fresh calls; mismatched buffers are refused."""
+    rng = np.random.default_rng(64)
+    A1, A2 = rng.standard_normal((64, 64)), rng.standard_normal((48, 48)) * 0.01
+    out, outs = torch.empty((64, 64), dtype=torch.float64, device="cuda"), torch.empty(3, dtype=torch.int32,
+                                                                                        device="cuda")
+    say("case taylor reused outputs")
+    E1, m1, s1, st1 = P.taylor(dev(A1), out=out, outs=outs)
+    R1 = P.taylor(dev(A1))
+    torch.cuda.synchronize()
+    assert E1.data_ptr() == out.data_ptr() and torch.equal(E1, R1[0])
+    assert (int(m1.item()), int(s1.item()), int(st1.item())) == (int(R1[1].item()), int(R1[2].item()), 0)
+    out2 = torch.empty((48, 48), dtype=torch.float64, device="cuda")
+    E2, m2, s2, _ = P.taylor(dev(A2), out=out2, outs=outs)
+    R2 = P.taylor(dev(A2))
+    torch.cuda.synchronize()
+    assert torch.equal(E2, R2[0]) and int(m2.item()) == int(R2[1].item()) and int(s2.item()) == int(R2[2].item())
+    with pytest.raises(ValueError):
+        P.taylor(dev(A2), out=out)  # wrong shape
+    with pytest.raises(ValueError):
+        P.taylor(dev(A2), outs=torch.empty(2, dtype=torch.int32, device="cuda"))
