@@ -157,3 +157,29 @@ def test_full_size_n8192_householder(P):
     err = np.abs(X - R).sum(0).max() / np.abs(R).sum(0).max()
     say("n=8192 rel err", err)
     assert err <= TOL
+
+
+def test_complex_batch_queue_order(P, orc):
+    """320 complex matrices of order 64 (real form 128, more than one round of the 8-wave
+    sweep): the cost keys come from complex rows (|re| + |im|); results equal those of the
+    permuted batch bit for bit, and a sample matches the oracle."""
+    g = np.random.default_rng(320)
+    ts = 10.0 ** g.uniform(-2, 1.5, size=320)
+    mats = [_hermitian(g, 64, t) for t in ts]
+    perm = g.permutation(len(mats))
+    from paper_1710_10989_amd.expm import Batch
+    B1 = Batch.from_host(mats, dtype=torch.complex128)
+    B2 = Batch.from_host([mats[i] for i in perm], dtype=torch.complex128)
+    say("case complex batch queue order")
+    E1, m1, s1, st1 = P.batched(B1)
+    E2, m2, s2, st2 = P.batched(B2)
+    torch.cuda.synchronize()
+    assert bool((st1 == 0).all()) and bool((st2 == 0).all())
+    p = torch.from_numpy(perm).cuda()
+    assert torch.equal(m1[p], m2) and torch.equal(s1[p], s2)
+    L1, L2 = B1.unpack(E1), B2.unpack(E2)
+    for j, i in enumerate(perm):
+        assert np.array_equal(L1[i], L2[j]), (i, j)
+    for i in (int(np.argmin(ts)), int(np.argmax(ts)), 0, 319):
+        ref, _ = orc.expm_taylor(mats[i])
+        assert orc.rel_err_1(L1[i], ref) <= TOL, i
