@@ -190,9 +190,12 @@ EXPM_API expm_status_t expm_batched_stage(const void *A_dev, void *E_dev, const 
                                  int32_t stage);
 
 /* e^A for `batch` matrices of the same order n stored back to back (matrix b at element
- * b * n^2).  Any order: real order <= 256 (complex <= 128) runs on the fused kernels with
- * static assignment (graph-capturable); larger orders run the tiled path in groups of matrices
- * (about 2048 output tiles per launch), synchronising once per group to read (m, s) back. */
+ * b * n^2).  Any order: real order <= 256 (complex <= 128) runs on the fused kernels, without
+ * host synchronisation (graph-capturable): a batch larger than one round of the persistent
+ * grid walks a device work queue sorted by the cost estimate of expm_batched (largest
+ * first), smaller batches and real order <= 16 (one wave per matrix) take a static
+ * assignment; larger orders run the tiled path in groups of matrices (about 2048 output tiles
+ * per launch), synchronising once per group to read (m, s) back. */
 EXPM_API expm_status_t expm_batched_uniform(const void *A_dev, void *E_dev, int64_t n, int64_t batch,
                                    const expm_opts_t *opts, int32_t *m_dev, int32_t *s_dev,
                                    int32_t *status_dev, void *ws_dev, size_t ws_bytes, void *stream);
