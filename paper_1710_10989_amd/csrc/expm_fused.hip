@@ -4,8 +4,9 @@
 // cost estimate first) and runs the whole method for it: copy A into a zero-padded np x np
 // buffer (np = n rounded up to 16) while taking the 1-norm, choose (m, s), form the powers
 // A^2, A^3 with MFMA GEMMs, build the linear combinations of the product-reduced sequence in
-// GEMM epilogues, run the product stage and the s squarings, and write e^A.  Zero padding is exact: every polynomial
-// in the padded matrix is block diagonal, so the leading n x n block is p(A).
+// GEMM epilogues, run the product stage and the s squarings, and write e^A.  Zero padding is
+// exact: every polynomial in the padded matrix is block diagonal, so the leading n x n block
+// is p(A).
 //
 // Scaling (Sec. 1, eq. eses) is folded into the coefficients: X^k = 2^(-sk) A^k, so the
 // stored powers are those of A and no pass rescales a matrix.
@@ -587,7 +588,8 @@ __global__ __launch_bounds__(1024) void expm_order_kernel(const int32_t *ns, int
   auto bin = [&](int64_t b) {
     const int nin = ns ? ns[b] : n_uniform;
     const int n = cplx ? 2 * nin : nin;  // order of the real matrix the method runs on
-    const int cls = (nin < 1 || n > kNpMax) ? 17 : 16 - ((n + 15) >> 4);  // 0 for np = 256 ... 15 for np = 16
+    // class 0 for np = 256 ... 15 for np = 16; 17 for an invalid order
+    const int cls = (nin < 1 || n > kNpMax) ? 17 : 16 - ((n + 15) >> 4);
     const int k = key ? (int)key[b] : 0;
     return cls * kKeyBins + (kKeyBins - 1 - k);
   };
@@ -636,7 +638,8 @@ __global__ __launch_bounds__(1024) void expm_order_kernel(const int32_t *ns, int
     const int64_t b = tid + (int64_t)j * 1024;
     if (b < batch) order[atomicAdd(&start[held[j]], 1)] = (int32_t)b;
   }
-  for (int64_t b = tid + (int64_t)kHeld * 1024; b < batch; b += 1024) order[atomicAdd(&start[bin(b)], 1)] = (int32_t)b;
+  for (int64_t b = tid + (int64_t)kHeld * 1024; b < batch; b += 1024)
+    order[atomicAdd(&start[bin(b)], 1)] = (int32_t)b;
 }
 
 int fused_max_blocks_per_cu(int nw) {
