@@ -112,7 +112,7 @@ def test_nonfinite_input(P):
 
 
 @pytest.mark.parametrize("kind", ["dense", "skew", "nilpotent", "diag_lowrank"])
-def test_alpha_selector(P, orc, kind):
+def test_alpha_selector(P, orc, alpha_ref, kind):
     from paper_1710_10989_amd import workloads as W
     g = np.random.default_rng(55)
     for norm in (0.02, 0.5, 3.0, 40.0):
@@ -121,11 +121,7 @@ def test_alpha_selector(P, orc, kind):
         E, m, s, st = P.taylor(dev(A), selector="alpha")
         torch.cuda.synchronize()
         m, s = int(m.item()), int(s.item())
-        nk = orc.powers_norms(A, 3)
-        mp, sp = orc.select_plain(nk[0])
-        n2 = nk[1] if mp >= 2 else -1.0
-        n3 = nk[2] if mp >= 12 else -1.0
-        assert (m, s) == P.select_rule([nk[0], n2, n3], "alpha")
+        assert (m, s) == alpha_ref(orc.powers_norms(A, 3))
         check_one(orc, A, E.cpu().numpy(), m, s)
 
 

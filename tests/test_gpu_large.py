@@ -67,7 +67,7 @@ def test_large_batch_every_degree(P, orc):
 
 
 @pytest.mark.parametrize("kind", ["dense", "nilpotent"])
-def test_large_alpha(P, orc, kind):
+def test_large_alpha(P, orc, alpha_ref, kind):
     from paper_1710_10989_amd import workloads as W
     g = np.random.default_rng(77)
     n = 320
@@ -76,9 +76,7 @@ def test_large_alpha(P, orc, kind):
     E, m, s, st = P.taylor(dev(A), selector="alpha")
     torch.cuda.synchronize()
     m, s = int(m.item()), int(s.item())
-    nk = orc.powers_norms(A, 3)
-    mp, _ = orc.select_plain(nk[0])
-    assert (m, s) == P.select_rule([nk[0], nk[1] if mp >= 2 else -1, nk[2] if mp >= 12 else -1], "alpha")
+    assert (m, s) == alpha_ref(orc.powers_norms(A, 3))
     ref, _ = orc.expm_taylor(A, prec="d")
     assert orc.rel_err_1(E.cpu().numpy(), ref) <= TOL
 

@@ -92,7 +92,7 @@ def test_ragged_small_orders_in_a_batch(P, orc):
 
 
 @pytest.mark.parametrize("kind", ["dense", "skew", "nilpotent", "diag_lowrank"])
-def test_alpha_small(P, orc, kind):
+def test_alpha_small(P, orc, alpha_ref, kind):
     from paper_1710_10989_amd import workloads as W
     g = np.random.default_rng(57)
     for n in (5, 12, 16):
@@ -102,11 +102,7 @@ def test_alpha_small(P, orc, kind):
             E, m, s, st = P.taylor(dev(A), selector="alpha")
             torch.cuda.synchronize()
             m, s = int(m.item()), int(s.item())
-            nk = orc.powers_norms(A, 3)
-            mp, _ = orc.select_plain(nk[0])
-            n2 = nk[1] if mp >= 2 else -1.0
-            n3 = nk[2] if mp >= 12 else -1.0
-            assert (m, s) == P.select_rule([nk[0], n2, n3], "alpha")
+            assert (m, s) == alpha_ref(orc.powers_norms(A, 3))
             check_e(orc, A, E.cpu().numpy(), m, s)
 
 
@@ -180,7 +176,7 @@ def test_magnus_step_vs_oracle(P, orc, n):
     _check_magnus(orc, S0, S1, Y0, u1, u2, h, Yg.cpu().numpy(), m.cpu().numpy(), s.cpu().numpy())
 
 
-def test_magnus_shared_generators_in_place_alpha(P, orc):
+def test_magnus_shared_generators_in_place_alpha(P, orc, alpha_ref):
     h = 0.3
     S0, S1, Y0, u1, u2, _ = _magnus_inputs(70, 11, h, seed_stream=4)
     Yd = dev(Y0)
@@ -194,8 +190,7 @@ def test_magnus_shared_generators_in_place_alpha(P, orc):
         want, Om = orc.magnus4_step(S0[0], S1[0], Y0[b], u1[b], u2[b], h)
         assert orc.rel_err_1(Yg[b], want) <= TOL, b
         nk = orc.powers_norms(Om, 3)
-        mp, _ = orc.select_plain(nk[0])
-        ma, sa = P.select_rule([nk[0], nk[1] if mp >= 2 else -1.0, nk[2] if mp >= 12 else -1.0], "alpha")
+        ma, sa = alpha_ref(nk)
         if (int(m[b].item()), int(s[b].item())) != (ma, sa):
             assert near_threshold(orc, nk[0]) or near_threshold(orc, nk[1] ** 0.5), b
 
