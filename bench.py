@@ -82,10 +82,31 @@ def executed_flops(ms, ss, ns, prods=PRODUCTS):
     return float(sum((prods[int(m)] + int(s)) * 2.0 * float(n) ** 3 for m, s, n in zip(ms, ss, ns) if m > 0))
 
 
-def cpu_oracle(mats, seconds, label):
-    """Whole passes of the FP64 direct-Taylor oracle over `mats` until about `seconds`."""
+def host_cpu():
+    """(threads the oracle may use, nproc, CPU model): the cores this process may run on,
+    capped at 16 (the host share of one GPU)."""
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return min(nproc, 16), nproc, model
+
+
+def cpu_oracle(mats, seconds, label, single_seconds=3.0):
+    """Whole passes of the FP64 direct-Taylor oracle over `mats` until about `seconds`, on an
+    explicitly set number of OpenMP threads; then the single-thread rate on a sub-sample."""
     import oracle
-    threads = min(os.cpu_count() or 1, 16)
+    want, nproc, model = host_cpu()
+    threads = oracle.set_threads(want)
     oracle.expm_taylor_batch(mats[:1], prec="d")
     done, c0 = 0, time.perf_counter()
     while True:
@@ -94,15 +115,29 @@ def cpu_oracle(mats, seconds, label):
         if time.perf_counter() - c0 >= seconds:
             break
     c1 = time.perf_counter()
+    # one thread: passes over every 16th matrix (the same mix of orders) for about single_seconds
+    sub = mats[::16] if len(mats) >= 64 else mats
+    oracle.set_threads(1)
+    d1, s0 = 0, time.perf_counter()
+    while True:
+        oracle.expm_taylor_batch(sub, prec="d")
+        d1 += 1
+        if time.perf_counter() - s0 >= single_seconds:
+            break
+    s1 = time.perf_counter()
+    oracle.set_threads(want)
     return {"value": done * len(mats) / (c1 - c0), "unit": "matrices/s", "cores": threads, "kind": "oracle",
+            "nproc": nproc, "cpu_model": model,
+            "single_core": {"value": d1 * len(sub) / (s1 - s0), "unit": "matrices/s",
+                            "sample": "%d pass(es) over %d matrices (every 16th), %.1f s" % (d1, len(sub), s1 - s0)},
             "sample": "%d pass(es) over %s, FP64 direct Taylor (own scaling ||X||_1 <= 1/2), OpenMP over "
-                      "matrices, %.1f s" % (done, label, c1 - c0)}
+                      "matrices on %d threads, %.1f s" % (done, label, threads, c1 - c0)}
 
 
-def line(args, metric, value, ms_step, dtype, config, roofline, cpu, unit="matrices/s"):
+def line(args, metric, value, ms_step, dtype, config, roofline, cpu, unit="matrices/s", vs_baseline=None):
     return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config, "roofline": roofline,
+            "vs_baseline": vs_baseline, "dtype": dtype, "data": "synthetic", "config": config, "roofline": roofline,
             "cpu_baseline": cpu}
 
 
@@ -146,6 +181,7 @@ def run_batched(args, torch, P, W):
     ms_k8 = sum(a.elapsed_time(b) for a, b in kev) / args.steps
     _, m, s, st = (x.cpu().numpy() for x in outs)
     assert np.all(st == 0), "non-ok status in the batch"
+    plain = plain_per_matrix(torch, P, B, mats, outs[0], m, s, args.plain_passes)
     ns = np.array([a.shape[0] for a in mats], dtype=np.float64)
     big = ((ns + 15) // 16) >= 7  # real orders handled by the 8-wave resident kernel (112..128)
     flops = executed_flops(m, s, ns)
@@ -162,8 +198,66 @@ def run_batched(args, torch, P, W):
             "kernel_timing": "HIP events around the kernel's phase, run alone (expm_batched_stage 1), "
                              "%d steps right after the timed region" % args.steps,
             "step_tflops": flops / (ms_step * 1e-3) / 1e12}
-    return line(args, "expm matrices/s (rel err <= 1e-12, FP64)", nb / (ms_step * 1e-3), ms_step, "f64", config,
-                roof, cpu)
+    config["plain_fp64_form"] = plain
+    value = nb / (ms_step * 1e-3)
+    return line(args, "expm matrices/s (rel err <= 1e-12, FP64)", value, ms_step, "f64", config,
+                roof, cpu, vs_baseline=value / plain["value"])
+
+
+def plain_per_matrix(torch, P, B, mats, E_batched, m_b, s_b, passes):
+    """The method's plain FP64 form on the same workload: one expm_taylor call (one launch) per
+    matrix, norm-based (m, s), matrices in the workload's order on one stream.  Checks that
+    every (m, s) equals the batched call's and that the results agree to 1e-12."""
+    from paper_1710_10989_amd import _native as N
+    import ctypes
+    L = N.lib()
+    nb = len(mats)
+    o = N.ExpmOpts(N.EXPM_F64, N.EXPM_PREC_FP64, N.EXPM_SEL_PLAIN, 0, 0.0)
+    nmax = max(a.shape[0] for a in mats)
+    ws = torch.empty(L.expm_workspace_bytes(nmax, 1, ctypes.byref(o)), dtype=torch.uint8, device="cuda")
+    E = torch.empty_like(B.packed)
+    ms = torch.empty((nb, 3), dtype=torch.int32, device="cuda")
+    offs = B.offsets.cpu().numpy()
+    a0, e0, m0 = B.packed.data_ptr(), E.data_ptr(), ms.data_ptr()
+    calls = [(ctypes.c_void_p(a0 + 8 * int(offs[b])), ctypes.c_void_p(e0 + 8 * int(offs[b])), mats[b].shape[0],
+              ctypes.c_void_p(m0 + 12 * b), ctypes.c_void_p(m0 + 12 * b + 4), ctypes.c_void_p(m0 + 12 * b + 8))
+             for b in range(nb)]
+    wsp, wsn, op = ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.byref(o)
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    fn = L.expm_taylor
+
+    def one_pass():
+        for a, e, n, pm, ps, pst in calls:
+            if fn(a, e, n, op, pm, ps, pst, wsp, wsn, stream) != 0:
+                raise RuntimeError("expm_taylor failed")
+
+    one_pass()
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    h0 = time.perf_counter()
+    t0.record()
+    for _ in range(passes):
+        one_pass()
+    t1.record()
+    h1 = time.perf_counter()
+    torch.cuda.synchronize()
+    ms_pass = t0.elapsed_time(t1) / passes
+    msh = ms.cpu().numpy()
+    assert np.all(msh[:, 2] == 0)
+    assert np.array_equal(msh[:, 0], m_b) and np.array_equal(msh[:, 1], s_b)
+    diff = (E - E_batched).abs()
+    dev = 0.0
+    for b in range(0, nb, 97):  # sampled matrices: relative 1-norm difference of the two forms
+        n, o_ = mats[b].shape[0], int(offs[b])
+        Xb = E[o_:o_ + n * n].view(n, n)
+        Db = diff[o_:o_ + n * n].view(n, n)
+        dev = max(dev, float(Db.sum(0).max() / Xb.abs().sum(0).max()))
+    assert dev <= 1e-12, dev
+    return {"value": nb / (ms_pass * 1e-3), "unit": "matrices/s", "ms_per_pass": ms_pass,
+            "host_ms_per_pass": (h1 - h0) * 1e3 / passes, "passes": passes,
+            "form": "plain FP64: one expm_taylor call (one kernel launch) per matrix, norm-based (m, s), "
+                    "one stream, after one untimed pass",
+            "max_rel_diff_vs_batched_sampled": dev}
 
 
 def run_single(args, torch, P, W):
@@ -532,6 +626,8 @@ def main():
     ap.add_argument("--count", type=int, default=4096)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--plain-passes", type=int, default=3,
+                    help="timed passes of the plain one-launch-per-matrix form (batched workload)")
     args = ap.parse_args()
     fast = args.workload in ("batched", "small", "magnus")
     if args.steps is None:

@@ -22,7 +22,7 @@ def build(force=False):
     """Compile ``liboracle.so`` with gcc (no FMA contraction, OpenMP over batches)."""
     if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
         tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-ffp-contract=off", "-fopenmp",
+        subprocess.check_call(["gcc", "-O3", "-fPIC", "-shared", "-ffp-contract=off", "-fopenmp",
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -48,6 +48,8 @@ def lib():
         L.or_select_alpha.argtypes = [vp, vp, ip, ip]; L.or_select_alpha.restype = None
         L.or_powers_norms.argtypes = [i64, vp, i32, vp]; L.or_powers_norms.restype = None
         L.or_select_alpha_split.argtypes = [vp, vp, vp, ip, ip]; L.or_select_alpha_split.restype = None
+        L.or_set_threads.argtypes = [i32]; L.or_set_threads.restype = None
+        L.or_get_threads.argtypes = []; L.or_get_threads.restype = i32
         _lib = L
     return _lib
 
@@ -93,6 +95,12 @@ def expm_taylor(A, prec="ld"):
     if rc < 0:
         raise ValueError("non-finite input")
     return E, s.value
+
+
+def set_threads(t):
+    """OpenMP threads of the batch routines; returns the count a parallel region then uses."""
+    lib().or_set_threads(int(t))
+    return lib().or_get_threads()
 
 
 def expm_taylor_batch(mats, prec="d"):

@@ -7,8 +7,8 @@
  * with the GPU library: every constant below is transcribed here from the paper, and
  * every routine is a plain loop nest written for readability, not speed.
  *
- * Build: gcc -O2 -fPIC -shared -ffp-contract=off -fopenmp (no FMA contraction, so the
- * rounding of each operation is the textbook one).
+ * Build: gcc -O3 -fPIC -shared -ffp-contract=off -fopenmp (no FMA contraction and no
+ * reassociation, so the rounding of each operation is the textbook one).
  *
  * Matrices are n x n, row-major, contiguous (a[i*n + j]).  Complex matrices are
  * interleaved (re, im) pairs.  "ld" routines compute in 80-bit x87 long double, "d"
@@ -232,6 +232,12 @@ int or_expm_taylor_z(int64_t n, const double *Az, double *Ez, int *s_out) {
 }
 
 /* Batched direct Taylor in double or long double, one OpenMP task per matrix. */
+/* Threads of the batch routines (OpenMP over matrices): set, and the number a parallel region
+ * then runs with. */
+#include <omp.h>
+void or_set_threads(int t) { omp_set_num_threads(t > 0 ? t : 1); }
+int or_get_threads(void) { return omp_get_max_threads(); }
+
 int or_expm_taylor_batch(int64_t count, const int64_t *ns, const int64_t *offsets, const double *A,
                          double *E, int prec, int *s_out) {
   int bad = 0;

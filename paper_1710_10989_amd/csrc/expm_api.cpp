@@ -298,7 +298,7 @@ static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, cons
     f8.queue = f4.queue = r8.queue = r6.queue = r4.queue = tn.queue = queue;
     uint8_t *key = (uint8_t *)(base + L.key_off);
     if ((stage == -1 || stage == 0) &&
-        launch_order(a.A, offs, ns, (int)n_uniform, batch, cplx, key, order, queue, st) != hipSuccess)
+        launch_order(a.A, offs, ns, (int)n_uniform, a.np_max, batch, cplx, key, order, queue, st) != hipSuccess)
       return EXPM_E_HIP;
     if (features) {
       // global-memory kernels: np >= 80 on 8 waves, the rest on 4 waves
@@ -361,7 +361,7 @@ static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, cons
       uint8_t *key = (uint8_t *)(base + L.key_off);
       f8.order = r8.order = r6.order = r4.order = order;
       f8.queue = r8.queue = r6.queue = r4.queue = queue;
-      if (launch_order(a.A, nullptr, nullptr, (int)n_uniform, batch, cplx, key, order, queue, st) != hipSuccess)
+      if (launch_order(a.A, nullptr, nullptr, (int)n_uniform, a.np_max, batch, cplx, key, order, queue, st) != hipSuccess)
         return EXPM_E_HIP;
       ok = k == K_FUSED8 ? go(K_FUSED8, f8, 0, 0, 1)
            : k == K_RES8 ? go(K_RES8, r8, 1, 1, 2)

@@ -80,7 +80,9 @@ hipError_t launch_magnus4(const double *S0, const double *S1, int64_t s_stride, 
 hipError_t launch_resident(const FusedArgs &a, int nw, int grid, hipStream_t st);  // nw = 8, 12, 4
 // Work-queue order of a batch: cost keys of every matrix (into key, batch bytes; skipped when
 // key is null), then the counting sort by (real order, key) into order and the queue words.
-hipError_t launch_order(const double *A, const int64_t *offs, const int32_t *ns, int n_uniform, int64_t batch,
-                        int cplx, uint8_t *key, int32_t *order, unsigned long long *queue, hipStream_t st);
+// Orders above np_max (the call's largest padded real order) are classed invalid.
+hipError_t launch_order(const double *A, const int64_t *offs, const int32_t *ns, int n_uniform, int np_max,
+                        int64_t batch, int cplx, uint8_t *key, int32_t *order, unsigned long long *queue,
+                        hipStream_t st);
 
 }  // namespace expm

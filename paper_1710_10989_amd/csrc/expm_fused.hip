@@ -576,9 +576,9 @@ __global__ __launch_bounds__(256) void expm_cost_key_kernel(const double *A, con
 // and within an order by cost key, largest first (the longest jobs are claimed first, so a
 // sweep does not end on a few expensive matrices claimed late); resets the counters and
 // records the range bounds.  One workgroup of 1024 threads; key may be null (all keys 0).
-__global__ __launch_bounds__(1024) void expm_order_kernel(const int32_t *ns, int n_uniform, const uint8_t *key,
-                                                          int64_t batch, int cplx, int32_t *order,
-                                                          unsigned long long *queue) {
+__global__ __launch_bounds__(1024) void expm_order_kernel(const int32_t *ns, int n_uniform, int np_max,
+                                                          const uint8_t *key, int64_t batch, int cplx,
+                                                          int32_t *order, unsigned long long *queue) {
   constexpr int kCls = 18, kBins = kCls * kKeyBins;
   static_assert(kBins <= 2 * 1024, "two bins per thread in the scan");
   __shared__ int hist[kBins], start[kBins], part[16];
@@ -588,8 +588,10 @@ __global__ __launch_bounds__(1024) void expm_order_kernel(const int32_t *ns, int
   auto bin = [&](int64_t b) {
     const int nin = ns ? ns[b] : n_uniform;
     const int n = cplx ? 2 * nin : nin;  // order of the real matrix the method runs on
-    // class 0 for np = 256 ... 15 for np = 16; 17 for an invalid order
-    const int cls = (nin < 1 || n > kNpMax) ? 17 : 16 - ((n + 15) >> 4);
+    // class 0 for np = 256 ... 15 for np = 16; 17 for an invalid order (also one above the
+    // call's n_max, which no sweep of the call would otherwise reach): drained with np = 16,
+    // whose kernels report it
+    const int cls = (nin < 1 || n > np_max) ? 17 : 16 - ((n + 15) >> 4);
     const int k = key ? (int)key[b] : 0;
     return cls * kKeyBins + (kKeyBins - 1 - k);
   };
@@ -691,8 +693,9 @@ hipError_t launch_resident(const FusedArgs &a, int nw, int grid, hipStream_t st)
   return hipGetLastError();
 }
 
-hipError_t launch_order(const double *A, const int64_t *offs, const int32_t *ns, int n_uniform, int64_t batch,
-                        int cplx, uint8_t *key, int32_t *order, unsigned long long *queue, hipStream_t st) {
+hipError_t launch_order(const double *A, const int64_t *offs, const int32_t *ns, int n_uniform, int np_max,
+                        int64_t batch, int cplx, uint8_t *key, int32_t *order, unsigned long long *queue,
+                        hipStream_t st) {
   if (key) {
     const int64_t g = (batch + 3) / 4;
     hipLaunchKernelGGL(expm_cost_key_kernel, dim3((unsigned)(g < 2048 ? g : 2048)), dim3(256), 0, st, A, offs, ns,
@@ -700,8 +703,8 @@ hipError_t launch_order(const double *A, const int64_t *offs, const int32_t *ns,
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(expm_order_kernel, dim3(1), dim3(1024), 0, st, ns, n_uniform, (const uint8_t *)key, batch, cplx,
-                     order, queue);
+  hipLaunchKernelGGL(expm_order_kernel, dim3(1), dim3(1024), 0, st, ns, n_uniform, np_max < kNpMax ? np_max : kNpMax,
+                     (const uint8_t *)key, batch, cplx, order, queue);
   return hipGetLastError();
 }
 

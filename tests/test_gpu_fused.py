@@ -170,6 +170,30 @@ def test_batched_mixed_vs_oracle(P, orc):
     say("batched worst rel err", worst)
 
 
+def test_batched_order_above_n_max_is_reported(P, orc):
+    # a matrix whose order exceeds the call's n_max gets EXPM_E_INVALID_ARG and (-1, -1); the
+    # others are unaffected (the workspace is sized for n_max only)
+    from paper_1710_10989_amd.expm import Batch
+    g = np.random.default_rng(31)
+    sizes = [16, 64, 128, 48, 33, 96, 17]
+    mats = [g.standard_normal((n, n)) / n for n in sizes]
+    full = Batch.from_host(mats)
+    for n_max in (64, 96):
+        B = Batch(full.packed, full.offsets, full.ns, n_max)
+        say("case batched n_max", n_max)
+        E, m, s, st = P.batched(B)
+        torch.cuda.synchronize()
+        outs = B.unpack(E)
+        m, s, st = m.cpu().numpy(), s.cpu().numpy(), st.cpu().numpy()
+        for i, A in enumerate(mats):
+            if A.shape[0] > n_max:
+                assert (st[i], m[i], s[i]) == (1, -1, -1), (n_max, i)
+            else:
+                assert st[i] == 0 and (m[i], s[i]) == orc.select_plain(orc.norm1(A)), (n_max, i)
+                R, _ = orc.expm_taylor(A)
+                assert orc.rel_err_1(outs[i], R) <= TOL, (n_max, i)
+
+
 def test_batched_full_size_sampled(P, orc):
     # the whole 4096-matrix workload in the launch configuration the benchmark times
     mats, kinds = _batch(4096, 0)

@@ -142,6 +142,12 @@ def test_trained_selector_gain(L, orc):
     say("mean products+squarings", cost, "accepted", acc, "rejected", rej)
     assert cost["learned"] < cost["plain"]
     assert acc > rej
+    # the learned rule gains over the plain one but never over the alpha rule: an accepted
+    # proposal passes the alpha bound with no more information than the alpha rule has, and
+    # the alpha rule takes the cheapest choice that passes it; a rejection runs the plain rule
+    per = {k: np.array([COST[a] + b for a, b in zip(v[1], v[2])]) for k, v in res.items()}
+    assert np.all(per["learned"] >= per["alpha"])
+    say("learned - alpha mean products+squarings", float(np.mean(per["learned"] - per["alpha"])))
     outs = B.unpack(res["learned"][0])
     sample = np.random.default_rng(1).choice(len(mats), 40, replace=False)
     refs, _ = orc.expm_taylor_batch([mats[i] for i in sample], prec="ld")
