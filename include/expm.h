@@ -14,7 +14,8 @@
  *    (EXPM_C128) are interleaved (re, im) pairs of doubles.
  *  - Pointers named *_dev are device (HBM) pointers; the caller owns every buffer.  The
  *    library allocates no device memory: scratch space is the caller's workspace, sized by
- *    expm_workspace_bytes().  The output must not alias the input.
+ *    expm_workspace_bytes() (expm_batched_noalloc uses a fixed device array of the library
+ *    instead).  The output must not alias the input.
  *  - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue work and return;
  *    results, (m, s) and per-matrix status are written to device memory, so nothing is known
  *    on the host until the caller synchronises.  Exception: see expm_taylor for n > 256.
@@ -171,6 +172,24 @@ EXPM_API expm_status_t expm_batched(const void *A_dev, void *E_dev, const int64_
                            const int32_t *n_dev, int64_t batch, int64_t n_max,
                            const expm_opts_t *opts, int32_t *m_dev, int32_t *s_dev,
                            int32_t *status_dev, void *ws_dev, size_t ws_bytes, void *stream);
+
+/* expm_batched for callers that cannot allocate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): no workspace argument; the scratch the call needs
+ * (work-queue words, the sorted order, cost keys, the 8-wave on-chip kernel's parked matrices)
+ * lives in a device array of the library, 64.3 MiB, which every device the library runs on
+ * holds until the process ends.  The call allocates nothing (no hipMalloc, no stream or event
+ * creation) and runs every sweep on `stream` in turn (expm_batched runs some of them on a
+ * second stream beside it).  Results, (m, s) and status are exactly those of expm_batched.
+ * Limits: real order n_max <= 128 (complex n_max <= 64) and batch <= 65536, else
+ * EXPM_E_WORKSPACE (the scratch is too small); reduced precision, comparison methods:
+ * EXPM_E_UNSUPPORTED; other arguments as expm_batched.  All calls on one device share its
+ * array, which keeps the last call's contents (every call rewrites what it reads): calls that
+ * overlap on one device (concurrent streams or host threads) race and must be serialised by
+ * the caller. */
+EXPM_API expm_status_t expm_batched_noalloc(const void *A_dev, void *E_dev, const int64_t *offsets_dev,
+                                           const int32_t *n_dev, int64_t batch, int64_t n_max,
+                                           const expm_opts_t *opts, int32_t *m_dev, int32_t *s_dev,
+                                           int32_t *status_dev, void *stream);
 
 /* expm_batched in phases, for callers that time or overlap them: stage 0 sorts the batch into
  * the device work queue (largest real order first, then largest cost estimate); stage 1 runs the 8-wave on-chip kernel

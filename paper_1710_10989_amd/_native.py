@@ -17,7 +17,7 @@ EXPM_SEL_PLAIN, EXPM_SEL_ALPHA, EXPM_SEL_LEARNED = 0, 1, 2
 EXPM_FLAG_PS, EXPM_FLAG_PADE, EXPM_FLAG_TRI = 1, 2, 4
 
 EXPORTED = ("expm_status_string", "expm_theta", "expm_select_rule", "expm_workspace_bytes",
-            "expm_select", "expm_taylor", "expm_batched", "expm_batched_stage", "expm_batched_uniform",
+            "expm_select", "expm_taylor", "expm_batched", "expm_batched_noalloc", "expm_batched_stage", "expm_batched_uniform",
             "expm_magnus4_step", "expm_features", "expm_mlp_scratch_bytes", "expm_mlp_param_count", "expm_mlp_forward",
             "expm_mlp_grad", "expm_mlp_adam", "expm_learned_set", "expm_learned_counts")
 
@@ -54,6 +54,8 @@ def lib():
         L.expm_taylor.argtypes = [vp, vp, i64, op, vp, vp, vp, vp, sz, vp]; L.expm_taylor.restype = i32
         L.expm_batched.argtypes = [vp, vp, vp, vp, i64, i64, op, vp, vp, vp, vp, sz, vp]
         L.expm_batched.restype = i32
+        L.expm_batched_noalloc.argtypes = [vp, vp, vp, vp, i64, i64, op, vp, vp, vp, vp]
+        L.expm_batched_noalloc.restype = i32
         L.expm_batched_stage.argtypes = [vp, vp, vp, vp, i64, i64, op, vp, vp, vp, vp, sz, vp, i32]
         L.expm_batched_stage.restype = i32
         L.expm_batched_uniform.argtypes = [vp, vp, i64, i64, op, vp, vp, vp, vp, sz, vp]

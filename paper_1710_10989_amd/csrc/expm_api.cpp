@@ -129,6 +129,56 @@ FusedLayout fused_layout(int64_t n_max, int64_t batch) {
   return L;
 }
 
+// ---- expm_batched_noalloc: the fused path's scratch in a device array of the library ----
+// Real orders <= 128 only (the on-chip kernels: the global-memory kernels' slots are not
+// needed), at most kNoAllocBatch matrices, at most kNoAllocSlots 8-wave resident workgroups
+// (one per CU on MI355X).  Layout: queue words | order (int32 x batch) | cost keys (batch
+// bytes) | park slots of the 8-wave resident kernel.
+constexpr int64_t kNoAllocBatch = 65536;
+constexpr int kNoAllocSlots = 256;
+constexpr size_t kNoAllocParkOff = kAlign + ((sizeof(int32_t) * kNoAllocBatch + kAlign - 1) & ~(kAlign - 1)) +
+                                   ((kNoAllocBatch + kAlign - 1) & ~(kAlign - 1));
+constexpr size_t kScratchBytes =
+    kNoAllocParkOff + (size_t)kNoAllocSlots * kResParkDoublesPerT * kResT * sizeof(double);  // 64.3 MiB
+
+// Held by every device the library runs on until the process ends.  Host code never uses this
+// name as an address: noalloc_scratch() looks up the device address once per device.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+
+// Device address of `scratch` on the current device (looked up once per device, with that
+// device current); nullptr on a HIP error.
+void *noalloc_scratch() {
+  static std::map<int, void *> per_dev;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  auto it = per_dev.find(dev);
+  if (it != per_dev.end()) return it->second;
+  void *ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+  per_dev.emplace(dev, ptr);
+  return ptr;
+}
+
+// Layout of the fused path's scratch inside `scratch` for `batch` matrices of real order
+// <= 128: no global-memory slots; the 8-wave resident sweep gets at most kNoAllocSlots slots
+// (its grid is capped to them).
+FusedLayout noalloc_layout(int64_t nr_max, int64_t batch) {
+  FusedLayout L;
+  memset(&L, 0, sizeof(L));
+  const int64_t tr = std::min<int64_t>(np_max_t(nr_max), kResT);
+  L.slotsr = tr > kRes6T ? std::min(grid_for(K_RES8, batch), kNoAllocSlots) : 0;
+  L.slotr_doubles = (size_t)kResParkDoublesPerT * tr;
+  L.queue_off = 0;
+  L.order_off = kAlign;
+  L.key_off = L.order_off + align_up(sizeof(int32_t) * (size_t)batch);
+  L.slots8_off = L.slots4_off = L.slotsr_off = kNoAllocParkOff;
+  L.total = kNoAllocParkOff + (size_t)L.slotsr * L.slotr_doubles * sizeof(double);
+  return L;
+}
+
 // Second stream of the current device for the sweeps that run beside the 8-wave resident
 // sweep (created once per device, default priority), with the fork and join events.  The
 // mutex makes each call's record/wait pairs atomic, so concurrent host threads cannot
@@ -228,11 +278,13 @@ static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, cons
                                int64_t batch, int64_t n_uniform, int64_t n_max,
                                const expm_opts_t *opts, double u, int32_t *m_dev, int32_t *s_dev,
                                int32_t *status_dev, void *ws, size_t ws_bytes, void *stream,
-                               int select_only, int stage = -1, double *features = nullptr) {
-  // n_uniform and n_max are input orders; the kernels pad the real order
+                               int select_only, int stage = -1, double *features = nullptr,
+                               const FusedLayout *given = nullptr) {
+  // n_uniform and n_max are input orders; the kernels pad the real order.  `given`: a layout
+  // of the caller's (the no-allocation variant), whose sweeps then all run on `stream`.
   const int cplx = opts->dtype == EXPM_C128;
   const int64_t nr_max = real_order(opts, n_max), nr_uni = real_order(opts, n_uniform);
-  FusedLayout L = fused_layout(nr_max, batch);
+  FusedLayout L = given ? *given : fused_layout(nr_max, batch);
   if (!ws || ws_bytes < L.total) return EXPM_E_WORKSPACE;
   if (((uintptr_t)ws) % kAlign) return EXPM_E_INVALID_ARG;
   FusedArgs a;
@@ -278,8 +330,8 @@ static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, cons
       case K_FUSED8: grid = L.slots8; e = launch_fused(x, 8, grid, st); break;
       case K_FUSED4: grid = L.slots4; e = launch_fused(x, 4, grid, st); break;
       case K_RES8:
-        grid = grid_for(K_RES8, batch);
-        if (grid > L.slotsr) return false;
+        grid = given ? std::min(grid_for(K_RES8, batch), L.slotsr) : grid_for(K_RES8, batch);
+        if (grid < 1 || grid > L.slotsr) return false;
         e = launch_resident(x, 8, grid, st);
         break;
       case K_RES6: grid = grid_for(K_RES6, batch); e = launch_resident(x, 12, grid, st); break;
@@ -332,7 +384,11 @@ static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, cons
     if (stage == 2) return on(st, {3, 4, 5, 6}) ? EXPM_OK : EXPM_E_HIP;
     if (stage == 5) return on(st, {5, 6}) ? EXPM_OK : EXPM_E_HIP;
     if (stage >= 3) return sub(stage) ? EXPM_OK : EXPM_E_HIP;
-    if (stage == -1) {
+    if (stage == -1 && given) {
+      // no second stream (creating one is not for callers that cannot allocate): the sweeps
+      // in turn on the caller's stream
+      if (!((tmax <= kRes6T || go(K_RES8, r8, 1, 1, 2)) && on(st, {3, 4, 5, 6}))) return EXPM_E_HIP;
+    } else if (stage == -1) {
       std::lock_guard<std::mutex> lk(g_fj_mu);
       ForkJoin fj;
       if (!fork_join_for_device(&fj)) return EXPM_E_HIP;
@@ -447,6 +503,25 @@ expm_status_t expm_batched(const void *A_dev, void *E_dev, const int64_t *offset
   if (real_order(opts, n_max) > kFusedNMax || tiled_only(opts) || opts->flags) return EXPM_E_UNSUPPORTED;
   return run_fused(A_dev, E_dev, offsets_dev, n_dev, batch, 0, n_max, opts, u, m_dev, s_dev,
                    status_dev, ws_dev, ws_bytes, stream, 0);
+}
+
+expm_status_t expm_batched_noalloc(const void *A_dev, void *E_dev, const int64_t *offsets_dev,
+                                   const int32_t *n_dev, int64_t batch, int64_t n_max, const expm_opts_t *opts,
+                                   int32_t *m_dev, int32_t *s_dev, int32_t *status_dev, void *stream) {
+  double u;
+  expm_status_t st = check_opts(opts, &u);
+  if (st != EXPM_OK) return st;
+  if (!A_dev || !E_dev || !offsets_dev || !n_dev || !m_dev || !s_dev || batch < 1 || n_max < 1 ||
+      A_dev == E_dev)
+    return EXPM_E_INVALID_ARG;
+  if (tiled_only(opts) || opts->flags) return EXPM_E_UNSUPPORTED;
+  if (real_order(opts, n_max) > 16 * kResT || batch > kNoAllocBatch) return EXPM_E_WORKSPACE;
+  void *ws = noalloc_scratch();
+  if (!ws) return EXPM_E_HIP;
+  const FusedLayout L = noalloc_layout(real_order(opts, n_max), batch);
+  if (L.total > kScratchBytes) return EXPM_E_WORKSPACE;
+  return run_fused(A_dev, E_dev, offsets_dev, n_dev, batch, 0, n_max, opts, u, m_dev, s_dev, status_dev, ws,
+                   kScratchBytes, stream, 0, -1, nullptr, &L);
 }
 
 expm_status_t expm_batched_stage(const void *A_dev, void *E_dev, const int64_t *offsets_dev,

@@ -155,6 +155,25 @@ def batched(batch, u=None, prec="fp64", selector="plain", workspace=None, out=No
     return E, m, s, status
 
 
+def batched_noalloc(batch, u=None, prec="fp64", selector="plain", outs=None):
+    """e^A for every matrix of a Batch through expm_batched_noalloc (no workspace: the library's
+    own device scratch; real order <= 128, at most 65536 matrices).  outs: reuse (E, m, s,
+    status).  Returns (E_packed, m, s, status) device tensors."""
+    nb = batch.ns.numel()
+    o = _opts(batch.packed.dtype, prec, selector, u)
+    if outs is not None:
+        E, m, s, status = outs
+    else:
+        E = torch.empty_like(batch.packed)
+        m = torch.empty(nb, dtype=torch.int32, device=batch.packed.device)
+        s = torch.empty_like(m)
+        status = torch.empty_like(m)
+    N.check(N.lib().expm_batched_noalloc(_ptr(batch.packed), _ptr(E), _ptr(batch.offsets), _ptr(batch.ns), nb,
+                                         batch.n_max, ctypes.byref(o), _ptr(m), _ptr(s), _ptr(status), _stream()),
+            "expm_batched_noalloc")
+    return E, m, s, status
+
+
 def batched_uniform(A, u=None, prec="fp64", selector="plain", workspace=None, out=None, outs=None,
                     method="reduced"):
     """e^A for a stack A of shape (batch, n, n) of same-order matrices (float64 or complex128).

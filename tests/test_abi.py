@@ -134,3 +134,21 @@ def test_argument_errors_return_before_any_launch():
     assert L.expm_taylor(v, w, 8, ctypes.byref(o), v, v, v, v, 16, None) == N.EXPM_E_WORKSPACE
     assert L.expm_batched(v, w, None, v, 4, 8, ctypes.byref(o), v, v, v, v, 1 << 20, None) == N.EXPM_E_INVALID_ARG
     assert L.expm_select(None, 8, ctypes.byref(o), v, v, v, 1 << 20, None) == N.EXPM_E_INVALID_ARG
+
+
+def test_noalloc_limits_return_before_any_launch():
+    # the no-allocation variant refuses sizes beyond its fixed scratch with EXPM_E_WORKSPACE
+    # and reduced forms with EXPM_E_UNSUPPORTED, before touching any device memory
+    L = N.lib()
+    o = N.ExpmOpts(0, 0, 0, 0, 0.0)
+    v, w = ctypes.c_void_p(16), ctypes.c_void_p(32)
+    call = lambda A, E, nb, nmax, opts: L.expm_batched_noalloc(A, E, v, v, nb, nmax, ctypes.byref(opts), v, v, v,
+                                                               None)
+    assert call(v, w, 4, 129, o) == N.EXPM_E_WORKSPACE
+    assert call(v, w, 65537, 128, o) == N.EXPM_E_WORKSPACE
+    assert call(v, w, 4, 65, N.ExpmOpts(1, 0, 0, 0, 0.0)) == N.EXPM_E_WORKSPACE  # complex: real order 130
+    assert call(v, w, 4, 64, N.ExpmOpts(0, 1, 0, 0, 0.0)) == N.EXPM_E_UNSUPPORTED
+    assert call(v, w, 4, 64, N.ExpmOpts(0, 0, 0, N.EXPM_FLAG_PS, 0.0)) == N.EXPM_E_UNSUPPORTED
+    assert call(v, v, 4, 64, o) == N.EXPM_E_INVALID_ARG  # output aliases input
+    assert call(None, w, 4, 64, o) == N.EXPM_E_INVALID_ARG
+    assert call(v, w, 0, 64, o) == N.EXPM_E_INVALID_ARG
