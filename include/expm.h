@@ -24,7 +24,12 @@
  *    outside [2^-53, 2^-10]) or a HIP launch failure.  Nothing is launched when an argument
  *    error is returned.  No C++ exception crosses this boundary.
  *  - Per-matrix status (device): EXPM_OK, or EXPM_E_NONFINITE when the input holds a NaN or
- *    an infinity; then (m, s) = (-1, -1) and the output is filled with NaN.
+ *    an infinity or its 1-norm overflows the double range; then (m, s) = (-1, -1) and the
+ *    output is filled with NaN.
+ *  - The scaling X = 2^-s A (eq. eses) is applied to the matrix when it is loaded (exactly,
+ *    a power of two), before any power is formed, so no intermediate overflows whatever
+ *    ||A||_1 is; entries of X that fall below the normal range lose bits (as they would in any
+ *    evaluation of 2^-s A).
  */
 #ifndef EXPM_H_
 #define EXPM_H_

@@ -48,6 +48,8 @@ def lib():
         L.or_select_alpha.argtypes = [vp, vp, ip, ip]; L.or_select_alpha.restype = None
         L.or_powers_norms.argtypes = [i64, vp, i32, vp]; L.or_powers_norms.restype = None
         L.or_select_alpha_split.argtypes = [vp, vp, vp, ip, ip]; L.or_select_alpha_split.restype = None
+        L.or_expm_apply.argtypes = [i64, vp, i64, vp, vp]; L.or_expm_apply.restype = i32
+        L.or_expm_apply_z.argtypes = [i64, vp, i64, vp, vp]; L.or_expm_apply_z.restype = i32
         L.or_set_threads.argtypes = [i32]; L.or_set_threads.restype = None
         L.or_get_threads.argtypes = []; L.or_get_threads.restype = i32
         _lib = L
@@ -95,6 +97,22 @@ def expm_taylor(A, prec="ld"):
     if rc < 0:
         raise ValueError("non-finite input")
     return E, s.value
+
+
+def expm_columns(A, cols):
+    """Columns `cols` of e^A, i.e. e^A e_j, from the series of A / q applied q times to e_j in
+    long double, q = ceil(||A||_1 / 2) (see or_expm_apply).  Returns an (n, len(cols)) array."""
+    cplx = np.iscomplexobj(A)
+    A = _c128(A) if cplx else _f64(A)
+    n = A.shape[0]
+    V = np.zeros((len(cols), n), dtype=A.dtype)
+    for c, j in enumerate(cols):
+        V[c, j] = 1.0
+    out = np.empty_like(V)
+    f = lib().or_expm_apply_z if cplx else lib().or_expm_apply
+    if f(n, _p(A), len(cols), _p(V), _p(out)) < 0:
+        raise ValueError("series did not converge")
+    return out.T.copy()
 
 
 def set_threads(t):

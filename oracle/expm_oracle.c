@@ -30,6 +30,8 @@
  *   or_select_alpha    (m, s) from alpha_p = max(d_p, d_{p+1}), d_k = ||A^k||^(1/k), formed
  *                      explicitly (the refinement of the norm cited by the paper in Sec. 1)
  *   or_powers_norms    ||A^k||_1, k = 1..kmax, from explicit powers
+ *   or_expm_apply      e^A v for a few vectors v by the series itself (Sec. 1) applied to
+ *                      A / q, q times (and or_expm_apply_z for complex A)
  */
 #include <complex.h>
 #include <math.h>
@@ -229,6 +231,84 @@ int or_expm_taylor_z(int64_t n, const double *Az, double *Ez, int *s_out) {
   for (int64_t i = 0; i < n * n; ++i) { Ez[2 * i] = (double)creall(S[i]); Ez[2 * i + 1] = (double)cimagl(S[i]); }
   free(X); free(P); free(Q); free(S);
   return terms;
+}
+
+/*
+ * e^A applied to k vectors, from the series definition e^B w = sum_j B^j w / j! (Sec. 1) and
+ * e^A = (e^(A/q))^q: with q = max(1, ceil(||A||_1 / 2)), the series of B = A / q is applied q
+ * times (||B||_1 <= 2, so no term exceeds e^2 ||w||_1 and little cancels), each time
+ * t_0 = w, t_j = B t_{j-1} / j, w <- sum of the t_j, in long double (real A: A row-major
+ * n x n; complex A: interleaved).  A series stops at the first j with j >= 2 ||B||_1 and
+ * ||t_j||_1 <= 2^-64 ||sum||_1: from there on each term is at most half the one before
+ * (||B||_1 / (j + 1) < 1/2), so the neglected tail is at most ||t_j||_1.  V and out hold the k
+ * vectors one after the other (k x n, each contiguous).  Returns the number of applications q,
+ * or -1 when a series needs more than 1000 terms.  OpenMP over the vectors.  Meant for
+ * sampled columns of e^A (v = e_j) at orders where forming e^A on the CPU is too slow.
+ */
+static int64_t apply_steps(ld eta) {
+  const ld q = ceill(eta / 2.0L);
+  return q < 1.0L ? 1 : (int64_t)q;
+}
+
+int or_expm_apply(int64_t n, const double *A, int64_t k, const double *V, double *out) {
+  const ld eta = (ld)or_norm1(n, A);
+  const int64_t q = apply_steps(eta);
+  const ld beta = eta / (ld)q;
+  int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : bad)
+  for (int64_t c = 0; c < k; ++c) {
+    ld *w = malloc(sizeof(ld) * n), *t = malloc(sizeof(ld) * n), *u = malloc(sizeof(ld) * n);
+    for (int64_t i = 0; i < n; ++i) w[i] = V[c * n + i];
+    for (int64_t step = 0; step < q && !bad; ++step) {
+      for (int64_t i = 0; i < n; ++i) t[i] = w[i];
+      int j;
+      for (j = 1; j <= 1000; ++j) {
+        for (int64_t i = 0; i < n; ++i) {
+          ld acc = 0.0L;
+          for (int64_t p = 0; p < n; ++p) acc += (ld)A[i * n + p] * t[p];
+          u[i] = acc / ((ld)q * (ld)j);
+        }
+        ld tn = 0.0L, sn = 0.0L;
+        for (int64_t i = 0; i < n; ++i) { t[i] = u[i]; w[i] += t[i]; tn += fabsl(t[i]); sn += fabsl(w[i]); }
+        if ((ld)j >= 2.0L * beta && tn <= ldexpl(sn, -64)) break;
+      }
+      if (j > 1000) bad += 1;
+    }
+    for (int64_t i = 0; i < n; ++i) out[c * n + i] = (double)w[i];
+    free(w); free(t); free(u);
+  }
+  return bad ? -1 : (int)q;
+}
+
+int or_expm_apply_z(int64_t n, const double *Az, int64_t k, const double *Vz, double *outz) {
+  const ld eta = (ld)or_norm1_z(n, Az);
+  const int64_t q = apply_steps(eta);
+  const ld beta = eta / (ld)q;
+  int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : bad)
+  for (int64_t c = 0; c < k; ++c) {
+    ldc *w = malloc(sizeof(ldc) * n), *t = malloc(sizeof(ldc) * n), *u = malloc(sizeof(ldc) * n);
+    for (int64_t i = 0; i < n; ++i) w[i] = Vz[2 * (c * n + i)] + I * Vz[2 * (c * n + i) + 1];
+    for (int64_t step = 0; step < q && !bad; ++step) {
+      for (int64_t i = 0; i < n; ++i) t[i] = w[i];
+      int j;
+      for (j = 1; j <= 1000; ++j) {
+        for (int64_t i = 0; i < n; ++i) {
+          ldc acc = 0.0L;
+          for (int64_t p = 0; p < n; ++p)
+            acc += ((ld)Az[2 * (i * n + p)] + I * (ld)Az[2 * (i * n + p) + 1]) * t[p];
+          u[i] = acc / ((ld)q * (ld)j);
+        }
+        ld tn = 0.0L, sn = 0.0L;
+        for (int64_t i = 0; i < n; ++i) { t[i] = u[i]; w[i] += t[i]; tn += cabsl(t[i]); sn += cabsl(w[i]); }
+        if ((ld)j >= 2.0L * beta && tn <= ldexpl(sn, -64)) break;
+      }
+      if (j > 1000) bad += 1;
+    }
+    for (int64_t i = 0; i < n; ++i) { outz[2 * (c * n + i)] = (double)creall(w[i]); outz[2 * (c * n + i) + 1] = (double)cimagl(w[i]); }
+    free(w); free(t); free(u);
+  }
+  return bad ? -1 : (int)q;
 }
 
 /* Batched direct Taylor in double or long double, one OpenMP task per matrix. */

@@ -283,7 +283,8 @@ __device__ void run_one(const FusedArgs &a, int64_t b, double *slot, double *red
   const double eta = red[0];
   __syncthreads();
 
-  if (bad) {
+  // a 1-norm that overflows (finite entries) is refused like a non-finite entry
+  if (bad || !(eta <= __DBL_MAX__)) {
     if (E) for (int e = tid; e < nin * nin * (cx ? 2 : 1); e += NT) E[e] = __builtin_nan("");
     if (tid == 0) {
       a.m_out[b] = -1; a.s_out[b] = -1;
@@ -296,6 +297,15 @@ __device__ void run_one(const FusedArgs &a, int64_t b, double *slot, double *red
   if (tid == 0) select_ms(a.k.theta, 0, eta, -1.0, -1.0, &sh_ms[0], &sh_ms[1]);
   __syncthreads();
   const int m_plain = sh_ms[0], s_plain = sh_ms[1];
+  // buffer B *= 2^e exactly (elementwise)
+  auto rescale = [&](double *B, int e2) {
+    if (e2 == 0) return;
+    gdouble *Bg = gptr(B);
+    for (int e = tid; e < (int)nn; e += NT) Bg[e] = ldexp(Bg[e], e2);
+    __syncthreads();
+  };
+  // X_p = 2^-sp A (sp the plain rule's s): every power formed from here on stays in range
+  rescale(buf[0], -s_plain);
 
   // ---- powers A^2 (buffer 1), A^3 (buffer 2) as the selection needs them ----
   bool have2 = false, have3 = false;
@@ -321,9 +331,10 @@ __device__ void run_one(const FusedArgs &a, int64_t b, double *slot, double *red
   if (a.features) {
     // feature row and training label of the learned selector (no e^A)
     form3();
-    n2 = block_norm1<NT>(buf[1], np, red);
-    n3 = block_norm1<NT>(buf[2], np, red);
-    const double tr = block_trace<NT>(buf[0], np, red), asym = block_asym1<NT>(buf[0], np, red);
+    n2 = unscale_norm(block_norm1<NT>(buf[1], np, red), 2, s_plain);
+    n3 = unscale_norm(block_norm1<NT>(buf[2], np, red), 3, s_plain);
+    const double tr = ldexp(block_trace<NT>(buf[0], np, red), s_plain);
+    const double asym = ldexp(block_asym1<NT>(buf[0], np, red), s_plain);
     if (tid == 0) {
       double *row = a.features + b * kFeatRow;
       learned_features(eta, n2, tr, asym, n, row);
@@ -338,8 +349,8 @@ __device__ void run_one(const FusedArgs &a, int64_t b, double *slot, double *red
     __syncthreads();
     return;
   } else if (a.sel == EXPM_SEL_ALPHA) {
-    if (m_plain >= 2) { form2(); n2 = block_norm1<NT>(buf[1], np, red); }
-    if (m_plain >= 12) { form3(); n3 = block_norm1<NT>(buf[2], np, red); }
+    if (m_plain >= 2) { form2(); n2 = unscale_norm(block_norm1<NT>(buf[1], np, red), 2, s_plain); }
+    if (m_plain >= 12) { form3(); n3 = unscale_norm(block_norm1<NT>(buf[2], np, red), 3, s_plain); }
     if (m_plain >= 2) {
       if (tid == 0) select_ms(a.k.theta, 1, eta, n2, n3, &sh_ms[0], &sh_ms[1]);
       __syncthreads();
@@ -349,20 +360,28 @@ __device__ void run_one(const FusedArgs &a, int64_t b, double *slot, double *red
     // proposal from the MLP on features available once A^2 exists; kept only if the alpha
     // bound holds for it (with ||A^3|| when the proposal forms A^3 anyway), else the plain rule
     form2();
-    n2 = block_norm1<NT>(buf[1], np, red);
-    const double tr = block_trace<NT>(buf[0], np, red), asym = block_asym1<NT>(buf[0], np, red);
+    n2 = unscale_norm(block_norm1<NT>(buf[1], np, red), 2, s_plain);
+    const double tr = ldexp(block_trace<NT>(buf[0], np, red), s_plain);
+    const double asym = ldexp(block_asym1<NT>(buf[0], np, red), s_plain);
     const int cls = mlp_infer<NT>(eta, n2, tr, asym, n);
     int mq, sq;
     mlp_class_ms(cls, &mq, &sq);
-    if (mq >= 12) { form3(); n3 = block_norm1<NT>(buf[2], np, red); }
+    if (mq >= 12) { form3(); n3 = unscale_norm(block_norm1<NT>(buf[2], np, red), 3, s_plain); }
     const bool ok = proposal_ok(a.k.theta, eta, n2, mq >= 12 ? n3 : -1.0, mq, sq);
     if (ok) { m = mq; s = sq; } else { m = m_plain; s = s_plain; }
     if (tid == 0) atomicAdd(&g_learned_counts[ok ? 0 : 1], 1ull);
   }
+  // the powers formed so far are those of X_p; X^k = 2^(k (sp - s)) X_p^k (exact) when another
+  // rule chose s != sp; the missing powers are then formed from X itself
+  if (s != s_plain) {
+    rescale(buf[0], s_plain - s);
+    if (have2) rescale(buf[1], 2 * (s_plain - s));
+    if (have3) rescale(buf[2], 3 * (s_plain - s));
+  }
   if (m >= 2) form2();
   if (m >= 12) form3();
   if (tid == 0) {
-    make_coefs(a.k, m, s, g_ep.c);
+    make_coefs(a.k, m, 0, g_ep.c);  // the scaling is in the matrices
     a.m_out[b] = m; a.s_out[b] = s;
     if (a.status) a.status[b] = EXPM_OK;
   }

@@ -66,6 +66,13 @@ __host__ __device__ inline int scale_exp(double eta, double theta) {
   return ee - et + ((be & kFrac) > (bt & kFrac) ? 1 : 0);
 }
 
+// The kernels scale A by 2^-sp (sp: the plain rule's s) when it is loaded, before any power
+// is formed, so every matrix they hold stays in range whatever ||A|| is.  The norm of a power
+// of the scaled matrix is that of A^k times 2^-k sp: unscale_norm gives ||A^k|| back (exactly;
+// +inf when it overflows, which the ALPHA rule then treats as no better than ||A||).  nk < 0
+// (power not formed) passes through.
+__host__ __device__ inline double unscale_norm(double nk, int k, int sp) { return nk < 0 ? nk : ldexp(nk, k * sp); }
+
 // Norm quantities for the ALPHA rule from ||A||, ||A^2||, ||A^3|| (n2, n3 < 0: not formed,
 // replaced by submultiplicative bounds).  d[k-1] >= ||A^k||^(1/k), k = 1..5.
 __host__ __device__ inline void alpha_d(double n1, double n2, double n3, double d[5]) {

@@ -16,7 +16,7 @@ struct LargeLayout {
   int64_t np;       // n rounded up to kLargeTile
   int64_t group;    // matrices processed together
   int64_t nrb;      // row blocks of the norm passes
-  size_t bufs_off, partial_off, norms_off, flags_off, coef_off, list_off, total;
+  size_t bufs_off, partial_off, norms_off, flags_off, coef_off, list_off, shift_off, total;
 };
 
 LargeLayout large_layout(int64_t n_real, int64_t batch);

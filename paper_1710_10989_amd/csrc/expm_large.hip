@@ -66,6 +66,8 @@ struct LargeArgs {
   int ps;                  // Paterson-Stockmeyer comparison method
   const int *flags;        // per matrix: bit 0 non-finite input, bit 1 not upper triangular
   int coff;                // first coefficient of this step in the matrix's 64
+  int32_t *shift;          // per matrix: exponents e0, e1, e2 of the pending rescale
+                           // B_k *= 2^e_k of buffers 0, 1, 2 (lg_rescale_kernel)
   // step description
   int kind;                // epilogue kind (GEMM) or elementwise kind
   int p, q, b0, b1, b2, in0, in1, o[5], dst;
@@ -210,38 +212,67 @@ __global__ __launch_bounds__(256) void lg_colmax_kernel(LargeArgs a, const doubl
   if (threadIdx.x == 0) atomicMax(&norms[mi], (unsigned long long)__double_as_longlong(red[0]));
 }
 
-// (m, s) and coefficients per matrix.  alpha: use ||A^2||, ||A^3|| where formed (norm bits
-// zero and m_plain below the degree that forms them mean "not formed").
+// (m, s) and coefficients per matrix, and the rescale that puts the scaling into the matrices:
+// buffer 0 holds A after the load, so the first pass (alpha = 0) asks for X = 2^-s A (s of the
+// plain rule, or of the Paterson-Stockmeyer rule), exactly, before any power is formed; the
+// coefficients are then the constants themselves.  alpha = 1 (after A^2, A^3 of that X_p =
+// 2^-sp A were formed where the plain degree forms them; their norms are those of X_p^k)
+// recomputes sp, takes ||A^k|| = 2^(k sp) ||X_p^k||, selects, and asks for
+// X^k = 2^(k (sp - s)) X_p^k.  A 1-norm that overflows (finite entries) is refused like a
+// non-finite entry.
 __global__ void lg_select_kernel(LargeArgs a, int count, int stride, const unsigned long long *norms,
                                  const int *flags, int alpha, Consts k, int32_t *status, double *coef) {
   const int mi = blockIdx.x * blockDim.x + threadIdx.x;
   if (mi >= count) return;
   const int64_t gb = a.g0 + mi;
   int32_t *m_arr = const_cast<int32_t *>(a.m_arr), *s_arr = const_cast<int32_t *>(a.s_arr);
-  if (flags[mi] & 1) {
+  int32_t *sh = a.shift + 3 * mi;
+  sh[0] = sh[1] = sh[2] = 0;
+  const double eta = __longlong_as_double((long long)norms[mi]);
+  if ((flags[mi] & 1) || !(eta <= __DBL_MAX__)) {
     m_arr[gb] = -1; s_arr[gb] = -1;
     if (status) status[gb] = EXPM_E_NONFINITE;
     return;
   }
-  const double eta = __longlong_as_double((long long)norms[mi]);
   int m, s;
   if (a.ps) {
     select_ps(k.theta_ps, eta, &m, &s);
     m_arr[gb] = m; s_arr[gb] = s;
     if (status) status[gb] = EXPM_OK;
-    if (m >= 6) make_ps_coefs(m, s, coef + (size_t)mi * 64);
-    else make_coefs(k, m, s, coef + (size_t)mi * 64);
+    if (m >= 6) make_ps_coefs(m, 0, coef + (size_t)mi * 64);
+    else make_coefs(k, m, 0, coef + (size_t)mi * 64);
+    sh[0] = -s;
     return;
   }
   select_ms(k.theta, 0, eta, -1.0, -1.0, &m, &s);
+  const int sp = s;
   if (alpha && m >= 2) {
-    const double n2 = __longlong_as_double((long long)norms[stride + mi]);
-    const double n3 = m >= 12 ? __longlong_as_double((long long)norms[2 * stride + mi]) : -1.0;
+    const double n2 = unscale_norm(__longlong_as_double((long long)norms[stride + mi]), 2, sp);
+    const double n3 = m >= 12 ? unscale_norm(__longlong_as_double((long long)norms[2 * stride + mi]), 3, sp) : -1.0;
     select_ms(k.theta, 1, eta, n2, n3, &m, &s);
+    sh[0] = sp - s; sh[1] = 2 * (sp - s); sh[2] = 3 * (sp - s);
+  } else if (!alpha) {
+    sh[0] = -sp;
   }
   m_arr[gb] = m; s_arr[gb] = s;
   if (status) status[gb] = EXPM_OK;
-  make_coefs(k, m, s, coef + (size_t)mi * 64);
+  make_coefs(k, m, 0, coef + (size_t)mi * 64);
+}
+
+// B_k *= 2^e_k (exact) for buffers k < nbuf of every matrix of the group with e_k != 0.
+// Grid (np * np / 1024, count).
+__global__ __launch_bounds__(256) void lg_rescale_kernel(LargeArgs a, int nbuf) {
+  const int mi = blockIdx.y;
+  const int64_t total = (int64_t)a.np * a.np;
+  for (int k = 0; k < nbuf; ++k) {
+    const int e2 = a.shift[3 * mi + k];
+    if (e2 == 0) continue;
+    gdouble *B = gptr(a.ws + (size_t)mi * a.mstride + (size_t)k * a.bstride);
+    for (int u = 0; u < 4; ++u) {
+      const int64_t e = ((int64_t)blockIdx.x * 4 + u) * 256 + threadIdx.x;
+      if (e < total) B[e] = ldexp(B[e], e2);
+    }
+  }
 }
 
 // One 128 x 128 output tile of a GEMM step for matrix list[blockIdx.y], products in PREC.
@@ -355,7 +386,8 @@ LargeLayout large_layout(int64_t n_real, int64_t batch) {
   L.flags_off = align_up(L.norms_off + (size_t)3 * g * sizeof(unsigned long long));
   L.coef_off = align_up(L.flags_off + (size_t)g * sizeof(int));
   L.list_off = align_up(L.coef_off + (size_t)g * 64 * sizeof(double));
-  L.total = align_up(L.list_off + (size_t)g * 64 * sizeof(int32_t));
+  L.shift_off = align_up(L.list_off + (size_t)g * 64 * sizeof(int32_t));
+  L.total = align_up(L.shift_off + (size_t)g * 3 * sizeof(int32_t));
   return L;
 }
 
@@ -439,6 +471,7 @@ expm_status_t run_large(const LargeCall &c, hipStream_t st) {
   int *flags = (int *)(base + L.flags_off);
   double *coef = (double *)(base + L.coef_off);
   int32_t *lists = (int32_t *)(base + L.list_off);
+  int32_t *shift = (int32_t *)(base + L.shift_off);
 
   LargeArgs a;
   memset(&a, 0, sizeof(a));
@@ -452,7 +485,9 @@ expm_status_t run_large(const LargeCall &c, hipStream_t st) {
   a.coef = coef;
   a.ps = c.ps;
   a.flags = flags;
+  a.shift = shift;
   for (int j = 0; j < 5; ++j) a.o[j] = SEL_NONE;
+  const unsigned rs_blocks = (unsigned)((L.np * L.np + 1023) / 1024);
 
   std::vector<int32_t> mh, sh;
   for (int64_t g0 = 0; g0 < c.batch; g0 += L.group) {
@@ -474,6 +509,7 @@ expm_status_t run_large(const LargeCall &c, hipStream_t st) {
       // plain choice first: it says which powers the method forms anyway
       hipLaunchKernelGGL(lg_select_kernel, dim3((cnt + 63) / 64), dim3(64), 0, st, a, cnt, (int)L.group, norms,
                          flags, 0, c.k, c.status, coef);
+      hipLaunchKernelGGL(lg_rescale_kernel, dim3(rs_blocks, cnt), dim3(256), 0, st, a, 1);
       mh.assign(cnt, 0);
       if (hipMemcpyAsync(mh.data(), c.m_out + g0, cnt * sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
           hipStreamSynchronize(st) != hipSuccess)
@@ -503,9 +539,11 @@ expm_status_t run_large(const LargeCall &c, hipStream_t st) {
       // the alpha selection reads norms[group + i] and norms[2 group + i]
       hipLaunchKernelGGL(lg_select_kernel, dim3((cnt + 63) / 64), dim3(64), 0, st, a, cnt, (int)L.group, norms,
                          flags, 1, c.k, c.status, coef);
+      if (!c.select_only) hipLaunchKernelGGL(lg_rescale_kernel, dim3(rs_blocks, cnt), dim3(256), 0, st, a, 3);
     } else {
       hipLaunchKernelGGL(lg_select_kernel, dim3((cnt + 63) / 64), dim3(64), 0, st, a, cnt, (int)L.group, norms,
                          flags, 0, c.k, c.status, coef);
+      if (!c.select_only) hipLaunchKernelGGL(lg_rescale_kernel, dim3(rs_blocks, cnt), dim3(256), 0, st, a, 1);
     }
     if (hipGetLastError() != hipSuccess || !run.ok) return EXPM_E_HIP;
     mh.assign(cnt, 0);

@@ -184,34 +184,37 @@ __device__ bool t_expm(const Consts &K, const Theta &th, double *L, const TLane 
   t_select_plain(th, eta, &m, &s);
   m = __builtin_amdgcn_readfirstlane(m);
   s = __builtin_amdgcn_readfirstlane(s);
-  const int m_plain = m;
+  const int m_plain = m, s_plain = s;
   q4 X1, X2;
-  if (SEL == EXPM_SEL_PLAIN) {
+  // X_p = 2^-sp A (sp the plain rule's s) before any power is formed: every matrix stays in range
 #pragma unroll
-    for (int r = 0; r < 4; ++r) X0[r] = ldexp(X0[r], -s);
-  }
+  for (int r = 0; r < 4; ++r) X0[r] = ldexp(X0[r], -s);
   if (m_plain >= 2) {
     t_put(L, ln, X0);
     t_zero(X1);
-    t_gemm(L, ln, X0, X1);  // X^2 (A^2 under the alpha rule)
+    t_gemm(L, ln, X0, X1);  // X_p^2
   }
   if (m_plain >= 12) {
     t_zero(X2);
-    t_gemm(L, ln, X1, X2);  // X^3
+    t_gemm(L, ln, X1, X2);  // X_p^3
   }
   if (SEL == EXPM_SEL_ALPHA) {
     if (m_plain >= 2) {
-      // a plain degree below 12 means s = 0 and an alpha degree of at most 8: A^3 is not needed
-      const double n2 = t_norm1(X1), n3 = m_plain >= 12 ? t_norm1(X2) : -1.0;
+      // a plain degree below 12 means s = 0 and an alpha degree of at most 8: A^3 is not needed;
+      // ||A^k|| = 2^(k sp) ||X_p^k||
+      const double n2 = unscale_norm(t_norm1(X1), 2, s_plain);
+      const double n3 = m_plain >= 12 ? unscale_norm(t_norm1(X2), 3, s_plain) : -1.0;
       select_ms(K.theta, 1, eta, n2, n3, &m, &s);
       m = __builtin_amdgcn_readfirstlane(m);
       s = __builtin_amdgcn_readfirstlane(s);
     }
+    // X^k = 2^(k (sp - s)) X_p^k, exactly
+    const int dsc = s_plain - s;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      X0[r] = ldexp(X0[r], -s);
-      X1[r] = ldexp(X1[r], -2 * s);
-      X2[r] = ldexp(X2[r], -3 * s);
+      X0[r] = ldexp(X0[r], dsc);
+      X1[r] = ldexp(X1[r], 2 * dsc);
+      X2[r] = ldexp(X2[r], 3 * dsc);
     }
   }
   *m_out = m;
@@ -618,12 +621,14 @@ __global__ __launch_bounds__(64 * kTinyW, SEL == EXPM_SEL_PLAIN ? 4 : 2) void ex
     const int nin = cur.nin, n = cur.n;
     const int64_t off = cur.off;
     const bool head = lane_id() == 0;
+    double eta = 0.0;  // ||A||_1, taken once the input is known to be finite
     if (nin < 1 || n > 16) {
       if (head) {
         a.m_out[b] = -1; a.s_out[b] = -1;
         if (a.status) a.status[b] = (nin < 1 || n > a.np_max) ? EXPM_E_INVALID_ARG : EXPM_E_UNSUPPORTED;
       }
-    } else if (__any(!isfinite(Xc[0]) || !isfinite(Xc[1]) || !isfinite(Xc[2]) || !isfinite(Xc[3]))) {
+    } else if (__any(!isfinite(Xc[0]) || !isfinite(Xc[1]) || !isfinite(Xc[2]) || !isfinite(Xc[3])) ||
+               !((eta = t_norm1(Xc)) <= __DBL_MAX__)) {  // (a 1-norm that overflows is refused likewise)
       if (a.E)
         for (int e = lane_id(); e < nin * nin * (cx ? 2 : 1); e += 64) a.E[off + e] = __builtin_nan("");
       if (head) {
@@ -634,11 +639,10 @@ __global__ __launch_bounds__(64 * kTinyW, SEL == EXPM_SEL_PLAIN ? 4 : 2) void ex
       q4 AC;
       int m, s;
       bool full;
-      if constexpr (METHOD == 1) full = t_expm_ps(K, L, ln, Xc, t_norm1(Xc), a.select_only, &m, &s, AC);
+      if constexpr (METHOD == 1) full = t_expm_ps(K, L, ln, Xc, eta, a.select_only, &m, &s, AC);
       else if constexpr (METHOD == 2)
-        full = t_expm_pade(K, L, gj + (threadIdx.x >> 6) * 16 * kGjLd, ln, Xc, t_norm1(Xc), a.select_only, &m, &s,
-                           AC);
-      else full = t_expm<SEL>(K, th, L, ln, Xc, t_norm1(Xc), a.select_only, &m, &s, AC);
+        full = t_expm_pade(K, L, gj + (threadIdx.x >> 6) * 16 * kGjLd, ln, Xc, eta, a.select_only, &m, &s, AC);
+      else full = t_expm<SEL>(K, th, L, ln, Xc, eta, a.select_only, &m, &s, AC);
       if (head) {
         a.m_out[b] = m; a.s_out[b] = s;
         if (a.status) a.status[b] = EXPM_OK;

@@ -343,8 +343,8 @@ __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, i
   constexpr bool act = !IDLE;
   dbl4 X0[T], X1[T], X2[T], AC[T];
 
-  // ---- load A (real form of a complex input) into LDS; finiteness, 1-norm.  No register
-  // copy of A lives across the selection (a call); X0 is read back from LDS afterwards. ----
+  // ---- load A (real form of a complex input); finiteness, 1-norm; then X_p = 2^-sp A with sp
+  // the plain rule's s (exact), into LDS: every power formed from here on stays in range. ----
   int bad = 0;
   double csum = 0.0;
   if constexpr (act) {
@@ -385,12 +385,13 @@ __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, i
         bad |= !isfinite(X0[i][r]);
         csum += fabs(X0[i][r]);
       }
-    to_lds<T>(L, ln, X0);
     csum += __shfl_xor(csum, 16);
     csum += __shfl_xor(csum, 32);
   }
   bad = ufi(__syncthreads_or(bad));
-  if (bad) {
+  const double eta = wg_max<NW>(csum, red);
+  // a 1-norm that overflows (finite entries) is refused like a non-finite entry
+  if (bad || !(eta <= __DBL_MAX__)) {
     double *E = a.E ? a.E + off : nullptr;
     if (E) for (int e = tid; e < nin * nin * (cx ? 2 : 1); e += 64 * NW) E[e] = __builtin_nan("");
     if (tid == 0) {
@@ -400,7 +401,6 @@ __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, i
     __syncthreads();
     return;
   }
-  const double eta = wg_max<NW>(csum, red);
 
   // plain rule, evaluated by every lane on the (uniform) norm: integer work on bit patterns
   int m_plain, s_plain;
@@ -408,7 +408,16 @@ __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, i
   m_plain = ufi(m_plain);
   s_plain = ufi(s_plain);
   int m = m_plain, s = s_plain;
-  if constexpr (act) from_lds<T>(L, ln, X0);
+  if constexpr (act) {
+    if (s_plain > 0) {
+#pragma unroll
+      for (int i = 0; i < T; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) X0[i][r] = ldexp(X0[i][r], -s_plain);
+    }
+    to_lds<T>(L, ln, X0);
+  }
+  __syncthreads();
 
   // ---- A^2 (X1), the norms the selector needs, then A^3 (X2) at most once ----
   if (m_plain >= 2 && !IDLE) {
@@ -419,10 +428,10 @@ __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, i
   bool need3 = false;
   int mq = 0, sq = 0;
   if (SEL == EXPM_SEL_ALPHA && m_plain >= 2) {
-    n2 = norm1<NW, T>(X1, act, red);
+    n2 = unscale_norm(norm1<NW, T>(X1, act, red), 2, s_plain);
     need3 = m_plain >= 12;
   } else if (SEL == EXPM_SEL_LEARNED && m_plain >= 2) {
-    n2 = norm1<NW, T>(X1, act, red);
+    n2 = unscale_norm(norm1<NW, T>(X1, act, red), 2, s_plain);
     double tr = 0.0, asy = 0.0;
     if constexpr (act) {
       constexpr int S = Res<T>::S;
@@ -439,8 +448,8 @@ __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, i
       asy += __shfl_xor(asy, 16);
       asy += __shfl_xor(asy, 32);
     }
-    tr = wg_sum<NW>(act ? tr : 0.0, red);
-    asy = wg_max<NW>(act ? asy : 0.0, red);
+    tr = ldexp(wg_sum<NW>(act ? tr : 0.0, red), s_plain);  // of A, not of X_p
+    asy = ldexp(wg_max<NW>(act ? asy : 0.0, red), s_plain);
     const int cls = ufi(res_mlp<64 * NW>(eta, n2, tr, asy, n));
     mlp_class_ms(cls, &mq, &sq);
     if (mq >= 12) {
@@ -470,12 +479,12 @@ __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, i
       rgemm_reg<T>(L, ln, X1, X2);
     }
     if (SEL == EXPM_SEL_ALPHA) {
-      n3 = norm1<NW, T>(X2, act, red);
+      n3 = unscale_norm(norm1<NW, T>(X2, act, red), 3, s_plain);
       if (tid == 0) res_select(sh_consts.theta, 1, eta, n2, n3, &sh_ms[0], &sh_ms[1]);
       __syncthreads();
       m = ufi(sh_ms[0]); s = ufi(sh_ms[1]);
     } else if (SEL == EXPM_SEL_LEARNED && mq >= 12) {
-      n3 = norm1<NW, T>(X2, act, red);
+      n3 = unscale_norm(norm1<NW, T>(X2, act, red), 3, s_plain);
       const bool ok = ufi(res_proposal_ok(sh_consts.theta, eta, n2, n3, mq, sq)) != 0;
       if (ok) { m = mq; s = sq; }
       if (tid == 0) atomicAdd(&g_learned_counts[ok ? 0 : 1], 1ull);
@@ -494,15 +503,37 @@ __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, i
     __syncthreads();
     return;
   }
-  // scaled coefficients of degree M, computed by every lane from the constants in LDS and
-  // moved to scalar registers
+  // The powers held so far are those of X_p = 2^-sp A; the other rules may have chosen s != sp:
+  // X = 2^(sp - s) X_p, so X^k = 2^(k (sp - s)) X_p^k, rescaled exactly here (A itself when its
+  // elements are read below, through x1).
+  const int dsc = s_plain - s;
+  if (SEL != EXPM_SEL_PLAIN && dsc != 0 && act) {
+    if (m_plain >= 2) {
+#pragma unroll
+      for (int i = 0; i < T; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) X1[i][r] = ldexp(X1[i][r], 2 * dsc);
+    }
+    if (need3) {
+#pragma unroll
+      for (int i = 0; i < T; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) X2[i][r] = ldexp(X2[i][r], 3 * dsc);
+    }
+  }
+  auto x1 = [&](double v) {
+    if constexpr (SEL == EXPM_SEL_PLAIN) return v;
+    else return ldexp(v, dsc);
+  };
+  // coefficients of degree M (the scaling is in the matrices), computed by every lane from the
+  // constants in LDS and moved to scalar registers
   auto coefs = [&](auto deg, double *c, int count) {
     double t[24];
-    make_coefs(sh_consts, decltype(deg)::value, s, t);
+    make_coefs(sh_consts, decltype(deg)::value, 0, t);
     for (int j = 0; j < count; ++j) c[j] = uni(t[j]);
   };
 
-  // ---- T_m(A / 2^s) into AC.  Products of polynomials in A commute, so each product is
+  // ---- T_m(X) into AC.  Products of polynomials in A commute, so each product is
   // ordered to make the operand that is not at hand in registers the resident one.  Every
   // elementwise pass writes its results in place of inputs that die with it, so no pass
   // holds more register matrices than the product that follows it. ----
@@ -512,7 +543,8 @@ __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, i
     else { coefs(std::integral_constant<int, 1>(), c, 1); c[1] = 0.0; }
     if constexpr (act) {
       const Own<T> o(ln);
-      each_elem<kPark>(P0, X0, [&](int i, int r, double a1) {
+      each_elem<kPark>(P0, X0, [&](int i, int r, double a1r) {
+        const double a1 = x1(a1r);
         X1[i][r] = o.delta(i, r) + c[0] * a1 + (m == 2 ? c[1] * X1[i][r] : 0.0);
       });
 #pragma unroll
@@ -525,14 +557,16 @@ __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, i
     __syncthreads();
     if constexpr (act) {
       const Own<T> o(ln);
-      each_elem<kPark>(P0, X0, [&](int i, int r, double a1) { L[o.at(i, r)] = c[3] * a1 + c[4] * X1[i][r]; });
+      each_elem<kPark>(P0, X0, [&](int i, int r, double a1r) {
+        const double a1 = x1(a1r); L[o.at(i, r)] = c[3] * a1 + c[4] * X1[i][r]; });
     }
     __syncthreads();
     if constexpr (act) {
       zero<T>(AC);
       rgemm_reg<T>(L, ln, X1, AC);
       const Own<T> o(ln);
-      each_elem<kPark>(P0, X0, [&](int i, int r, double a1) {
+      each_elem<kPark>(P0, X0, [&](int i, int r, double a1r) {
+        const double a1 = x1(a1r);
         AC[i][r] = o.delta(i, r) + c[0] * a1 + c[1] * (AC[i][r] + c[2] * X1[i][r]);
       });
     }
@@ -544,7 +578,8 @@ __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, i
     __syncthreads();
     if constexpr (act) {
       const Own<T> o(ln);
-      each_elem<kPark>(P0, X0, [&](int i, int r, double a1) { L[o.at(i, r)] = c[0] * a1 + c[1] * X1[i][r]; });
+      each_elem<kPark>(P0, X0, [&](int i, int r, double a1r) {
+        const double a1 = x1(a1r); L[o.at(i, r)] = c[0] * a1 + c[1] * X1[i][r]; });
     }
     __syncthreads();
     if constexpr (act) {
@@ -554,7 +589,8 @@ __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, i
     __syncthreads();
     if constexpr (act) {
       const Own<T> o(ln);
-      each_elem<kPark>(P0, X0, [&](int i, int r, double a1) {
+      each_elem<kPark>(P0, X0, [&](int i, int r, double a1r) {
+        const double a1 = x1(a1r);
         const double d = o.delta(i, r), a2 = X1[i][r], a4 = c[2] * AC[i][r];
         L[o.at(i, r)] = c[3] * a2 + a4;                                 // Lm
         X1[i][r] = c[4] * d + c[5] * a1 + c[6] * a2 + c[7] * a4;         // Rm
@@ -570,7 +606,8 @@ __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, i
     __syncthreads();
     if constexpr (act) {
       const Own<T> o(ln);
-      each_elem<kPark>(P0, X0, [&](int i, int r, double a1) {
+      each_elem<kPark>(P0, X0, [&](int i, int r, double a1r) {
+        const double a1 = x1(a1r);
         const double d = o.delta(i, r), a2 = X1[i][r], a3 = X2[i][r];
         L[o.at(i, r)] = k[12] * d + k[13] * a1 + k[14] * a2 + k[15] * a3;  // B_4
         const double b1 = k[0] * d + k[1] * a1 + k[2] * a2 + k[3] * a3;
@@ -616,7 +653,8 @@ __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, i
     __syncthreads();
     if constexpr (act) {
       const Own<T> o(ln);
-      each_elem<kPark>(P0, X0, [&](int i, int r, double a1) {
+      each_elem<kPark>(P0, X0, [&](int i, int r, double a1r) {
+        const double a1 = x1(a1r);
         const double d = o.delta(i, r), a2 = X1[i][r], a3 = L[o.at(i, r)], a6 = AC[i][r];
         L[o.at(i, r)] = k[0] * d + k[1] * a1 + k[2] * a2 + k[3] * a3;  // B_1
         const double b2 = k[4] * d + k[5] * a1 + k[6] * a2 + k[7] * a3 + k[8] * a6;

@@ -173,10 +173,11 @@ __device__ void run_sr(const FusedArgs &a, int64_t b, int n, int nin, int cx, in
         bad |= !isfinite(x);
         csum += fabs(x);
       }
-    sr_put<T, H>(L1, ln, X0);
   }
   bad = ufi(__syncthreads_or(bad));
-  if (bad) {
+  const double eta = sr_colmax(csum, ln, H, act, 16 * T, red);
+  // a 1-norm that overflows (finite entries) is refused like a non-finite entry
+  if (bad || !(eta <= __DBL_MAX__)) {
     double *E = a.E ? a.E + off : nullptr;
     if (E) for (int e = tid; e < nin * nin * (cx ? 2 : 1); e += 64 * kSrNW) E[e] = __builtin_nan("");
     if (tid == 0) {
@@ -186,13 +187,24 @@ __device__ void run_sr(const FusedArgs &a, int64_t b, int n, int nin, int cx, in
     __syncthreads();
     return;
   }
-  const double eta = sr_colmax(csum, ln, H, act, 16 * T, red);
 
   int m_plain, s_plain;
   select_ms(sh_consts.theta, 0, eta, -1.0, -1.0, &m_plain, &s_plain);
   m_plain = ufi(m_plain);
   s_plain = ufi(s_plain);
   int m = m_plain, s = s_plain;
+  // X_p = 2^-sp A (sp the plain rule's s, exact) into L1: every power formed from here on
+  // stays in range
+  if constexpr (act) {
+    if (s_plain > 0) {
+#pragma unroll
+      for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) X0[i][r] = ldexp(X0[i][r], -s_plain);
+    }
+    sr_put<T, H>(L1, ln, X0);
+  }
+  __syncthreads();
 
   // ---- A^2 (X1) = A A from L1; the norms the selector needs; A^3 (X2) at most once ----
   if (m_plain >= 2) {
@@ -205,10 +217,10 @@ __device__ void run_sr(const FusedArgs &a, int64_t b, int n, int nin, int cx, in
   bool need3 = false;
   int mq = 0, sq = 0;
   if (SEL == EXPM_SEL_ALPHA && m_plain >= 2) {
-    n2 = sr_colmax(act ? sr_abs_part<T, H>(X1) : 0.0, ln, H, act, 16 * T, red);
+    n2 = unscale_norm(sr_colmax(act ? sr_abs_part<T, H>(X1) : 0.0, ln, H, act, 16 * T, red), 2, s_plain);
     need3 = m_plain >= 12;
   } else if (SEL == EXPM_SEL_LEARNED && m_plain >= 2) {
-    n2 = sr_colmax(act ? sr_abs_part<T, H>(X1) : 0.0, ln, H, act, 16 * T, red);
+    n2 = unscale_norm(sr_colmax(act ? sr_abs_part<T, H>(X1) : 0.0, ln, H, act, 16 * T, red), 2, s_plain);
     double tr = 0.0, asy = 0.0;
     if constexpr (act) {
       const SrOwn<T, H> o(ln);
@@ -222,8 +234,8 @@ __device__ void run_sr(const FusedArgs &a, int64_t b, int n, int nin, int cx, in
           asy += fabs(X0[i][r] - L1[col * S + (row ^ swz(col))]);
         }
     }
-    tr = wg_sum<kSrNW>(act ? tr : 0.0, red);
-    asy = sr_colmax(act ? asy : 0.0, ln, H, act, 16 * T, red);
+    tr = ldexp(wg_sum<kSrNW>(act ? tr : 0.0, red), s_plain);  // of A, not of X_p
+    asy = ldexp(sr_colmax(act ? asy : 0.0, ln, H, act, 16 * T, red), s_plain);
     const int cls = ufi(res_mlp<64 * kSrNW>(eta, n2, tr, asy, n));
     mlp_class_ms(cls, &mq, &sq);
     if (mq >= 12) {
@@ -245,12 +257,12 @@ __device__ void run_sr(const FusedArgs &a, int64_t b, int n, int nin, int cx, in
       sr_gemm<T, H>(L1, L2, ln, X2);
     }
     if (SEL == EXPM_SEL_ALPHA) {
-      n3 = sr_colmax(act ? sr_abs_part<T, H>(X2) : 0.0, ln, H, act, 16 * T, red);
+      n3 = unscale_norm(sr_colmax(act ? sr_abs_part<T, H>(X2) : 0.0, ln, H, act, 16 * T, red), 3, s_plain);
       if (tid == 0) res_select(sh_consts.theta, 1, eta, n2, n3, &sh_ms[0], &sh_ms[1]);
       __syncthreads();
       m = ufi(sh_ms[0]); s = ufi(sh_ms[1]);
     } else if (SEL == EXPM_SEL_LEARNED && mq >= 12) {
-      n3 = sr_colmax(act ? sr_abs_part<T, H>(X2) : 0.0, ln, H, act, 16 * T, red);
+      n3 = unscale_norm(sr_colmax(act ? sr_abs_part<T, H>(X2) : 0.0, ln, H, act, 16 * T, red), 3, s_plain);
       const bool ok = ufi(res_proposal_ok(sh_consts.theta, eta, n2, n3, mq, sq)) != 0;
       if (ok) { m = mq; s = sq; }
       if (tid == 0) atomicAdd(&g_learned_counts[ok ? 0 : 1], 1ull);
@@ -268,13 +280,27 @@ __device__ void run_sr(const FusedArgs &a, int64_t b, int n, int nin, int cx, in
     __syncthreads();
     return;
   }
+  // The powers held so far are those of X_p; the other rules may have chosen s != sp:
+  // X^k = 2^(k (sp - s)) X_p^k, rescaled exactly.
+  const int dsc = s_plain - s;
+  if (SEL != EXPM_SEL_PLAIN && dsc != 0 && act) {
+#pragma unroll
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        X0[i][r] = ldexp(X0[i][r], dsc);
+        if (m_plain >= 2) X1[i][r] = ldexp(X1[i][r], 2 * dsc);
+        if (need3) X2[i][r] = ldexp(X2[i][r], 3 * dsc);
+      }
+  }
+  // coefficients of the chosen degree (the scaling is in the matrices)
   auto coefs = [&](auto deg, double *c, int count) {
     double t[24];
-    make_coefs(sh_consts, decltype(deg)::value, s, t);
+    make_coefs(sh_consts, decltype(deg)::value, 0, t);
     for (int j = 0; j < count; ++j) c[j] = uni(t[j]);
   };
 
-  // ---- T_m(A / 2^s) into AC (X0 = A, X1 = A^2, X2 = A^3 where formed) ----
+  // ---- T_m(X) into AC (X0 = X, X1 = X^2, X2 = X^3 where formed) ----
   __syncthreads();  // every product so far has finished reading L1 and L2
   if (m <= 2) {
     double c[2];

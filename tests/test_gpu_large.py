@@ -181,3 +181,25 @@ def test_complex_batch_queue_order(P, orc):
     for i in (int(np.argmin(ts)), int(np.argmax(ts)), 0, 319):
         ref, _ = orc.expm_taylor(mats[i])
         assert orc.rel_err_1(L1[i], ref) <= TOL, i
+
+
+def test_complex_config_size_vs_oracle(P, orc):
+    """Four of the complex workload's own matrices (n = 256, -i H dt, dt log-uniform in
+    [1e-2, 1e2]; the smallest and largest dt of the 512 and two more) against the oracle's
+    long-double complex direct Taylor e^A: relative 1-norm error <= 1e-12, and unitarity."""
+    from paper_1710_10989_amd import workloads as W
+    mats, dts = W.hermitian_unitary_batch(count=512, n=256)
+    pick = sorted({int(np.argmin(dts)), int(np.argmax(dts)), 0, 257})
+    A = torch.from_numpy(np.stack([mats[i] for i in pick])).cuda()
+    say("case complex n=256 workload matrices", pick, [round(dts[i], 3) for i in pick])
+    E, m, s, st = P.batched_uniform(A)
+    torch.cuda.synchronize()
+    assert bool((st == 0).all())
+    for j, i in enumerate(pick):
+        ref, _ = orc.expm_taylor(mats[i])
+        X = E[j].cpu().numpy()
+        err = orc.rel_err_1(X, ref)
+        unit = np.abs(X.conj().T @ X - np.eye(256)).sum(0).max()
+        say("  dt=%.3g (m, s)=(%d, %d) rel err %.2e unitarity %.2e" % (dts[i], int(m[j]), int(s[j]), err, unit))
+        assert err <= TOL, (i, err)
+        assert unit <= 1e-12 * (1 << max(int(s[j]), 0)), (i, unit)

@@ -153,3 +153,55 @@ def test_trained_selector_gain(L, orc):
     refs, _ = orc.expm_taylor_batch([mats[i] for i in sample], prec="ld")
     for i, R in zip(sample, refs):
         assert orc.rel_err_1(outs[i], R) <= TOL, (i, kinds[i])
+
+
+def test_held_out_sample_vs_oracle(L, orc):
+    """The learned workload's held-out set (20000 matrices, n in {32, 64, 128, 256}, generated
+    as the benchmark does) through one expm_batched call with the trained selector; 2048 of them
+    (512 per order) against the oracle: relative 1-norm error <= 1e-12 against the FP64 direct
+    Taylor result, and where that misses, against the long-double one; where even the
+    oracle's own FP64 result misses 1e-13 (ill-conditioned, reading R19) within 10x of its
+    error.  Counts of each case are printed."""
+    import os
+    import paper_1710_10989_amd as P
+    from paper_1710_10989_amd.expm import Batch
+    if not os.path.exists(L.DEFAULT_CKPT):
+        pytest.skip("no trained checkpoint")
+    L.load_installed()
+    gen = torch.Generator().manual_seed(20000)
+    stacks = [L.device_batch(5000, n, gen) for n in L.SIZES]
+    packed = torch.cat([a.reshape(-1) for a in stacks])
+    ns = torch.cat([torch.full((5000,), n, dtype=torch.int32) for n in L.SIZES]).cuda()
+    sizes = torch.cat([torch.full((5000,), n * n, dtype=torch.int64) for n in L.SIZES])
+    offs = torch.cat([torch.zeros(1, dtype=torch.int64), torch.cumsum(sizes, 0)[:-1]]).cuda()
+    B = Batch(packed, offs, ns, 256)
+    say("case learned held-out 20000")
+    E, m, s, st = P.batched(B, selector="learned")
+    torch.cuda.synchronize()
+    assert bool((st == 0).all())
+    g = np.random.default_rng(2048)
+    pick = np.concatenate([k * 5000 + g.choice(5000, 512, replace=False) for k in range(4)])
+    offs_h = offs.cpu().numpy()
+    ns_h = ns.cpu().numpy()
+    mats, outs = [], []
+    for i in pick:
+        n, o = int(ns_h[i]), int(offs_h[i])
+        mats.append(packed[o:o + n * n].view(n, n).cpu().numpy())
+        outs.append(E[o:o + n * n].view(n, n).cpu().numpy())
+    refs, _ = orc.expm_taylor_batch(mats, prec="d")
+    direct = ld = ill = 0
+    for A, X, R in zip(mats, outs, refs):
+        if orc.rel_err_1(X, R) <= TOL:
+            direct += 1
+            continue
+        Rl, _ = orc.expm_taylor(A)
+        err = orc.rel_err_1(X, Rl)
+        if err <= TOL:
+            ld += 1
+            continue
+        derr = orc.rel_err_1(R, Rl)
+        assert derr > 1e-13 and err <= 10 * derr, (A.shape[0], err, derr)
+        ill += 1
+    say("held-out sample: %d within 1e-12 of the FP64 oracle, %d of the long-double one, %d ill-conditioned"
+        % (direct, ld, ill))
+    assert direct + ld + ill == len(pick)
