@@ -16,10 +16,12 @@ struct LargeLayout {
   int64_t np;       // n rounded up to kLargeTile
   int64_t group;    // matrices processed together
   int64_t nrb;      // row blocks of the norm passes
-  size_t bufs_off, partial_off, norms_off, flags_off, coef_off, list_off, shift_off, total;
+  size_t bufs_off, partial_off, norms_off, flags_off, coef_off, list_off, shift_off, planes_off, total;
 };
 
-LargeLayout large_layout(int64_t n_real, int64_t batch);
+// prec: expm_prec_t of the call (the reduced forms need room for operand planes); tiles:
+// output tiles per launch (the group holds about that many tiles' worth of matrices).
+LargeLayout large_layout(int64_t n_real, int64_t batch, int prec, int tiles);
 
 struct LargeCall {
   const double *A;    // first input; matrix b at A + b * in_stride doubles
@@ -32,6 +34,7 @@ struct LargeCall {
   int select_only;
   int ps;             // Paterson-Stockmeyer comparison method (EXPM_FLAG_PS)
   int tri;            // triangular refinement (EXPM_FLAG_TRI)
+  int tiles;          // output tiles per launch
   int32_t *m_out, *s_out, *status;  // device, one per matrix
   void *ws;
   size_t ws_bytes;

@@ -31,6 +31,10 @@ namespace expm {
 namespace {
 
 typedef TileShape<8, 128, 128, 4, 2, 2, 4> LS;
+// LDS pool of the reduced-precision products: the three-stage ring of bfloat16 planes
+// (144 KiB), reused as the chunk copy of C
+constexpr int kPoolLp = 18432;
+static_assert(kLargeTile * 129 <= kPoolLp, "tile copy exceeds the reduced-precision pool");
 constexpr int LDC_L = 129;
 static_assert(kLargeTile * LDC_L <= kPool8, "tile copy exceeds the LDS pool");
 
@@ -66,6 +70,8 @@ struct LargeArgs {
   int ps;                  // Paterson-Stockmeyer comparison method
   const int *flags;        // per matrix: bit 0 non-finite input, bit 1 not upper triangular
   int coff;                // first coefficient of this step in the matrix's 64
+  void *planes;            // operand planes of reduced-precision products (2 PL np^2
+                           // elements per matrix: left-operand planes, then right-operand)
   int32_t *shift;          // per matrix: exponents e0, e1, e2 of the pending rescale
                            // B_k *= 2^e_k of buffers 0, 1, 2 (lg_rescale_kernel)
   // step description
@@ -275,7 +281,27 @@ __global__ __launch_bounds__(256) void lg_rescale_kernel(LargeArgs a, int nbuf) 
   }
 }
 
-// One 128 x 128 output tile of a GEMM step for matrix list[blockIdx.y], products in PREC.
+// Thread 0 of a GEMM tile fills the LDS descriptor of the step for matrix mi.
+__device__ inline void fill_desc(const LargeArgs &a, int mi, int64_t gb, int m, int s) {
+  EpiDesc &d = g_ep;
+  d.P = sel_ptr(a, mi, a.p, m, s);
+  d.Q = sel_ptr(a, mi, a.q, m, s);
+  d.b0 = sel_ptr(a, mi, 0, m, s); d.b1 = sel_ptr(a, mi, 1, m, s); d.b2 = sel_ptr(a, mi, 2, m, s);
+  d.in0 = a.in0 >= 0 ? sel_ptr(a, mi, a.in0, m, s) : nullptr;
+  d.in1 = a.in1 >= 0 ? sel_ptr(a, mi, a.in1, m, s) : nullptr;
+  for (int j = 0; j < 5; ++j) d.o[j] = a.o[j] >= 0 ? sel_ptr(a, mi, a.o[j], m, s) : nullptr;
+  double *dst = sel_ptr(a, mi, a.dst, m, s);
+  if (dst) {
+    d.dst = dst; d.dst_ld = a.np; d.dst_nvalid = a.np; d.cplx = 0;
+  } else {
+    d.dst = a.E + gb * a.io_stride; d.dst_ld = a.n; d.dst_nvalid = a.nin; d.cplx = a.cplx;
+  }
+  d.kind = a.kind;
+  d.np = a.np;
+  for (int i = 0; i < 64; ++i) d.c[i] = i + a.coff < 64 ? a.coef[(size_t)mi * 64 + a.coff + i] : 0.0;
+}
+
+// One 128 x 128 output tile of an FP64 GEMM step for matrix list[blockIdx.y].
 template <int PREC>
 __global__ __launch_bounds__(512, 1) void lg_gemm_kernel(LargeArgs a) {
   const int mi = a.list[blockIdx.y];
@@ -283,24 +309,7 @@ __global__ __launch_bounds__(512, 1) void lg_gemm_kernel(LargeArgs a) {
   const int m = a.m_arr[gb], s = a.s_arr[gb];
   const int tiles = a.np / kLargeTile;
   const int tm = blockIdx.x / tiles, tn = blockIdx.x - tm * tiles;
-  if (threadIdx.x == 0) {
-    EpiDesc &d = g_ep;
-    d.P = sel_ptr(a, mi, a.p, m, s);
-    d.Q = sel_ptr(a, mi, a.q, m, s);
-    d.b0 = sel_ptr(a, mi, 0, m, s); d.b1 = sel_ptr(a, mi, 1, m, s); d.b2 = sel_ptr(a, mi, 2, m, s);
-    d.in0 = a.in0 >= 0 ? sel_ptr(a, mi, a.in0, m, s) : nullptr;
-    d.in1 = a.in1 >= 0 ? sel_ptr(a, mi, a.in1, m, s) : nullptr;
-    for (int j = 0; j < 5; ++j) d.o[j] = a.o[j] >= 0 ? sel_ptr(a, mi, a.o[j], m, s) : nullptr;
-    double *dst = sel_ptr(a, mi, a.dst, m, s);
-    if (dst) {
-      d.dst = dst; d.dst_ld = a.np; d.dst_nvalid = a.np; d.cplx = 0;
-    } else {
-      d.dst = a.E + gb * a.io_stride; d.dst_ld = a.n; d.dst_nvalid = a.nin; d.cplx = a.cplx;
-    }
-    d.kind = a.kind;
-    d.np = a.np;
-    for (int i = 0; i < 64; ++i) d.c[i] = i + a.coff < 64 ? a.coef[(size_t)mi * 64 + a.coff + i] : 0.0;
-  }
+  if (threadIdx.x == 0) fill_desc(a, mi, gb, m, s);
   __syncthreads();
   TileLds<LS> &L = *reinterpret_cast<TileLds<LS> *>(lds_pool<8>());
   const int wave = threadIdx.x >> 6;
@@ -318,7 +327,81 @@ __global__ __launch_bounds__(512, 1) void lg_gemm_kernel(LargeArgs a) {
   double *cbuf = lds_pool<8>();
   stage_acc<LS, LDC_L, PREC>(cbuf, acc, wr_row, wc_col);
   __syncthreads();
-  run_epilogue<8>(m0, n0, kLargeTile, kLargeTile, LDC_L);
+  run_epilogue<8>(cbuf, m0, n0, kLargeTile, kLargeTile, LDC_L);
+}
+
+// Operand planes of a reduced-precision product (tile_gemm_lp): the FP64 buffer `sel` of each
+// listed matrix, converted once, into the matrix's plane region: forms bit 0 row-major planes
+// at the left-operand slot, bit 1 transposed planes at the right-operand slot.  BF16X3: hi,
+// mid, lo = successive bfloat16 roundings (split3); F32: the FP32 rounding.  A 64 x 64 tile per
+// workgroup, transposed through LDS.  Grid (np / 64, np / 64, count).
+template <int PREC>
+__global__ __launch_bounds__(256) void lg_planes_kernel(LargeArgs a, int sel, int forms) {
+  typedef typename LpOf<PREC>::E E;
+  constexpr int PL = LpOf<PREC>::PL;
+  __shared__ double t[64][65];
+  const int mi = a.list[blockIdx.z];
+  const int64_t gb = a.g0 + mi;
+  const int m = a.m_arr[gb], s = a.s_arr[gb];
+  cgdouble *B = gptr((const double *)sel_ptr(a, mi, sel, m, s));
+  const int np = a.np;
+  const size_t nn = (size_t)np * np;
+  E *base = (E *)a.planes + (size_t)mi * (2 * PL) * nn;
+  const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  auto put = [&](E *dst, size_t e, double x) {
+    if constexpr (PREC == PREC_BF16X3) {
+      short h, md, l;
+      split3(x, h, md, l);
+      dst[e] = h; dst[nn + e] = md; dst[2 * nn + e] = l;
+    } else {
+      dst[e] = (float)x;
+    }
+  };
+  for (int rr = ty; rr < 64; rr += 4) {
+    const double x = B[(size_t)(r0 + rr) * np + c0 + tx];
+    t[rr][tx] = x;
+    if (forms & 1) put(base, (size_t)(r0 + rr) * np + c0 + tx, x);
+  }
+  if (forms & 2) {
+    __syncthreads();
+    for (int rr = ty; rr < 64; rr += 4) put(base + PL * nn, (size_t)(c0 + rr) * np + r0 + tx, t[tx][rr]);
+  }
+}
+
+// One 128 x 128 output tile of a reduced-precision product on operand planes (left operand
+// row-major planes, right operand transposed planes of the matrix's plane region), then the
+// step's epilogue, as lg_gemm_kernel.
+__shared__ double g_pool_lp[kPoolLp];
+template <int PREC>
+__global__ __launch_bounds__(512, 1) void lg_gemm_lp_kernel(LargeArgs a) {
+  typedef typename LpOf<PREC>::E E;
+  constexpr int PL = LpOf<PREC>::PL;
+  static_assert(sizeof(LpLds<LS, PREC>) <= sizeof(g_pool_lp), "stage ring exceeds the pool");
+  const int mi = a.list[blockIdx.y];
+  const int64_t gb = a.g0 + mi;
+  const int m = a.m_arr[gb], s = a.s_arr[gb];
+  const int tiles = a.np / kLargeTile;
+  const int tm = blockIdx.x / tiles, tn = blockIdx.x - tm * tiles;
+  if (threadIdx.x == 0) fill_desc(a, mi, gb, m, s);
+  __syncthreads();
+  LpLds<LS, PREC> &L = *reinterpret_cast<LpLds<LS, PREC> *>(g_pool_lp);
+  const int wave = threadIdx.x >> 6;
+  const int wr = wave / LS::WC, wc = wave % LS::WC;
+  const int wr_row = wr * LS::BR * 16, wc_col = wc * LS::BC * 16;
+  const int m0 = tm * kLargeTile, n0 = tn * kLargeTile;
+  const size_t nn = (size_t)a.np * a.np;
+  const E *P = (const E *)a.planes + (size_t)mi * (2 * PL) * nn;
+  flt4 acc[LS::TPW];
+  tile_gemm_lp<LS, PREC>(P, P + PL * nn, nn, a.np, a.np, a.np, a.np, m0, n0, L, true, wr_row, wc_col, acc);
+  if (a.kind == EK_STORE) {
+    store_acc<LS, PREC>(acc, m0 + wr_row, n0 + wc_col);
+    return;
+  }
+  __syncthreads();
+  stage_acc<LS, LDC_L, PREC>(g_pool_lp, acc, wr_row, wc_col);
+  __syncthreads();
+  run_epilogue<8>(g_pool_lp, m0, n0, kLargeTile, kLargeTile, LDC_L);
 }
 
 // Elementwise steps (no product), kinds LC1, LC2 (T = I + c0 A [+ c1 A^2]), LC4W, LC8W,
@@ -369,12 +452,12 @@ __global__ __launch_bounds__(256) void lg_elem_kernel(LargeArgs a) {
 
 }  // namespace
 
-LargeLayout large_layout(int64_t n_real, int64_t batch) {
+LargeLayout large_layout(int64_t n_real, int64_t batch, int prec, int tiles_per_launch) {
   LargeLayout L;
   L.n = n_real;
   L.np = (n_real + kLargeTile - 1) / kLargeTile * kLargeTile;
   const int64_t tiles = (L.np / kLargeTile) * (L.np / kLargeTile);
-  int64_t g = (2048 + tiles - 1) / tiles;   // about 2048 output tiles per launch
+  int64_t g = (tiles_per_launch + tiles - 1) / tiles;   // about that many output tiles per launch
   if (g < 1) g = 1;
   if (g > batch) g = batch;
   L.group = g;
@@ -387,7 +470,10 @@ LargeLayout large_layout(int64_t n_real, int64_t batch) {
   L.coef_off = align_up(L.flags_off + (size_t)g * sizeof(int));
   L.list_off = align_up(L.coef_off + (size_t)g * 64 * sizeof(double));
   L.shift_off = align_up(L.list_off + (size_t)g * 64 * sizeof(int32_t));
-  L.total = align_up(L.shift_off + (size_t)g * 3 * sizeof(int32_t));
+  // operand planes: BF16X3 2 x 3 bfloat16 planes per matrix, FP32 and FP32_ALL 2 float planes
+  const size_t plane_bytes = prec == EXPM_PREC_BF16X3 ? 12 : prec == EXPM_PREC_FP64 ? 0 : 8;
+  L.planes_off = align_up(L.shift_off + (size_t)g * 3 * sizeof(int32_t));
+  L.total = align_up(L.planes_off + (size_t)g * plane_bytes * nn);
   return L;
 }
 
@@ -428,10 +514,29 @@ struct Launcher {
     // EXPM_PREC_FP32_ALL: every product in FP32; otherwise the reduced form covers the powers
     // and the first product of the stage, and the rest stays FP64
     const int pr = prec == EXPM_PREC_FP32_ALL ? PREC_F32 : reduced ? prec : PREC_F64;
-    if (pr == PREC_F32) hipLaunchKernelGGL(lg_gemm_kernel<PREC_F32>, dim3(tiles, (unsigned)idx.size()), dim3(512), 0, st, a);
-    else if (pr == PREC_BF16X3)
-      hipLaunchKernelGGL(lg_gemm_kernel<PREC_BF16X3>, dim3(tiles, (unsigned)idx.size()), dim3(512), 0, st, a);
-    else hipLaunchKernelGGL(lg_gemm_kernel<PREC_F64>, dim3(tiles, (unsigned)idx.size()), dim3(512), 0, st, a);
+    const dim3 grid(tiles, (unsigned)idx.size());
+    if (pr == PREC_F64) {
+      hipLaunchKernelGGL(lg_gemm_kernel<PREC_F64>, grid, dim3(512), 0, st, a);
+    } else {
+      // operands converted once into planes (both forms from one read when P = Q), then the
+      // product on the planes
+      const dim3 pg((unsigned)(L.np / 64), (unsigned)(L.np / 64), (unsigned)idx.size());
+      if (pr == PREC_F32) {
+        if (p == q) hipLaunchKernelGGL(lg_planes_kernel<PREC_F32>, pg, dim3(256), 0, st, a, p, 3);
+        else {
+          hipLaunchKernelGGL(lg_planes_kernel<PREC_F32>, pg, dim3(256), 0, st, a, p, 1);
+          hipLaunchKernelGGL(lg_planes_kernel<PREC_F32>, pg, dim3(256), 0, st, a, q, 2);
+        }
+        hipLaunchKernelGGL(lg_gemm_lp_kernel<PREC_F32>, grid, dim3(512), 0, st, a);
+      } else {
+        if (p == q) hipLaunchKernelGGL(lg_planes_kernel<PREC_BF16X3>, pg, dim3(256), 0, st, a, p, 3);
+        else {
+          hipLaunchKernelGGL(lg_planes_kernel<PREC_BF16X3>, pg, dim3(256), 0, st, a, p, 1);
+          hipLaunchKernelGGL(lg_planes_kernel<PREC_BF16X3>, pg, dim3(256), 0, st, a, q, 2);
+        }
+        hipLaunchKernelGGL(lg_gemm_lp_kernel<PREC_BF16X3>, grid, dim3(512), 0, st, a);
+      }
+    }
     if (hipGetLastError() != hipSuccess) ok = false;
   }
 
@@ -462,7 +567,7 @@ struct Launcher {
 
 expm_status_t run_large(const LargeCall &c, hipStream_t st) {
   const int64_t n = c.cplx ? 2 * c.nin : c.nin;
-  LargeLayout L = large_layout(n, c.batch);
+  LargeLayout L = large_layout(n, c.batch, c.prec, c.tiles);
   if (!c.ws || c.ws_bytes < L.total) return EXPM_E_WORKSPACE;
   char *base = (char *)c.ws;
   double *bufs = (double *)(base + L.bufs_off);
@@ -486,6 +591,7 @@ expm_status_t run_large(const LargeCall &c, hipStream_t st) {
   a.ps = c.ps;
   a.flags = flags;
   a.shift = shift;
+  a.planes = base + L.planes_off;
   for (int j = 0; j < 5; ++j) a.o[j] = SEL_NONE;
   const unsigned rs_blocks = (unsigned)((L.np * L.np + 1023) / 1024);
 

@@ -114,8 +114,7 @@ __device__ inline void for_chunk(const double *cbuf, int row0, int col0, int row
 }
 
 template <int NW>
-__device__ inline void run_epilogue(int row0, int col0, int rows, int cols, int ldc) {
-  const double *cbuf = lds_pool<NW>();
+__device__ inline void run_epilogue(const double *cbuf, int row0, int col0, int rows, int cols, int ldc) {
   const int np = g_ep.np;
   const double *c = g_ep.c;
   switch (g_ep.kind) {
@@ -272,7 +271,7 @@ __device__ __noinline__ void gemm_t() {
       __syncthreads();
       const int rows = (np - m0) < S::BM ? (np - m0) : S::BM;
       const int cols = (np - n0) < S::BN ? (np - n0) : S::BN;
-      run_epilogue<NW>(m0, n0, rows, cols, LDC);
+      run_epilogue<NW>(cbuf, m0, n0, rows, cols, LDC);
       __syncthreads();  // chunk copy consumed before the next chunk's loads
     }
   }
