@@ -246,6 +246,43 @@ EXPM_API expm_status_t expm_magnus4_step(const double *S0_dev, const double *S1_
                                          int32_t *status_dev, void *stream);
 
 /* ---------------------------------------------------------------------------------------
+ * Launch configuration (not part of the paper's method; no effect on any result's
+ * definition): what an autotuner picks per order range, precision and selector by timing the
+ * candidates on the device (paper_1710_10989_amd/autotune.py keeps the winners in a JSON cache
+ * keyed by the GPU architecture and installs them with expm_tune_set).  A zero field means the
+ * library's default, which is what an untuned process runs.  Process-wide.
+ *  arrangement[sel]     expm_batched with selector sel: 0 (default) the sweeps of real orders
+ *                       144..256, 80..96 and <= 16 on a second stream beside 112..128 then
+ *                       17..64 on `stream`; 1 every sweep in turn on `stream`; 2 144..256 and
+ *                       80..96 beside 112..128, 17..64, <= 16; 3 everything but 112..128 on
+ *                       the second stream.
+ *  small_kernel         real order <= 16: 0 / 1 one wavefront per matrix (default), 2 the
+ *                       4-wave on-chip kernel.
+ *  per_cu[k]            persistent workgroups per CU of sweep kernel k (0 global-memory 4-wave,
+ *                       1 global-memory 8-wave, 2 on-chip 4-wave, 3 split-row, 4 on-chip 8-wave,
+ *                       5 one-wave kernel, in that kernel's workgroups); 0 or more than the
+ *                       occupancy maximum means that maximum.
+ *  tiles_per_launch[p]  tiled path (orders above 256 and the reduced forms) with expm_prec_t p:
+ *                       output tiles per launch, which sets how many matrices a group holds
+ *                       (0: 2048).  It changes the workspace expm_workspace_bytes reports, so
+ *                       query that after expm_tune_set.
+ * Fields out of range: EXPM_E_INVALID_ARG. */
+typedef struct {
+  int32_t arrangement[3];
+  int32_t small_kernel;
+  int32_t per_cu[6];
+  int32_t tiles_per_launch[4];
+} expm_tune_t;
+
+EXPM_API expm_status_t expm_tune_set(const expm_tune_t *t);
+/* The installed configuration (zero fields: defaults). */
+EXPM_API expm_status_t expm_tune_get(expm_tune_t *t);
+/* The candidates' upper limits on the current device: per_cu[k] = occupancy maximum of sweep
+ * kernel k, the largest arrangement and small_kernel values, the default tiles_per_launch.
+ * EXPM_E_HIP when no device is visible. */
+EXPM_API expm_status_t expm_tune_limits(expm_tune_t *t);
+
+/* ---------------------------------------------------------------------------------------
  * Learned (m, s) selector (EXPM_SEL_LEARNED).  Not part of the paper: a small MLP proposes
  * (m, s) from features that exist once A^2 is formed; the proposal is kept only when the
  * alpha_p backward-error bound of eq. eq.theta holds for it (with ||A^3|| when the proposed

@@ -18,13 +18,18 @@ EXPM_FLAG_PS, EXPM_FLAG_PADE, EXPM_FLAG_TRI = 1, 2, 4
 
 EXPORTED = ("expm_status_string", "expm_theta", "expm_select_rule", "expm_workspace_bytes",
             "expm_select", "expm_taylor", "expm_batched", "expm_batched_noalloc", "expm_batched_stage", "expm_batched_uniform",
-            "expm_magnus4_step", "expm_features", "expm_mlp_scratch_bytes", "expm_mlp_param_count", "expm_mlp_forward",
+            "expm_magnus4_step", "expm_tune_set", "expm_tune_get", "expm_tune_limits", "expm_features", "expm_mlp_scratch_bytes", "expm_mlp_param_count", "expm_mlp_forward",
             "expm_mlp_grad", "expm_mlp_adam", "expm_learned_set", "expm_learned_counts")
 
 
 class ExpmOpts(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int32), ("prec", ctypes.c_int32), ("sel", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("u", ctypes.c_double)]
+
+
+class ExpmTune(ctypes.Structure):
+    _fields_ = [("arrangement", ctypes.c_int32 * 3), ("small_kernel", ctypes.c_int32),
+                ("per_cu", ctypes.c_int32 * 6), ("tiles_per_launch", ctypes.c_int32 * 4)]
 
 
 class ExpmError(RuntimeError):
@@ -62,6 +67,10 @@ def lib():
         L.expm_batched_uniform.restype = i32
         L.expm_magnus4_step.argtypes = [vp, vp, i64, vp, vp, vp, vp, i64, i64, dbl, op, vp, vp, vp, vp]
         L.expm_magnus4_step.restype = i32
+        tp = ctypes.POINTER(ExpmTune)
+        L.expm_tune_set.argtypes = [tp]; L.expm_tune_set.restype = i32
+        L.expm_tune_get.argtypes = [tp]; L.expm_tune_get.restype = i32
+        L.expm_tune_limits.argtypes = [tp]; L.expm_tune_limits.restype = i32
         L.expm_features.argtypes = [vp, vp, vp, i64, i64, op, vp, vp, vp, vp, sz, vp]
         L.expm_features.restype = i32
         L.expm_mlp_scratch_bytes.argtypes = [i32]; L.expm_mlp_scratch_bytes.restype = sz

@@ -83,8 +83,27 @@ FusedCaps fused_caps() {
 // K_RES6: split-row kernel, np 80..96; K_TINY: one wave per matrix, np 16
 enum Kern { K_FUSED4, K_FUSED8, K_RES4, K_RES6, K_RES8, K_TINY };
 
-int grid_for(Kern k, int64_t batch) {
+// Launch configuration installed by expm_tune_set (process-wide; zero fields = defaults).
+std::mutex g_tune_mu;
+expm_tune_t g_tune = {};
+expm_tune_t tune_now() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return g_tune;
+}
+constexpr int kDefaultTiles = 2048;
+
+// Persistent grid of sweep kernel k for `batch` matrices: resident workgroups per CU (the
+// occupancy maximum, or fewer when tuned; layouts size their slots with tuned = false).
+int grid_for(Kern k, int64_t batch, bool tuned = true) {
   FusedCaps c = fused_caps();
+  if (tuned) {
+    const int t = tune_now().per_cu[k];
+    if (t > 0) {
+      int *per = k == K_FUSED4 ? &c.per4 : k == K_FUSED8 ? &c.per8 : k == K_RES4 ? &c.res4
+               : k == K_RES6 ? &c.res6 : k == K_RES8 ? &c.res8 : &c.tiny;
+      if (t < *per) *per = t;
+    }
+  }
   if (k == K_TINY) {  // one matrix per wave; no per-workgroup slot
     const int64_t w = tiny_waves_per_block();
     const int64_t need = (batch + w - 1) / w;
@@ -113,9 +132,9 @@ FusedLayout fused_layout(int64_t n_max, int64_t batch) {
   const int64_t np = pad16(n_max);
   const int64_t np4 = std::min<int64_t>(np, 16 * (kSplitT - 1));
   const int64_t tr = std::min<int64_t>(np_max_t(n_max), kResT);
-  L.slots4 = grid_for(K_FUSED4, batch);
-  L.slots8 = np_max_t(n_max) >= kSplitT ? grid_for(K_FUSED8, batch) : 0;
-  L.slotsr = tr > kRes6T ? grid_for(K_RES8, batch) : 0;  // the 8-wave resident kernel: np 112, 128
+  L.slots4 = grid_for(K_FUSED4, batch, false);
+  L.slots8 = np_max_t(n_max) >= kSplitT ? grid_for(K_FUSED8, batch, false) : 0;
+  L.slotsr = tr > kRes6T ? grid_for(K_RES8, batch, false) : 0;  // the 8-wave resident kernel: np 112, 128
   L.slot8_doubles = (size_t)kFusedBufs * np * np;
   L.slot4_doubles = (size_t)kFusedBufs * np4 * np4;
   L.slotr_doubles = (size_t)kResParkDoublesPerT * tr;
@@ -169,7 +188,7 @@ FusedLayout noalloc_layout(int64_t nr_max, int64_t batch) {
   FusedLayout L;
   memset(&L, 0, sizeof(L));
   const int64_t tr = std::min<int64_t>(np_max_t(nr_max), kResT);
-  L.slotsr = tr > kRes6T ? std::min(grid_for(K_RES8, batch), kNoAllocSlots) : 0;
+  L.slotsr = tr > kRes6T ? std::min(grid_for(K_RES8, batch, false), kNoAllocSlots) : 0;
   L.slotr_doubles = (size_t)kResParkDoublesPerT * tr;
   L.queue_off = 0;
   L.order_off = kAlign;
@@ -177,6 +196,12 @@ FusedLayout noalloc_layout(int64_t nr_max, int64_t batch) {
   L.slots8_off = L.slots4_off = L.slotsr_off = kNoAllocParkOff;
   L.total = kNoAllocParkOff + (size_t)L.slotsr * L.slotr_doubles * sizeof(double);
   return L;
+}
+
+// Output tiles per launch of the tiled path for precision `prec` (tuned or the default).
+int tiles_per_launch(int prec) {
+  const int t = tune_now().tiles_per_launch[prec];
+  return t > 0 ? t : kDefaultTiles;
 }
 
 // Second stream of the current device for the sweeps that run beside the 8-wave resident
@@ -265,7 +290,7 @@ size_t expm_workspace_bytes(int64_t n_max, int64_t batch, const expm_opts_t *opt
   if (n_max < 1 || batch < 1 || check_opts(opts, &u) != EXPM_OK) return 0;
   const int64_t nr = real_order(opts, n_max);
   if (nr <= kFusedNMax && !tiled_only(opts, n_max)) return fused_layout(nr, batch).total;
-  return large_layout(nr, batch).total;
+  return large_layout(nr, batch, opts->prec, tiles_per_launch(opts->prec)).total;
 }
 
 // stage: -1 all phases; 0 sort the batch into the work queue; 1 sweep of the 8-wave resident
@@ -319,19 +344,20 @@ static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, cons
   r6.slots = r4.slots = tn.slots = nullptr;
   r6.slot_doubles = r4.slot_doubles = tn.slot_doubles = 0;
   // np = 16 runs one matrix per wave, except under the learned selector (whose network
-  // lives with the workgroup kernels)
-  const bool tiny = opts->sel != EXPM_SEL_LEARNED;
+  // lives with the workgroup kernels) or when tuned onto the 4-wave kernel
+  const expm_tune_t tune = tune_now();
+  const bool tiny = opts->sel != EXPM_SEL_LEARNED && tune.small_kernel != 2;
   const int tmax = np_max_t(nr_max);
   auto go = [&](Kern k, FusedArgs &x, int ctr, int lo, int hi) -> bool {
     x.q_ctr = ctr; x.q_lo = lo; x.q_hi = hi;
     int grid;
     hipError_t e;
     switch (k) {
-      case K_FUSED8: grid = L.slots8; e = launch_fused(x, 8, grid, st); break;
-      case K_FUSED4: grid = L.slots4; e = launch_fused(x, 4, grid, st); break;
+      case K_FUSED8: grid = std::min(L.slots8, grid_for(K_FUSED8, batch)); e = launch_fused(x, 8, grid, st); break;
+      case K_FUSED4: grid = std::min(L.slots4, grid_for(K_FUSED4, batch)); e = launch_fused(x, 4, grid, st); break;
       case K_RES8:
-        grid = given ? std::min(grid_for(K_RES8, batch), L.slotsr) : grid_for(K_RES8, batch);
-        if (grid < 1 || grid > L.slotsr) return false;
+        grid = std::min(grid_for(K_RES8, batch), L.slotsr);
+        if (grid < 1) return false;
         e = launch_resident(x, 8, grid, st);
         break;
       case K_RES6: grid = grid_for(K_RES6, batch); e = launch_resident(x, 12, grid, st); break;
@@ -388,16 +414,23 @@ static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, cons
       // no second stream (creating one is not for callers that cannot allocate): the sweeps
       // in turn on the caller's stream
       if (!((tmax <= kRes6T || go(K_RES8, r8, 1, 1, 2)) && on(st, {3, 4, 5, 6}))) return EXPM_E_HIP;
+    } else if (stage == -1 && tune.arrangement[opts->sel] == 1) {
+      // every sweep in turn on the caller's stream
+      if (!((tmax <= kRes6T || go(K_RES8, r8, 1, 1, 2)) && on(st, {3, 4, 5, 6}))) return EXPM_E_HIP;
     } else if (stage == -1) {
       std::lock_guard<std::mutex> lk(g_fj_mu);
       ForkJoin fj;
       if (!fork_join_for_device(&fj)) return EXPM_E_HIP;
       if (hipEventRecord(fj.fork, st) != hipSuccess || hipStreamWaitEvent(fj.side, fj.fork, 0) != hipSuccess)
         return EXPM_E_HIP;
-      // two chains side by side: np 144..256, 80..96 and 16 on the second stream; 112..128 then
-      // 32..64 on the caller's (the best of the arrangements measured)
-      const bool ok2 = on(fj.side, {3, 4, 6});
-      const bool ok1 = (tmax <= kRes6T || go(K_RES8, r8, 1, 1, 2)) && sub(5);
+      // two chains side by side; arrangement 0 (default, the best measured before tuning): np
+      // 144..256, 80..96 and 16 on the second stream, 112..128 then 32..64 on the caller's;
+      // 2: (144..256, 80..96) beside (112..128, 32..64, 16); 3: everything but 112..128 on the
+      // second stream
+      const int arr = tune.arrangement[opts->sel];
+      const bool ok2 = arr == 2 ? on(fj.side, {3, 4}) : arr == 3 ? on(fj.side, {3, 4, 5, 6}) : on(fj.side, {3, 4, 6});
+      const bool ok1 = (tmax <= kRes6T || go(K_RES8, r8, 1, 1, 2)) &&
+                       (arr == 2 ? (sub(5) && sub(6)) : arr == 3 ? true : sub(5));
       if (hipEventRecord(fj.join, fj.side) != hipSuccess || hipStreamWaitEvent(st, fj.join, 0) != hipSuccess)
         return EXPM_E_HIP;
       if (!ok1 || !ok2) return EXPM_E_HIP;
@@ -458,6 +491,7 @@ static expm_status_t run_large_call(const void *A, void *E, int64_t n, int64_t b
   c.m_out = m_dev;
   c.s_out = s_dev;
   c.status = status_dev;
+  c.tiles = tiles_per_launch(opts->prec);
   c.ws = ws;
   c.ws_bytes = ws_bytes;
   return run_large(c, (hipStream_t)stream);
@@ -586,6 +620,39 @@ expm_status_t expm_features(const void *A_dev, const int64_t *offsets_dev, const
   if (opts->dtype != EXPM_F64 || tiled_only(opts) || opts->flags || n_max > kFusedNMax) return EXPM_E_UNSUPPORTED;
   return run_fused(A_dev, nullptr, offsets_dev, n_dev, batch, 0, n_max, opts, u, m_dev, s_dev, nullptr, ws_dev,
                    ws_bytes, stream, 1, -1, features_dev);
+}
+
+expm_status_t expm_tune_set(const expm_tune_t *t) {
+  if (!t) return EXPM_E_INVALID_ARG;
+  for (int k = 0; k < 3; ++k)
+    if (t->arrangement[k] < 0 || t->arrangement[k] > 3) return EXPM_E_INVALID_ARG;
+  if (t->small_kernel < 0 || t->small_kernel > 2) return EXPM_E_INVALID_ARG;
+  for (int k = 0; k < 6; ++k)
+    if (t->per_cu[k] < 0 || t->per_cu[k] > 64) return EXPM_E_INVALID_ARG;
+  for (int k = 0; k < 4; ++k)
+    if (t->tiles_per_launch[k] < 0 || t->tiles_per_launch[k] > (1 << 20)) return EXPM_E_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune = *t;
+  return EXPM_OK;
+}
+
+expm_status_t expm_tune_get(expm_tune_t *t) {
+  if (!t) return EXPM_E_INVALID_ARG;
+  *t = tune_now();
+  return EXPM_OK;
+}
+
+expm_status_t expm_tune_limits(expm_tune_t *t) {
+  if (!t) return EXPM_E_INVALID_ARG;
+  memset(t, 0, sizeof(*t));
+  const FusedCaps c = fused_caps();
+  if (c.cus == 0) return EXPM_E_HIP;
+  t->arrangement[0] = t->arrangement[1] = t->arrangement[2] = 3;
+  t->small_kernel = 2;
+  t->per_cu[K_FUSED4] = c.per4; t->per_cu[K_FUSED8] = c.per8; t->per_cu[K_RES4] = c.res4;
+  t->per_cu[K_RES6] = c.res6; t->per_cu[K_RES8] = c.res8; t->per_cu[K_TINY] = c.tiny;
+  for (int k = 0; k < 4; ++k) t->tiles_per_launch[k] = kDefaultTiles;
+  return EXPM_OK;
 }
 
 size_t expm_mlp_scratch_bytes(int32_t batch) {
