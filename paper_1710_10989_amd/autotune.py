@@ -41,7 +41,7 @@ SELS = ("plain", "alpha", "learned")
 # uniform batch that exercises each sweep kernel: (real order, matrices); fused4 serves only the
 # learned selector's feature rows and is not timed
 KERNEL_CASE = {"fused8": (256, 512), "res4": (48, 4096), "splitrow": (96, 2048), "res8": (128, 2048),
-               "onewave": (16, 65536)}
+               "onewave": (16, 65536)}  # onewave: Gaussian entries, like the other cases
 
 
 def arch():
@@ -160,19 +160,30 @@ def tune(quick=False, log=print):
         entries["arrangement/16-128/fp64/%s" % sel] = {"choice": best, "ms": times}
         log("arrangement %s: %s -> %d" % (sel, times, best))
 
-    def run_b():
-        X.batched(B, workspace=ws, outs=outs)
+    del B, ws, outs
+
+    # order 16: one wavefront per matrix or the 4-wave kernel, on a uniform order-16 batch
+    # (the exponents of an exponential integrator: 65536 skew-symmetric matrices)
+    A16 = torch.from_numpy(W.small_skew_batch(count=65536 // scale, n=16)).cuda()
+    ws16 = torch.empty(X.workspace_bytes(16, A16.shape[0]), dtype=torch.uint8, device="cuda")
+    E16 = torch.empty_like(A16)
+    o16 = tuple(torch.empty(A16.shape[0], dtype=torch.int32, device="cuda") for _ in range(3))
+
+    def run_16():
+        X.batched_uniform(A16, workspace=ws16, out=E16, outs=o16)
 
     def set_small(t, v):
         t.small_kernel = v
-    best, times = _pick(cur, set_small, [1, 2], run_b, warm, reps)
-    entries["small_kernel/16/fp64/plain"] = {"choice": best, "ms": times}
+    best, times = _pick(cur, set_small, [1, 2], run_16, warm, reps)
+    entries["small_kernel/16/fp64/plain"] = {"choice": best, "ms": times, "matrices": int(A16.shape[0])}
     log("small_kernel: %s -> %d" % (times, best))
-    del B, ws, outs
+    del A16, ws16, E16, o16
 
     # persistent grid of each sweep kernel on a uniform batch of its order range
     g = np.random.default_rng(1710)
     for k, name in enumerate(KERNELS):
+        if name == "onewave" and cur.small_kernel == 2:
+            continue  # order 16 runs on the 4-wave kernel: the one-wave grid is never launched
         if name not in KERNEL_CASE or lim.per_cu[k] <= 1:
             if name in KERNEL_CASE:
                 entries["per_cu/%s/fp64/plain" % name] = {"choice": 0, "ms": {}}
@@ -202,7 +213,7 @@ def tune(quick=False, log=print):
     o3 = tuple(torch.empty(count, dtype=torch.int32, device="cuda") for _ in range(3))
     for pi, prec in enumerate(PRECS):
         times = {}
-        for v in (1024, 2048, 4096):
+        for v in (1024, 2048, 4096, 8192):
             cur.tiles_per_launch[pi] = v
             set_tune(cur)
             wsk = torch.empty(X.workspace_bytes(n, count, prec=prec), dtype=torch.uint8, device="cuda")

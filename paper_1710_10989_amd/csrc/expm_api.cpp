@@ -269,7 +269,8 @@ expm_status_t expm_select_rule(const double *norms, int32_t sel, double u, int32
 // real order 16 run the tiled path (the Pade comparison exists for real orders <= 16 only).
 static int64_t real_order(const expm_opts_t *o, int64_t n);
 static bool tiled_only(const expm_opts_t *o, int64_t n = 0) {
-  return o->prec != EXPM_PREC_FP64 || (o->flags & EXPM_FLAG_TRI) || ((o->flags & EXPM_FLAG_PS) && real_order(o, n) > 16);
+  return o->prec != EXPM_PREC_FP64 || (o->flags & EXPM_FLAG_TRI) ||
+         ((o->flags & (EXPM_FLAG_PS | EXPM_FLAG_PADE)) && real_order(o, n) > 16);
 }
 // Comparison methods on the fused kernels: FP64, plain rule, real order <= 16 (one wave per
 // matrix), Pade only for the two printed rows of u.
@@ -277,7 +278,7 @@ static expm_status_t method_check(const expm_opts_t *o, int64_t n, double u) {
   if (o->flags == 0) return EXPM_OK;
   if (o->flags == EXPM_FLAG_TRI) return o->dtype == EXPM_F64 ? EXPM_OK : EXPM_E_UNSUPPORTED;
   if (o->prec != EXPM_PREC_FP64 || o->sel != EXPM_SEL_PLAIN) return EXPM_E_UNSUPPORTED;
-  if ((o->flags & EXPM_FLAG_PADE) && (real_order(o, n) > 16 || (u != 0x1p-53 && u != 0x1p-24)))
+  if ((o->flags & EXPM_FLAG_PADE) && (real_order(o, n) > kPadeNpMax || (u != 0x1p-53 && u != 0x1p-24)))
     return EXPM_E_UNSUPPORTED;
   return EXPM_OK;
 }
@@ -487,6 +488,7 @@ static expm_status_t run_large_call(const void *A, void *E, int64_t n, int64_t b
   c.prec = opts->prec;  // expm_prec_t values match PREC_F64 / PREC_F32 / PREC_BF16X3
   c.select_only = select_only;
   c.ps = ps ? 1 : 0;
+  c.pade = (opts->flags & EXPM_FLAG_PADE) ? 1 : 0;
   c.tri = (opts->flags & EXPM_FLAG_TRI) ? 1 : 0;
   c.m_out = m_dev;
   c.s_out = s_dev;

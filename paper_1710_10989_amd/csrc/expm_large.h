@@ -10,13 +10,14 @@ namespace expm {
 constexpr int kLargeTile = 128;   // output tile of one workgroup
 constexpr int kLargeBufs = 8;     // n x n work buffers per matrix
 constexpr int kLargeRB = 64;      // rows per workgroup in the norm passes
+constexpr int kPadeNpMax = 2048;  // largest padded real order of the tiled Pade solve
 
 struct LargeLayout {
   int64_t n;        // order of the real matrix the method runs on (2 * input order if complex)
   int64_t np;       // n rounded up to kLargeTile
   int64_t group;    // matrices processed together
   int64_t nrb;      // row blocks of the norm passes
-  size_t bufs_off, partial_off, norms_off, flags_off, coef_off, list_off, shift_off, planes_off, total;
+  size_t bufs_off, partial_off, norms_off, flags_off, coef_off, list_off, shift_off, planes_off, piv_off, total;
 };
 
 // prec: expm_prec_t of the call (the reduced forms need room for operand planes); tiles:
@@ -33,6 +34,7 @@ struct LargeCall {
   int prec;           // PREC_F64 / PREC_F32 / PREC_BF16X3 for the reduced steps
   int select_only;
   int ps;             // Paterson-Stockmeyer comparison method (EXPM_FLAG_PS)
+  int pade;           // diagonal Pade comparison method (EXPM_FLAG_PADE), real order <= 2048
   int tri;            // triangular refinement (EXPM_FLAG_TRI)
   int tiles;          // output tiles per launch
   int32_t *m_out, *s_out, *status;  // device, one per matrix

@@ -68,6 +68,8 @@ struct LargeArgs {
   const int32_t *list;     // matrices (group-relative) of this launch
   int round;               // squaring round (1-based) for SEL_SQ*
   int ps;                  // Paterson-Stockmeyer comparison method
+  int pade;                // diagonal Pade comparison method (m = 2m' = 10 or 26)
+  int32_t *piv;            // per matrix: np row pivots of the Pade denominator's LU
   const int *flags;        // per matrix: bit 0 non-finite input, bit 1 not upper triangular
   int coff;                // first coefficient of this step in the matrix's 64
   void *planes;            // operand planes of reduced-precision products (2 PL np^2
@@ -82,7 +84,10 @@ struct LargeArgs {
 // Buffer of T.  Reduced sequences: 2 for m >= 8, else 3.  Paterson-Stockmeyer (A^2, A^3 in
 // 1, 2, A^4 in 3, Horner partial sums in 6 and 7): 3 with the base A^3, 5 with the base A^4,
 // so that neither operand of the last Horner step is its destination.
-__device__ inline int resolve_t(int m, int ps) {
+// Pade (r_10: V - U and V + U in 6, 7; r_26: in 4, 5): T is the numerator's buffer, which the
+// solve overwrites with r = (V - U)^-1 (V + U); the squarings alternate with the denominator's.
+__device__ inline int resolve_t(int m, int ps, int pade) {
+  if (pade) return m == 10 ? 7 : 5;
   if (ps && m >= 6) return ps_base(m) == 4 ? 5 : 3;
   return m >= 8 ? 2 : 3;
 }
@@ -92,7 +97,7 @@ __device__ inline int resolve_t(int m, int ps) {
 __device__ inline double *sel_ptr(const LargeArgs &a, int mi, int sel, int m, int s) {
   double *base = a.ws + (size_t)mi * a.mstride;
   int k = sel;
-  const int t = resolve_t(m, a.ps);
+  const int t = resolve_t(m, a.ps, a.pade);
   if (sel == SEL_T) k = t;
   else if (sel == SEL_TDST) { if (s == 0) return nullptr; k = t; }
   else if (sel == SEL_SQSRC) k = t ^ ((a.round - 1) & 1);
@@ -241,6 +246,18 @@ __global__ void lg_select_kernel(LargeArgs a, int count, int stride, const unsig
     return;
   }
   int m, s;
+  if (a.pade) {
+    // Sec. 2: r_10 or r_26, the cheaper with the solve costed 4/3 of a product (Table 1 theta);
+    // coefficients b_0 .. b_m' of p_m' (eq. eq.24)
+    select_pade(k.theta_pade, eta, &m, &s);
+    m_arr[gb] = m; s_arr[gb] = s;
+    if (status) status[gb] = EXPM_OK;
+    double *cf = coef + (size_t)mi * 64;
+    if (m == 10) for (int j = 0; j < 6; ++j) cf[j] = k.pade5[j];
+    else for (int j = 0; j < 14; ++j) cf[j] = k.pade13[j];
+    sh[0] = -s;
+    return;
+  }
   if (a.ps) {
     select_ps(k.theta_ps, eta, &m, &s);
     m_arr[gb] = m; s_arr[gb] = s;
@@ -408,7 +425,11 @@ __global__ __launch_bounds__(512, 1) void lg_gemm_lp_kernel(LargeArgs a) {
 // LC12.  Grid (np * np / (256 * 4), count).
 // LCPS: innermost Horner term of eq. poli9, F_(r-1) (+ a_16 A^4 for the base A^4), from the
 // coefficient block at coff.
-enum ElemKind { LC1 = 0, LC2 = 1, LC4W = 2, LC8W = 3, LC12 = 4, LCNAN = 5, LCPS = 6 };
+// LCPADE: the even and odd parts' inner sums of eq. eq.pade26 (r_26: W1 = b13 X^6 + b11 X^4 +
+// b9 X^2, Z1 = b7 X^6 + b5 X^4 + b3 X^2 + b1 I, W2 = b12 X^6 + b10 X^4 + b8 X^2, Z2 = b6 X^6 +
+// b4 X^4 + b2 X^2 + b0 I into 4, 5, 6, 7; r_10: W = b5 X^4 + b3 X^2 + b1 I, V = b4 X^4 + b2 X^2 +
+// b0 I into 4, 5) from X^2, X^4, X^6 in 1, 2, 3.  LCCOPY: dst = buffer in0.
+enum ElemKind { LC1 = 0, LC2 = 1, LC4W = 2, LC8W = 3, LC12 = 4, LCNAN = 5, LCPS = 6, LCPADE = 7, LCCOPY = 8 };
 
 __global__ __launch_bounds__(256) void lg_elem_kernel(LargeArgs a) {
   const int mi = a.list[blockIdx.y];
@@ -434,6 +455,20 @@ __global__ __launch_bounds__(256) void lg_elem_kernel(LargeArgs a) {
       case LC4W: gptr(sel_ptr(a, mi, 2, m, s))[e] = c[2] * id + c[3] * B0[e] + c[4] * B1[e]; break;
       case LC8W: gptr(sel_ptr(a, mi, 2, m, s))[e] = c[0] * B0[e] + c[1] * B1[e]; break;
       case LCNAN: put_dst(dst, dld, dnv, dcx, r, cc, __builtin_nan("")); break;
+      case LCCOPY: put_dst(dst, dld, dnv, dcx, r, cc, gptr(sel_ptr(a, mi, a.in0, m, s))[e]); break;
+      case LCPADE: {
+        const double x2 = B1[e], x4 = B2[e];
+        if (m == 10) {
+          gptr(sel_ptr(a, mi, 4, m, s))[e] = c[5] * x4 + c[3] * x2 + c[1] * id;
+          gptr(sel_ptr(a, mi, 5, m, s))[e] = c[4] * x4 + c[2] * x2 + c[0] * id;
+        } else {
+          const double x6 = gptr(sel_ptr(a, mi, 3, m, s))[e];
+          gptr(sel_ptr(a, mi, 4, m, s))[e] = c[13] * x6 + c[11] * x4 + c[9] * x2;
+          gptr(sel_ptr(a, mi, 5, m, s))[e] = c[7] * x6 + c[5] * x4 + c[3] * x2 + c[1] * id;
+          gptr(sel_ptr(a, mi, 6, m, s))[e] = c[12] * x6 + c[10] * x4 + c[8] * x2;
+          gptr(sel_ptr(a, mi, 7, m, s))[e] = c[6] * x6 + c[4] * x4 + c[2] * x2 + c[0] * id;
+        }
+      } break;
       case LCPS: {
         const double *k = c + a.coff;
         double t = k[0] * id + k[1] * B0[e] + k[2] * B1[e] + k[3] * B2[e];
@@ -448,6 +483,229 @@ __global__ __launch_bounds__(256) void lg_elem_kernel(LargeArgs a) {
       } break;
     }
   }
+}
+
+// ---- Pade comparison method: the solve (V - U) R = V + U (Sec. 2; an inverse costed as 4/3
+// of a product) by LU factorization with partial pivoting, in blocks of kLuNB columns.  The
+// right-hand side rides along as extra columns, so the factorization leaves L^-1 P (V + U) in
+// its place; back substitution with U then gives R there.  Steps per block k: the panel's LU
+// (one workgroup per matrix, the panel rows in registers), the panel's row swaps on every
+// other column, the unit-lower block solve of the block row, the trailing update by the MFMA
+// tile engine (K = kLuNB).  Then, blocks from the bottom: the upper block solve and the update
+// of the rows above.  The denominator lives in buffer 6 (r_10) or 4 (r_26), the numerator in
+// the next one.
+constexpr int kLuNB = 32;
+
+__device__ inline int lu_mbuf(int m) { return m == 10 ? 6 : 4; }
+
+// Panel: columns [k, k + 32) of rows [k, np); thread t holds rows t + 1024 q (q < RPT).
+// Pivot = largest |a| in the column (the smallest row on ties), as LAPACK's getf2.
+template <int RPT>
+__global__ __launch_bounds__(1024) void lg_lu_panel_kernel(LargeArgs a, int k) {
+  const int mi = a.list[blockIdx.x];
+  const int m = a.m_arr[a.g0 + mi];
+  const int np = a.np;
+  gdouble *M = gptr(a.ws + (size_t)mi * a.mstride + (size_t)lu_mbuf(m) * a.bstride);
+  int32_t *piv = a.piv + (size_t)mi * np;
+  __shared__ double rowA[kLuNB], rowB[kLuNB], wv[16];
+  __shared__ int wi[16], sp;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double v[RPT][kLuNB];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int i = tid + 1024 * q;
+#pragma unroll
+    for (int c = 0; c < kLuNB; ++c) v[q][c] = (i >= k && i < np) ? M[(size_t)i * np + k + c] : 0.0;
+  }
+#pragma clang loop unroll(full)
+  for (int j = 0; j < kLuNB; ++j) {
+    const int col = k + j;
+    double best = -1.0;
+    int bi = np;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int i = tid + 1024 * q;
+      const double x = fabs(v[q][j]);
+      if (i >= col && i < np && x > best) { best = x; bi = i; }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ob = __shfl_xor(best, o);
+      const int oi = __shfl_xor(bi, o);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    if (lane == 0) { wv[wave] = best; wi[wave] = bi; }
+    __syncthreads();
+    if (tid == 0) {
+      double b = wv[0];
+      int ii = wi[0];
+      for (int w = 1; w < 16; ++w)
+        if (wv[w] > b || (wv[w] == b && wi[w] < ii)) { b = wv[w]; ii = wi[w]; }
+      sp = ii;
+      piv[col] = ii;
+    }
+    __syncthreads();
+    const int p = sp;
+    // rows col and p trade places (their owners pass them through LDS)
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int i = tid + 1024 * q;
+      if (i == col) {
+#pragma unroll
+        for (int c = 0; c < kLuNB; ++c) rowA[c] = v[q][c];
+      }
+      if (i == p) {
+#pragma unroll
+        for (int c = 0; c < kLuNB; ++c) rowB[c] = v[q][c];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int i = tid + 1024 * q;
+      if (p != col && i == col) {
+#pragma unroll
+        for (int c = 0; c < kLuNB; ++c) v[q][c] = rowB[c];
+      }
+      if (p != col && i == p) {
+#pragma unroll
+        for (int c = 0; c < kLuNB; ++c) v[q][c] = rowA[c];
+      }
+    }
+    // rowB is the pivot row now at `col`: multipliers and the rank-1 update of the panel
+    const double d = rowB[j];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int i = tid + 1024 * q;
+      if (i > col && i < np) {
+        const double l = v[q][j] / d;
+        v[q][j] = l;
+#pragma unroll
+        for (int c = j + 1; c < kLuNB; ++c) v[q][c] -= l * rowB[c];
+      }
+    }
+    __syncthreads();  // rowA, rowB are rewritten by the next column
+  }
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int i = tid + 1024 * q;
+    if (i >= k && i < np)
+#pragma unroll
+      for (int c = 0; c < kLuNB; ++c) M[(size_t)i * np + k + c] = v[q][c];
+  }
+}
+
+// The panel's row swaps on every other column of the denominator and on the numerator.
+// Thread per column of the augmented [M | R]; grid (2 np / 256, count).
+__global__ __launch_bounds__(256) void lg_lu_swap_kernel(LargeArgs a, int k) {
+  const int mi = a.list[blockIdx.y];
+  const int m = a.m_arr[a.g0 + mi];
+  const int np = a.np;
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= 2 * np) return;
+  const int cc = c < np ? c : c - np;
+  if (c < np && cc >= k && cc < k + kLuNB) return;  // the panel swapped its own rows
+  gdouble *B = gptr(a.ws + (size_t)mi * a.mstride + (size_t)(lu_mbuf(m) + (c < np ? 0 : 1)) * a.bstride);
+  const int32_t *piv = a.piv + (size_t)mi * np;
+  for (int j = 0; j < kLuNB; ++j) {
+    const int p = piv[k + j];
+    if (p != k + j) {
+      const double t = B[(size_t)(k + j) * np + cc];
+      B[(size_t)(k + j) * np + cc] = B[(size_t)p * np + cc];
+      B[(size_t)p * np + cc] = t;
+    }
+  }
+}
+
+// Block row k of U and of L^-1 P R: x <- L11^-1 x for the columns right of the panel and every
+// numerator column (L11 unit lower, in LDS).  Thread per column; grid
+// (((np - k - 32) + np) / 256, count).
+__global__ __launch_bounds__(256) void lg_lu_fsub_kernel(LargeArgs a, int k) {
+  const int mi = a.list[blockIdx.y];
+  const int m = a.m_arr[a.g0 + mi];
+  const int np = a.np;
+  gdouble *M = gptr(a.ws + (size_t)mi * a.mstride + (size_t)lu_mbuf(m) * a.bstride);
+  __shared__ double Lk[kLuNB][kLuNB + 1];
+  for (int e = threadIdx.x; e < kLuNB * kLuNB; e += 256) Lk[e / kLuNB][e % kLuNB] = M[(size_t)(k + e / kLuNB) * np + k + e % kLuNB];
+  __syncthreads();
+  const int nm = np - k - kLuNB;
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= nm + np) return;
+  gdouble *B = c < nm ? M : gptr(a.ws + (size_t)mi * a.mstride + (size_t)(lu_mbuf(m) + 1) * a.bstride);
+  const int cc = c < nm ? k + kLuNB + c : c - nm;
+  double x[kLuNB];
+#pragma unroll
+  for (int i = 0; i < kLuNB; ++i) x[i] = B[(size_t)(k + i) * np + cc];
+#pragma unroll
+  for (int i = 1; i < kLuNB; ++i)
+#pragma unroll
+    for (int j = 0; j < i; ++j) x[i] -= Lk[i][j] * x[j];
+#pragma unroll
+  for (int i = 0; i < kLuNB; ++i) B[(size_t)(k + i) * np + cc] = x[i];
+}
+
+// Block row k of R: x <- U11^-1 x for every numerator column (U11 upper, in LDS).  Grid
+// (np / 256, count).
+__global__ __launch_bounds__(256) void lg_lu_bsub_kernel(LargeArgs a, int k) {
+  const int mi = a.list[blockIdx.y];
+  const int m = a.m_arr[a.g0 + mi];
+  const int np = a.np;
+  gdouble *M = gptr(a.ws + (size_t)mi * a.mstride + (size_t)lu_mbuf(m) * a.bstride);
+  gdouble *R = gptr(a.ws + (size_t)mi * a.mstride + (size_t)(lu_mbuf(m) + 1) * a.bstride);
+  __shared__ double Uk[kLuNB][kLuNB + 1];
+  for (int e = threadIdx.x; e < kLuNB * kLuNB; e += 256) Uk[e / kLuNB][e % kLuNB] = M[(size_t)(k + e / kLuNB) * np + k + e % kLuNB];
+  __syncthreads();
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= np) return;
+  double x[kLuNB];
+#pragma unroll
+  for (int i = 0; i < kLuNB; ++i) x[i] = R[(size_t)(k + i) * np + c];
+#pragma unroll
+  for (int i = kLuNB - 1; i >= 0; --i) {
+#pragma unroll
+    for (int j = i + 1; j < kLuNB; ++j) x[i] -= Uk[i][j] * x[j];
+    x[i] /= Uk[i][i];
+  }
+#pragma unroll
+  for (int i = 0; i < kLuNB; ++i) R[(size_t)(k + i) * np + c] = x[i];
+}
+
+// dst -= P Q with K = 32 on 128 x 128 tiles: P = columns [pcol, pcol + 32) of the denominator,
+// Q = rows [qrow, qrow + 32); output rows [r_lo, r_hi) of the denominator's columns
+// [mcol, np) (Q and dst the denominator) followed by every numerator column (Q and dst the
+// numerator).  Grid (row tiles x column tiles, count).
+__global__ __launch_bounds__(512, 1) void lg_lu_gemm_kernel(LargeArgs a, int pcol, int qrow, int r_lo, int r_hi,
+                                                           int mcol) {
+  const int mi = a.list[blockIdx.y];
+  const int m = a.m_arr[a.g0 + mi];
+  const int np = a.np;
+  double *M = a.ws + (size_t)mi * a.mstride + (size_t)lu_mbuf(m) * a.bstride;
+  double *R = M + a.bstride;
+  const int tcm = mcol < np ? (np - mcol + kLargeTile - 1) / kLargeTile : 0;
+  const int tcn = tcm + np / kLargeTile;
+  const int tm = blockIdx.x / tcn, tn = blockIdx.x - tm * tcn;
+  const int m0 = r_lo + tm * kLargeTile;
+  const bool inm = tn < tcm;
+  double *Qb = inm ? M : R;
+  const int n0 = inm ? mcol + tn * kLargeTile : (tn - tcm) * kLargeTile;
+  TileLds<LS> &L = *reinterpret_cast<TileLds<LS> *>(lds_pool<8>());
+  const int wave = threadIdx.x >> 6;
+  const int wr = wave / LS::WC, wc = wave % LS::WC;
+  const int wr_row = wr * LS::BR * 16, wc_col = wc * LS::BC * 16;
+  dbl4 acc[LS::TPW];
+  tile_gemm<LS>(gptr(M + pcol), np, gptr(Qb + (size_t)qrow * np), np, r_hi, np, kLuNB, m0, n0, L, true, wr_row,
+                wc_col, acc);
+  gdouble *D = gptr(Qb);
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < LS::BR; ++i)
+#pragma unroll
+    for (int j = 0; j < LS::BC; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wr_row + 16 * i + 4 * r + (lane >> 4), col = n0 + wc_col + 16 * j + (lane & 15);
+        if (row < r_hi && col < np) D[(size_t)row * np + col] -= acc[i * LS::BC + j][r];
+      }
 }
 
 }  // namespace
@@ -473,7 +731,8 @@ LargeLayout large_layout(int64_t n_real, int64_t batch, int prec, int tiles_per_
   // operand planes: BF16X3 2 x 3 bfloat16 planes per matrix, FP32 and FP32_ALL 2 float planes
   const size_t plane_bytes = prec == EXPM_PREC_BF16X3 ? 12 : prec == EXPM_PREC_FP64 ? 0 : 8;
   L.planes_off = align_up(L.shift_off + (size_t)g * 3 * sizeof(int32_t));
-  L.total = align_up(L.planes_off + (size_t)g * plane_bytes * nn);
+  L.piv_off = align_up(L.planes_off + (size_t)g * plane_bytes * nn);
+  L.total = align_up(L.piv_off + (size_t)g * L.np * sizeof(int32_t));
   return L;
 }
 
@@ -540,6 +799,37 @@ struct Launcher {
     if (hipGetLastError() != hipSuccess) ok = false;
   }
 
+  // the Pade solve of the listed matrices (their denominators and numerators in place)
+  void lu(const std::vector<int32_t> &idx, int slot) {
+    if (idx.empty() || !ok) return;
+    LargeArgs a = base;
+    a.list = upload(idx, slot);
+    const int np = (int)L.np;
+    const unsigned cnt = (unsigned)idx.size();
+    const int ct = np / kLargeTile;
+    for (int k = 0; k < np && ok; k += kLuNB) {
+      if (np <= 1024) hipLaunchKernelGGL(lg_lu_panel_kernel<1>, dim3(cnt), dim3(1024), 0, st, a, k);
+      else hipLaunchKernelGGL(lg_lu_panel_kernel<2>, dim3(cnt), dim3(1024), 0, st, a, k);
+      hipLaunchKernelGGL(lg_lu_swap_kernel, dim3((unsigned)((2 * np + 255) / 256), cnt), dim3(256), 0, st, a, k);
+      const int rest = np - k - kLuNB;
+      hipLaunchKernelGGL(lg_lu_fsub_kernel, dim3((unsigned)((rest + np + 255) / 256), cnt), dim3(256), 0, st, a, k);
+      if (rest > 0) {
+        const int rt = (rest + kLargeTile - 1) / kLargeTile;
+        hipLaunchKernelGGL(lg_lu_gemm_kernel, dim3((unsigned)(rt * (rt + ct)), cnt), dim3(512), 0, st, a, k, k,
+                           k + kLuNB, np, k + kLuNB);
+      }
+      if (hipGetLastError() != hipSuccess) ok = false;
+    }
+    for (int k = np - kLuNB; k >= 0 && ok; k -= kLuNB) {
+      hipLaunchKernelGGL(lg_lu_bsub_kernel, dim3((unsigned)((np + 255) / 256), cnt), dim3(256), 0, st, a, k);
+      if (k > 0) {
+        const int rt = (k + kLargeTile - 1) / kLargeTile;
+        hipLaunchKernelGGL(lg_lu_gemm_kernel, dim3((unsigned)(rt * ct), cnt), dim3(512), 0, st, a, k, k, 0, k, np);
+      }
+      if (hipGetLastError() != hipSuccess) ok = false;
+    }
+  }
+
   // triangular refinement of the iterate after squaring round `round` (0: T_m)
   void tri(const std::vector<int32_t> &idx, int slot, int round) {
     if (idx.empty() || !ok) return;
@@ -551,11 +841,11 @@ struct Launcher {
     if (hipGetLastError() != hipSuccess) ok = false;
   }
 
-  void elem(const std::vector<int32_t> &idx, int slot, int kind, int dst, int coff = 0) {
+  void elem(const std::vector<int32_t> &idx, int slot, int kind, int dst, int coff = 0, int in0 = SEL_NONE) {
     if (idx.empty() || !ok) return;
     LargeArgs a = base;
     a.list = upload(idx, slot);
-    a.kind = kind; a.dst = dst;
+    a.kind = kind; a.dst = dst; a.in0 = in0;
     a.coff = coff;
     const int64_t blocks = (L.np * L.np + 1023) / 1024;
     hipLaunchKernelGGL(lg_elem_kernel, dim3((unsigned)blocks, (unsigned)idx.size()), dim3(256), 0, st, a);
@@ -577,6 +867,7 @@ expm_status_t run_large(const LargeCall &c, hipStream_t st) {
   double *coef = (double *)(base + L.coef_off);
   int32_t *lists = (int32_t *)(base + L.list_off);
   int32_t *shift = (int32_t *)(base + L.shift_off);
+  int32_t *piv = (int32_t *)(base + L.piv_off);
 
   LargeArgs a;
   memset(&a, 0, sizeof(a));
@@ -589,6 +880,8 @@ expm_status_t run_large(const LargeCall &c, hipStream_t st) {
   a.m_arr = c.m_out; a.s_arr = c.s_out;
   a.coef = coef;
   a.ps = c.ps;
+  a.pade = c.pade;
+  a.piv = piv;
   a.flags = flags;
   a.shift = shift;
   a.planes = base + L.planes_off;
@@ -661,18 +954,39 @@ expm_status_t run_large(const LargeCall &c, hipStream_t st) {
     if (c.select_only) continue;
 
     // ---- powers (the alpha path formed them already) ----
-    std::vector<int32_t> l2, l3, l4, lm[19], lnan;
+    std::vector<int32_t> l2, l3, l4, lm[27], lnan, l0;
     int smax = 0;
     for (int i = 0; i < cnt; ++i) {
       const int m = mh[i];
       if (m < 1) { lnan.push_back(i); continue; }  // non-finite input
+      if (c.pade) {  // m = 2m' = 10 or 26
+        l2.push_back(i);
+        lm[m].push_back(i);
+        if (sh[i] == 0) l0.push_back(i);
+        smax = std::max(smax, (int)sh[i]);
+        continue;
+      }
       if (m >= 2) l2.push_back(i);
       if (m >= (c.ps ? 6 : 12)) l3.push_back(i);
       if (c.ps && m == 16) l4.push_back(i);
       lm[m].push_back(i);
       smax = std::max(smax, (int)sh[i]);
     }
-    if (c.sel != EXPM_SEL_ALPHA) {
+    if (c.pade) {
+      // eqs. eq.pade10 / eq.pade26: X^2, X^4 (and X^6 for r_26), the inner sums, then the odd
+      // part U by the last product, whose epilogue writes the denominator V - U and the
+      // numerator V + U; r_26 forms V = X^6 W2 + Z2 and Y = X^6 W1 + Z1 first (U = X Y)
+      run.gemm(l2, 0, EK_STORE, 0, 0, 1);
+      run.gemm(l2, 1, EK_STORE, 1, 1, 2);
+      run.gemm(lm[26], 2, EK_STORE, 2, 1, 3);
+      run.elem(l2, 3, LCPADE, SEL_NONE);
+      run.gemm(lm[10], 4, EK_PADE, 0, 4, SEL_NONE, 5, SEL_NONE, {6, 7});
+      run.gemm(lm[26], 5, EK_ADD1, 3, 4, 1, 5);
+      run.gemm(lm[26], 5, EK_ADD1, 3, 6, 2, 7);
+      run.gemm(lm[26], 5, EK_PADE, 0, 1, SEL_NONE, 2, SEL_NONE, {4, 5});
+      run.lu(l2, 6);
+      run.elem(l0, 7, LCCOPY, SEL_TDST, 0, SEL_T);  // no squaring: e^A = r itself
+    } else if (c.sel != EXPM_SEL_ALPHA) {
       run.gemm(l2, 0, EK_STORE, 0, 0, 1, SEL_NONE, SEL_NONE, {}, 0, true);
       run.gemm(l3, 1, EK_STORE, 1, 0, 2, SEL_NONE, SEL_NONE, {}, 0, true);
     }
@@ -681,7 +995,7 @@ expm_status_t run_large(const LargeCall &c, hipStream_t st) {
     std::vector<int32_t> lvalid;
     for (int i = 0; i < cnt; ++i)
       if (mh[i] >= 1) lvalid.push_back(i);
-    // ---- product stage per degree ----
+    // ---- product stage per degree (Pade: done above) ----
     run.elem(lm[1], 2, LC1, SEL_TDST);
     run.elem(lm[2], 3, LC2, SEL_TDST);
     run.elem(lm[4], 4, LC4W, 2);

@@ -33,7 +33,9 @@ enum EpiKind {
   EK_ADD1 = 4,    // dst = v + in0
   EK_SPLIT2 = 5,  // o0 = v + in0; o1 = o0 + in1
   EK_M18A = 6,    // o0..o4 = B_1..B_5 of the degree-18 sequence from (id, b0, b1, b2, v)
-  EK_PSH = 7      // dst = v + c0 id + c1 b0 + c2 b1 + c3 b2   (a Horner step of eq. poli9)
+  EK_PSH = 7,     // dst = v + c0 id + c1 b0 + c2 b1 + c3 b2   (a Horner step of eq. poli9)
+  EK_PADE = 8     // o0 = in0 - v, o1 = in0 + v: with v = U, in0 = V the denominator V - U and the
+                  // numerator V + U of the diagonal Pade approximant (eq. eq.pade26)
 };
 
 struct EpiDesc {
@@ -191,6 +193,14 @@ __device__ inline void run_epilogue(const double *cbuf, int row0, int col0, int 
       for_chunk<NW, 3>(cbuf, row0, col0, rows, cols, ldc, np, in, [&](int r, int cc, int, double v, const double *x) {
         const double t = v + (r == cc ? c0 : 0.0) + c1 * x[0] + c2 * x[1] + c3 * x[2];
         put_dst(dst, ld, nv, cx, r, cc, t);
+      });
+    } break;
+    case EK_PADE: {
+      gdouble *o0 = gptr(g_ep.o[0]), *o1 = gptr(g_ep.o[1]);
+      cgdouble *const in[1] = {gptr(g_ep.in0)};
+      for_chunk<NW, 1>(cbuf, row0, col0, rows, cols, ldc, np, in, [&](int, int, int e, double v, const double *x) {
+        o0[e] = x[0] - v;
+        o1[e] = x[0] + v;
       });
     } break;
     default: break;

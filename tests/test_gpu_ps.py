@@ -166,9 +166,76 @@ def test_comparisons_uniform_small_batch(P, orc):
 def test_pade_rejections(P):
     from paper_1710_10989_amd import _native as N
     g = np.random.default_rng(4)
-    with pytest.raises(N.ExpmError) as e:
-        P.taylor(dev(g.standard_normal((17, 17))), method="pade")
+    with pytest.raises(N.ExpmError) as e:  # the tiled solve covers real orders up to 2048
+        P.taylor(dev(g.standard_normal((2049, 2049))), method="pade")
     assert e.value.code == N.EXPM_E_UNSUPPORTED
     with pytest.raises(N.ExpmError) as e:
         P.taylor(dev(g.standard_normal((5, 5))), method="pade", u=2.0 ** -40)
     assert e.value.code == N.EXPM_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("n", [17, 48, 130, 300])
+@pytest.mark.parametrize("target,expect", [(0.1, (10, 0)), (1.0, (10, 2)), (4.0, (26, 0)), (100.0, (26, 5))])
+def test_pade_tiled_orders(P, orc, n, target, expect):
+    """Pade r_10 / r_26 above order 16 (the tiled path: products by the MFMA tile engine, the
+    solve by blocked LU with partial pivoting): (2m, s) equal the oracle's rule, e^A within
+    1e-12 of the direct Taylor oracle, and the method's own output (the oracle's r_2m(A / 2^s)
+    squared s times, from its definition with a long-double LU) within 64 u 2^s."""
+    if n == 300 and target in (0.1, 4.0):
+        pytest.skip("two norms suffice at n = 300")
+    g = np.random.default_rng(int(target * 100) + n)
+    A = g.standard_normal((n, n))
+    A *= target / np.abs(A).sum(0).max()
+    say("case pade tiled n=%d" % n, expect)
+    E, m, s, st = P.taylor(dev(A), method="pade")
+    torch.cuda.synchronize()
+    m, s = int(m.item()), int(s.item())
+    assert int(st.item()) == 0
+    assert (m, s) == expect == orc.select_pade(orc.norm1(A))
+    X = E.cpu().numpy()
+    ref, _ = orc.expm_taylor(A)
+    assert orc.rel_err_1(X, ref) <= TOL
+    own = orc.expm_pade(A, m, s)
+    assert orc.rel_err_1(X, own) <= max(TOL, 64 * 2.0 ** -53 * (1 << s))
+
+
+def test_pade_tiled_batch_and_complex(P, orc):
+    """A uniform batch of order 200 (several matrices per group, both degrees, structured
+    inputs) and a complex input (real form of order 2 x 40) through the tiled Pade path."""
+    from paper_1710_10989_amd import workloads as W
+    g = np.random.default_rng(200)
+    mats = [W.rescale(W.structured(g, 200, k), t) for k, t in
+            (("dense", 0.05), ("skew", 3.0), ("nilpotent", 30.0), ("diag_lowrank", 0.7), ("dense", 9.0))]
+    say("case pade tiled batch")
+    E, m, s, st = P.batched_uniform(dev(np.stack(mats)), method="pade")
+    torch.cuda.synchronize()
+    assert bool((st == 0).all())
+    for i, A in enumerate(mats):
+        assert (int(m[i]), int(s[i])) == orc.select_pade(orc.norm1(A))
+        ref, _ = orc.expm_taylor(A)
+        assert orc.rel_err_1(E[i].cpu().numpy(), ref) <= TOL, i
+    Z = (g.standard_normal((40, 40)) + 1j * g.standard_normal((40, 40))) / 10
+    say("case pade tiled complex")
+    Ez, mz, sz, stz = P.taylor(dev(Z), method="pade")
+    torch.cuda.synchronize()
+    assert int(stz.item()) == 0
+    ref, _ = orc.expm_taylor(Z)
+    assert orc.rel_err_1(Ez.cpu().numpy(), ref) <= TOL
+
+
+def test_pade_tiled_config_size(P, orc):
+    """One n = 1024 matrix of the precision workload by Pade r_26 against sampled columns of
+    the oracle's e^A (long-double series), 1e-12 per column."""
+    from paper_1710_10989_amd import workloads as W
+    A = W.large_dense(2, 1024, seed_stream=0)[1]
+    cols = [3, 500, 1000]
+    say("case pade n=1024")
+    E, m, s, st = P.taylor(dev(A), method="pade")
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    assert (int(m.item()), int(s.item())) == orc.select_pade(orc.norm1(A))
+    R = orc.expm_columns(A, cols)
+    X = E[:, cols].cpu().numpy()
+    err = float((np.abs(X - R).sum(0) / np.abs(R).sum(0)).max())
+    say("  (2m, s)=(%d, %d) sampled rel err %.2e" % (int(m.item()), int(s.item()), err))
+    assert err <= TOL
