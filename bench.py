@@ -181,7 +181,7 @@ def run_batched(args, torch, P, W):
     ms_k8 = sum(a.elapsed_time(b) for a, b in kev) / args.steps
     _, m, s, st = (x.cpu().numpy() for x in outs)
     assert np.all(st == 0), "non-ok status in the batch"
-    plain = plain_per_matrix(torch, P, B, mats, outs[0], m, s, args.plain_passes)
+    plain = plain_per_matrix(torch, P, B, mats, outs[0], m, s, args.plain_passes) if args.plain_passes > 0 else None
     ns = np.array([a.shape[0] for a in mats], dtype=np.float64)
     big = ((ns + 15) // 16) >= 7  # real orders handled by the 8-wave resident kernel (112..128)
     flops = executed_flops(m, s, ns)
@@ -201,7 +201,7 @@ def run_batched(args, torch, P, W):
     config["plain_fp64_form"] = plain
     value = nb / (ms_step * 1e-3)
     return line(args, "expm matrices/s (rel err <= 1e-12, FP64)", value, ms_step, "f64", config,
-                roof, cpu, vs_baseline=value / plain["value"])
+                roof, cpu, vs_baseline=value / plain["value"] if plain else None)
 
 
 def plain_per_matrix(torch, P, B, mats, E_batched, m_b, s_b, passes):
@@ -689,7 +689,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="ignore the autotuner's cache (library defaults)")
     ap.add_argument("--plain-passes", type=int, default=3,
-                    help="timed passes of the plain one-launch-per-matrix form (batched workload)")
+                    help="timed passes of the plain one-launch-per-matrix form (batched workload; 0: skip it)")
     args = ap.parse_args()
     fast = args.workload in ("batched", "small", "magnus")
     if args.steps is None:
