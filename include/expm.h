@@ -56,10 +56,15 @@ typedef enum {
   EXPM_E_UNSUPPORTED = 5
 } expm_status_t;
 
-/* Element type of A and e^A.  EXPM_C128 runs the method on the real form [[X, -Y], [Y, X]] of
- * A = X + iY (of order 2n): the map is an algebra homomorphism, so the real exponential of
- * the real form is the real form of e^A.  (m, s) are chosen from the 1-norm of the real form,
- * which lies between ||A||_1 and sqrt(2) ||A||_1. */
+/* Element type of A and e^A.  For EXPM_C128, (m, s) are chosen from the 1-norm of A itself
+ * (max over columns of sum_i |a_ij|, |z| the modulus) on every path.  Above complex order 128,
+ * in FP64 with the product-reduced Taylor method or Paterson-Stockmeyer, the method runs on
+ * complex matrices natively (planar real and imaginary parts, a complex product as four real
+ * products; the alpha rule reads the complex norms of the powers).  Up to order 128, and for
+ * the reduced-precision forms and Pade, it runs on the real form [[X, -Y], [Y, X]] of
+ * A = X + iY (of order 2n): the map is an algebra homomorphism, so the real exponential of the
+ * real form is the real form of e^A; there the alpha rule reads the real form's norms of the
+ * powers, which bound the complex ones from above (within a factor sqrt(2)). */
 typedef enum { EXPM_F64 = 0, EXPM_C128 = 1 } expm_dtype_t;
 
 /* Arithmetic of the polynomial products.  In the reduced forms the powers A^2, A^3 (A^6) and

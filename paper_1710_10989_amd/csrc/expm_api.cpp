@@ -283,15 +283,25 @@ static expm_status_t method_check(const expm_opts_t *o, int64_t n, double u) {
   return EXPM_OK;
 }
 
-// Order of the real matrix the method runs on: complex inputs use their real form.
+// Order of the real matrix the method runs on: complex inputs use their real form (except on
+// the tiled path's native complex route, which keeps the complex order; see native_complex).
 static int64_t real_order(const expm_opts_t *o, int64_t n) { return o->dtype == EXPM_C128 ? 2 * n : n; }
+
+// Complex inputs on the tiled path run natively (planar real and imaginary buffers, a complex
+// product as four real MFMA products, (m, s) from the complex 1-norm) in FP64 with the
+// product-reduced Taylor method or Paterson-Stockmeyer; the reduced-precision forms and Pade
+// run on the real form.
+static bool native_complex(const expm_opts_t *o) {
+  return o->dtype == EXPM_C128 && o->prec == EXPM_PREC_FP64 && !(o->flags & EXPM_FLAG_PADE);
+}
 
 size_t expm_workspace_bytes(int64_t n_max, int64_t batch, const expm_opts_t *opts) {
   double u;
   if (n_max < 1 || batch < 1 || check_opts(opts, &u) != EXPM_OK) return 0;
   const int64_t nr = real_order(opts, n_max);
   if (nr <= kFusedNMax && !tiled_only(opts, n_max)) return fused_layout(nr, batch).total;
-  return large_layout(nr, batch, opts->prec, tiles_per_launch(opts->prec)).total;
+  if (native_complex(opts)) return large_layout(n_max, batch, opts->prec, tiles_per_launch(opts->prec), 2).total;
+  return large_layout(nr, batch, opts->prec, tiles_per_launch(opts->prec), 1).total;
 }
 
 // stage: -1 all phases; 0 sort the batch into the work queue; 1 sweep of the 8-wave resident
@@ -482,7 +492,7 @@ static expm_status_t run_large_call(const void *A, void *E, int64_t n, int64_t b
   c.A = (const double *)A;
   c.E = (double *)E;
   c.nin = n;
-  c.cplx = opts->dtype == EXPM_C128;
+  c.cplx = opts->dtype != EXPM_C128 ? 0 : native_complex(opts) ? 2 : 1;
   c.batch = batch;
   c.sel = opts->sel == EXPM_SEL_LEARNED ? EXPM_SEL_ALPHA : opts->sel;
   c.prec = opts->prec;  // expm_prec_t values match PREC_F64 / PREC_F32 / PREC_BF16X3

@@ -203,7 +203,10 @@ __device__ void for_each_elem(int np, const double *const (&inp)[NIN], const F &
 // One GEMM step: thread 0 fills the LDS descriptor through `set`, then all threads run it.
 template <int NW, class S>
 __device__ void gemm_step(const S &set) {
-  if (threadIdx.x == 0) set(g_ep);
+  if (threadIdx.x == 0) {
+    g_ep.idw = 1.0;
+    set(g_ep);
+  }
   __syncthreads();
   gemm_block<NW>();
   __syncthreads();
@@ -271,6 +274,11 @@ __device__ void run_one(const FusedArgs &a, int64_t b, double *slot, double *red
         colsum += fabs(v[u]);
         B0g[(i + u) * np + tid] = v[u];
       }
+    }
+    if (cx) {  // complex input: the 1-norm of A itself, sum_i |z_ij|
+      colsum = 0.0;
+      if (tid < nin)
+        for (int r = 0; r < nin; ++r) colsum += hypot(Ag[2 * ((size_t)r * nin + tid)], Ag[2 * ((size_t)r * nin + tid) + 1]);
     }
   }
   bad = __syncthreads_or(bad);

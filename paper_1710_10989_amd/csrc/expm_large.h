@@ -22,13 +22,15 @@ struct LargeLayout {
 
 // prec: expm_prec_t of the call (the reduced forms need room for operand planes); tiles:
 // output tiles per launch (the group holds about that many tiles' worth of matrices).
-LargeLayout large_layout(int64_t n_real, int64_t batch, int prec, int tiles);
+// planes: 2 for the native complex path (every buffer holds a real and an imaginary plane).
+LargeLayout large_layout(int64_t n_real, int64_t batch, int prec, int tiles, int planes);
 
 struct LargeCall {
   const double *A;    // first input; matrix b at A + b * in_stride doubles
   double *E;          // first output, same layout
   int64_t nin;        // input order (complex or real)
-  int cplx;           // interleaved complex input / output, run on the real form
+  int cplx;           // interleaved complex input / output: 1 run on the real form (order 2 nin),
+                      // 2 native complex (planar buffers, four real products per product)
   int64_t batch;
   int sel;            // EXPM_SEL_PLAIN or EXPM_SEL_ALPHA
   int prec;           // PREC_F64 / PREC_F32 / PREC_BF16X3 for the reduced steps

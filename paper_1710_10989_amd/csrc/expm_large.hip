@@ -131,7 +131,9 @@ __global__ __launch_bounds__(256) void lg_load_kernel(LargeArgs a, double *parti
       const int r = r0 + u;
       double x = 0.0;
       if (r < n && col < n) {
-        if (!cx) {
+        if (cx == 2) {  // native complex: the real part here, the imaginary one below
+          x = A[2 * ((size_t)r * n + col)];
+        } else if (!cx) {
           x = A[(size_t)r * n + col];
         } else {
           const int ri = r < nin ? r : r - nin, ci = col < nin ? col : col - nin;
@@ -141,6 +143,19 @@ __global__ __launch_bounds__(256) void lg_load_kernel(LargeArgs a, double *parti
         }
       }
       v[u] = x;
+    }
+    if (cx == 2) {
+      const size_t nn = (size_t)np * np;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int r = r0 + u;
+        const double y = (r < n && col < n) ? A[2 * ((size_t)r * n + col) + 1] : 0.0;
+        bad |= !isfinite(v[u]) || !isfinite(y);
+        acc += hypot(v[u], y);  // |z| (a-1: the 1-norm of the complex matrix)
+        B0[(size_t)r * np + col] = v[u];
+        B0[nn + (size_t)r * np + col] = y;
+      }
+      continue;
     }
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
@@ -194,12 +209,18 @@ __global__ __launch_bounds__(256) void lg_colsum_kernel(LargeArgs a, int sel, do
   const int mi = a.list[blockIdx.z];
   cgdouble *B = gptr(a.ws + (size_t)mi * a.mstride + (size_t)sel * a.bstride);
   double acc = 0.0;
+  const size_t nn = (size_t)a.np * a.np;
   for (int r0 = rb * kLargeRB; r0 < (rb + 1) * kLargeRB; r0 += 16) {
     double v[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) v[u] = B[(size_t)(r0 + u) * a.np + col];
+    if (a.cplx == 2) {
 #pragma unroll
-    for (int u = 0; u < 16; ++u) acc += fabs(v[u]);
+      for (int u = 0; u < 16; ++u) acc += hypot(v[u], B[nn + (size_t)(r0 + u) * a.np + col]);
+    } else {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc += fabs(v[u]);
+    }
   }
   partial[((size_t)mi * nrb + rb) * a.np + col] = acc;
 }
@@ -286,7 +307,7 @@ __global__ void lg_select_kernel(LargeArgs a, int count, int stride, const unsig
 // Grid (np * np / 1024, count).
 __global__ __launch_bounds__(256) void lg_rescale_kernel(LargeArgs a, int nbuf) {
   const int mi = blockIdx.y;
-  const int64_t total = (int64_t)a.np * a.np;
+  const int64_t total = (int64_t)a.np * a.np * (a.cplx == 2 ? 2 : 1);
   for (int k = 0; k < nbuf; ++k) {
     const int e2 = a.shift[3 * mi + k];
     if (e2 == 0) continue;
@@ -313,12 +334,30 @@ __device__ inline void fill_desc(const LargeArgs &a, int mi, int64_t gb, int m, 
   } else {
     d.dst = a.E + gb * a.io_stride; d.dst_ld = a.n; d.dst_nvalid = a.nin; d.cplx = a.cplx;
   }
+  d.idw = 1.0;
   d.kind = a.kind;
   d.np = a.np;
   for (int i = 0; i < 64; ++i) d.c[i] = i + a.coff < 64 ? a.coef[(size_t)mi * 64 + a.coff + i] : 0.0;
 }
 
-// One 128 x 128 output tile of an FP64 GEMM step for matrix list[blockIdx.y].
+// Native complex steps (cplx == 2): every buffer holds the real plane and then the imaginary
+// one (nn elements apart).  After the real plane's epilogue thread 0 points the descriptor at
+// the imaginary planes: inputs and outputs move by nn (the output matrix e^A by one double, to
+// the imaginary members), and the identity terms drop out (real coefficients).
+__device__ inline void desc_to_imag(size_t nn) {
+  EpiDesc &d = g_ep;
+  d.b0 += nn; d.b1 += nn; d.b2 += nn;
+  if (d.in0) d.in0 += nn;
+  if (d.in1) d.in1 += nn;
+  for (int j = 0; j < 5; ++j)
+    if (d.o[j]) d.o[j] += nn;
+  d.dst += d.cplx == 2 ? 1 : nn;
+  d.idw = 0.0;
+}
+
+// One 128 x 128 output tile of an FP64 GEMM step for matrix list[blockIdx.y].  Native
+// complex: the real plane of the tile from two real products (Re P Re Q - Im P Im Q) and its
+// epilogue, then the imaginary plane (Re P Im Q + Im P Re Q) and its epilogue.
 template <int PREC>
 __global__ __launch_bounds__(512, 1) void lg_gemm_kernel(LargeArgs a) {
   const int mi = a.list[blockIdx.y];
@@ -334,17 +373,35 @@ __global__ __launch_bounds__(512, 1) void lg_gemm_kernel(LargeArgs a) {
   const int wr_row = wr * LS::BR * 16, wc_col = wc * LS::BC * 16;
   const int m0 = tm * kLargeTile, n0 = tn * kLargeTile;
   typename AccOf<PREC>::T acc[LS::TPW];
-  tile_gemm<LS, PREC>(gptr(g_ep.P), a.np, gptr(g_ep.Q), a.np, a.np, a.np, a.np, m0, n0, L, true, wr_row, wc_col,
-                      acc);
-  if (a.kind == EK_STORE) {
-    store_acc<LS, PREC>(acc, m0 + wr_row, n0 + wc_col);
+  double *cbuf = lds_pool<8>();
+  auto finish = [&]() {
+    if (a.kind == EK_STORE) {
+      store_acc<LS, PREC>(acc, m0 + wr_row, n0 + wc_col);
+      return;
+    }
+    __syncthreads();
+    stage_acc<LS, LDC_L, PREC>(cbuf, acc, wr_row, wc_col);
+    __syncthreads();
+    run_epilogue<8>(cbuf, m0, n0, kLargeTile, kLargeTile, LDC_L);
+  };
+  cgdouble *P = gptr(g_ep.P), *Q = gptr(g_ep.Q);
+  if (a.cplx != 2) {
+    tile_gemm<LS, PREC>(P, a.np, Q, a.np, a.np, a.np, a.np, m0, n0, L, true, wr_row, wc_col, acc);
+    finish();
     return;
   }
+  const size_t nn = (size_t)a.np * a.np;
+  tile_gemm<LS, PREC>(P, a.np, Q, a.np, a.np, a.np, a.np, m0, n0, L, true, wr_row, wc_col, acc);
   __syncthreads();
-  double *cbuf = lds_pool<8>();
-  stage_acc<LS, LDC_L, PREC>(cbuf, acc, wr_row, wc_col);
+  tile_gemm<LS, PREC, true, true>(P + nn, a.np, Q + nn, a.np, a.np, a.np, a.np, m0, n0, L, true, wr_row, wc_col, acc);
+  finish();
   __syncthreads();
-  run_epilogue<8>(cbuf, m0, n0, kLargeTile, kLargeTile, LDC_L);
+  if (threadIdx.x == 0) desc_to_imag(nn);
+  __syncthreads();
+  tile_gemm<LS, PREC>(P, a.np, Q + nn, a.np, a.np, a.np, a.np, m0, n0, L, true, wr_row, wc_col, acc);
+  __syncthreads();
+  tile_gemm<LS, PREC, true>(P + nn, a.np, Q, a.np, a.np, a.np, a.np, m0, n0, L, true, wr_row, wc_col, acc);
+  finish();
 }
 
 // Operand planes of a reduced-precision product (tile_gemm_lp): the FP64 buffer `sel` of each
@@ -440,15 +497,20 @@ __global__ __launch_bounds__(256) void lg_elem_kernel(LargeArgs a) {
   cgdouble *B1 = gptr(sel_ptr(a, mi, 1, m, s));
   cgdouble *B2 = gptr(sel_ptr(a, mi, 2, m, s));
   double *dstp = a.kind == LCNAN ? nullptr : sel_ptr(a, mi, a.dst, m, s);
-  gdouble *dst = dstp ? gptr(dstp) : gptr(a.E + gb * a.io_stride);
+  gdouble *dst0 = dstp ? gptr(dstp) : gptr(a.E + gb * a.io_stride);
   const int dld = dstp ? a.np : a.n, dnv = dstp ? a.np : a.nin, dcx = dstp ? 0 : a.cplx;
   const int np = a.np;
-  const int64_t total = (int64_t)np * np;
+  // native complex: the elements of the imaginary planes follow those of the real ones (no
+  // identity there); e indexes the buffers directly either way
+  const int64_t nn = (int64_t)np * np, total = nn * (a.cplx == 2 ? 2 : 1);
   for (int u = 0; u < 4; ++u) {
     const int64_t e = ((int64_t)blockIdx.x * 4 + u) * 256 + threadIdx.x;
     if (e >= total) break;
-    const int r = (int)(e / np), cc = (int)(e - (int64_t)r * np);
-    const double id = (r == cc) ? 1.0 : 0.0;
+    const bool im = e >= nn;
+    const int64_t e1 = im ? e - nn : e;
+    const int r = (int)(e1 / np), cc = (int)(e1 - (int64_t)r * np);
+    const double id = (r == cc && !im) ? 1.0 : 0.0;
+    gdouble *dst = dst0 + (im ? (dstp ? nn : 1) : 0);
     switch (a.kind) {
       case LC1: put_dst(dst, dld, dnv, dcx, r, cc, id + c[0] * B0[e]); break;
       case LC2: put_dst(dst, dld, dnv, dcx, r, cc, id + c[0] * B0[e] + c[1] * B1[e]); break;
@@ -710,7 +772,7 @@ __global__ __launch_bounds__(512, 1) void lg_lu_gemm_kernel(LargeArgs a, int pco
 
 }  // namespace
 
-LargeLayout large_layout(int64_t n_real, int64_t batch, int prec, int tiles_per_launch) {
+LargeLayout large_layout(int64_t n_real, int64_t batch, int prec, int tiles_per_launch, int planes) {
   LargeLayout L;
   L.n = n_real;
   L.np = (n_real + kLargeTile - 1) / kLargeTile * kLargeTile;
@@ -722,7 +784,7 @@ LargeLayout large_layout(int64_t n_real, int64_t batch, int prec, int tiles_per_
   L.nrb = L.np / kLargeRB;
   const size_t nn = (size_t)L.np * L.np;
   L.bufs_off = 0;
-  L.partial_off = align_up(L.bufs_off + (size_t)g * kLargeBufs * nn * sizeof(double));
+  L.partial_off = align_up(L.bufs_off + (size_t)g * kLargeBufs * planes * nn * sizeof(double));
   L.norms_off = align_up(L.partial_off + (size_t)g * L.nrb * L.np * sizeof(double));
   L.flags_off = align_up(L.norms_off + (size_t)3 * g * sizeof(unsigned long long));
   L.coef_off = align_up(L.flags_off + (size_t)g * sizeof(int));
@@ -847,7 +909,7 @@ struct Launcher {
     a.list = upload(idx, slot);
     a.kind = kind; a.dst = dst; a.in0 = in0;
     a.coff = coff;
-    const int64_t blocks = (L.np * L.np + 1023) / 1024;
+    const int64_t blocks = (L.np * L.np * (c.cplx == 2 ? 2 : 1) + 1023) / 1024;
     hipLaunchKernelGGL(lg_elem_kernel, dim3((unsigned)blocks, (unsigned)idx.size()), dim3(256), 0, st, a);
     if (hipGetLastError() != hipSuccess) ok = false;
   }
@@ -856,8 +918,11 @@ struct Launcher {
 }  // namespace
 
 expm_status_t run_large(const LargeCall &c, hipStream_t st) {
-  const int64_t n = c.cplx ? 2 * c.nin : c.nin;
-  LargeLayout L = large_layout(n, c.batch, c.prec, c.tiles);
+  // real order the kernels run on: the real form for cplx == 1; the complex order itself for
+  // the native complex path (cplx == 2, two planes per buffer)
+  const int64_t n = c.cplx == 1 ? 2 * c.nin : c.nin;
+  const int planes = c.cplx == 2 ? 2 : 1;
+  LargeLayout L = large_layout(n, c.batch, c.prec, c.tiles, planes);
   if (!c.ws || c.ws_bytes < L.total) return EXPM_E_WORKSPACE;
   char *base = (char *)c.ws;
   double *bufs = (double *)(base + L.bufs_off);
@@ -872,7 +937,7 @@ expm_status_t run_large(const LargeCall &c, hipStream_t st) {
   LargeArgs a;
   memset(&a, 0, sizeof(a));
   a.ws = bufs;
-  a.bstride = (size_t)L.np * L.np;
+  a.bstride = (size_t)L.np * L.np * planes;
   a.mstride = kLargeBufs * a.bstride;
   a.np = (int)L.np; a.n = (int)n; a.nin = (int)c.nin; a.cplx = c.cplx;
   a.A = c.A; a.E = c.E;
@@ -886,7 +951,7 @@ expm_status_t run_large(const LargeCall &c, hipStream_t st) {
   a.shift = shift;
   a.planes = base + L.planes_off;
   for (int j = 0; j < 5; ++j) a.o[j] = SEL_NONE;
-  const unsigned rs_blocks = (unsigned)((L.np * L.np + 1023) / 1024);
+  const unsigned rs_blocks = (unsigned)((L.np * L.np * (c.cplx == 2 ? 2 : 1) + 1023) / 1024);
 
   std::vector<int32_t> mh, sh;
   for (int64_t g0 = 0; g0 < c.batch; g0 += L.group) {

@@ -100,6 +100,19 @@ __device__ inline double t_norm1(const q4 &x) {
   return tuni(s);
 }
 
+// 1-norm of an interleaved complex nin x nin matrix (nin <= 8), sum_i |z_ij| maximised over the
+// columns j: lane j < nin sums its column.
+__device__ inline double t_norm1_z(const double *A, int nin) {
+  cgdouble *Ag = gptr(A);
+  const int l = lane_id();
+  double s = 0.0;
+  if (l < nin)
+    for (int r = 0; r < nin; ++r) s += hypot(Ag[2 * (r * nin + l)], Ag[2 * (r * nin + l) + 1]);
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) s = fmax(s, __shfl_xor(s, o));
+  return tuni(s);
+}
+
 // Loads matrix (n x n real, or the real form [[X, -Y], [Y, X]] of an nin x nin interleaved
 // complex matrix, n = 2 nin) zero-padded to 16 x 16.
 __device__ inline void t_load(const double *A, int n, int nin, int cx, const TLane &ln, q4 &x) {
@@ -628,7 +641,8 @@ __global__ __launch_bounds__(64 * kTinyW, SEL == EXPM_SEL_PLAIN ? 4 : 2) void ex
         if (a.status) a.status[b] = (nin < 1 || n > a.np_max) ? EXPM_E_INVALID_ARG : EXPM_E_UNSUPPORTED;
       }
     } else if (__any(!isfinite(Xc[0]) || !isfinite(Xc[1]) || !isfinite(Xc[2]) || !isfinite(Xc[3])) ||
-               !((eta = t_norm1(Xc)) <= __DBL_MAX__)) {  // (a 1-norm that overflows is refused likewise)
+               !((eta = cx ? t_norm1_z(a.A + off, nin) : t_norm1(Xc)) <= __DBL_MAX__)) {
+      // (a 1-norm that overflows is refused likewise; a complex input's is that of A itself)
       if (a.E)
         for (int e = lane_id(); e < nin * nin * (cx ? 2 : 1); e += 64) a.E[off + e] = __builtin_nan("");
       if (head) {

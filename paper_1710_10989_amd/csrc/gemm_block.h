@@ -44,8 +44,11 @@ struct EpiDesc {
   double *o[5];
   double *dst;
   int kind, np, dst_ld, dst_nvalid;
-  int cplx;  // dst is an interleaved complex n x n matrix (n = dst_nvalid) holding the
-             // realified result: rows 0..n-1 carry the real part, rows n..2n-1 the imaginary
+  int cplx;  // 1: dst is an interleaved complex n x n matrix (n = dst_nvalid) holding the
+             // realified result: rows 0..n-1 carry the real part, rows n..2n-1 the imaginary;
+             // 2: dst points at the real or imaginary member of an interleaved complex n x n
+             // matrix, and the result is that part (a plane of the native complex path)
+  double idw;  // weight of the identity terms (1; 0 for the imaginary plane of a complex step)
   double c[64];
 };
 
@@ -55,6 +58,8 @@ struct EpiDesc {
 __device__ inline void put_dst(gdouble *dst, int ld, int nv, int cplx, int r, int c, double v) {
   if (!cplx) {
     if (r < nv && c < nv) dst[r * ld + c] = v;
+  } else if (cplx == 2) {
+    if (r < nv && c < nv) dst[2 * (r * nv + c)] = v;
   } else if (c < nv) {
     if (r < nv) dst[2 * (r * nv + c)] = v;
     else if (r < 2 * nv) dst[2 * ((r - nv) * nv + c) + 1] = v;
@@ -119,6 +124,7 @@ template <int NW>
 __device__ inline void run_epilogue(const double *cbuf, int row0, int col0, int rows, int cols, int ldc) {
   const int np = g_ep.np;
   const double *c = g_ep.c;
+  const double idw = g_ep.idw;
   switch (g_ep.kind) {
     case EK_M4: {
       gdouble *dst = gptr(g_ep.dst);
@@ -126,7 +132,7 @@ __device__ inline void run_epilogue(const double *cbuf, int row0, int col0, int 
       const double c0 = c[0], c1 = c[1];
       cgdouble *const in[1] = {gptr(g_ep.b0)};
       for_chunk<NW, 1>(cbuf, row0, col0, rows, cols, ldc, np, in, [&](int r, int cc, int, double v, const double *x) {
-        const double t = (r == cc ? 1.0 : 0.0) + c0 * x[0] + c1 * v;
+        const double t = (r == cc ? idw : 0.0) + c0 * x[0] + c1 * v;
         put_dst(dst, ld, nv, cx, r, cc, t);
       });
     } break;
@@ -137,7 +143,7 @@ __device__ inline void run_epilogue(const double *cbuf, int row0, int col0, int 
       for_chunk<NW, 2>(cbuf, row0, col0, rows, cols, ldc, np, in, [&](int r, int cc, int e, double v, const double *x) {
         const double a4 = c2 * v;
         o0[e] = c3 * x[1] + a4;
-        o1[e] = (r == cc ? c4 : 0.0) + c5 * x[0] + c6 * x[1] + c7 * a4;
+        o1[e] = (r == cc ? c4 * idw : 0.0) + c5 * x[0] + c6 * x[1] + c7 * a4;
       });
     } break;
     case EK_M8B: {
@@ -146,7 +152,7 @@ __device__ inline void run_epilogue(const double *cbuf, int row0, int col0, int 
       const double c8 = c[8], c9 = c[9], c10 = c[10];
       cgdouble *const in[2] = {gptr(g_ep.b0), gptr(g_ep.b1)};
       for_chunk<NW, 2>(cbuf, row0, col0, rows, cols, ldc, np, in, [&](int r, int cc, int, double v, const double *x) {
-        const double t = v + (r == cc ? c8 : 0.0) + c9 * x[0] + c10 * x[1];
+        const double t = v + (r == cc ? c8 * idw : 0.0) + c9 * x[0] + c10 * x[1];
         put_dst(dst, ld, nv, cx, r, cc, t);
       });
     } break;
@@ -176,7 +182,7 @@ __device__ inline void run_epilogue(const double *cbuf, int row0, int col0, int 
       for (int i = 0; i < 24; ++i) k[i] = c[i];
       cgdouble *const in[3] = {gptr(g_ep.b0), gptr(g_ep.b1), gptr(g_ep.b2)};
       for_chunk<NW, 3>(cbuf, row0, col0, rows, cols, ldc, np, in, [&](int r, int cc, int e, double v, const double *x) {
-        const double id = (r == cc) ? 1.0 : 0.0;
+        const double id = (r == cc) ? idw : 0.0;
         const double x1 = x[0], x2 = x[1], x3 = x[2];
         o0[e] = k[0] * id + k[1] * x1 + k[2] * x2 + k[3] * x3;
         o1[e] = k[4] * id + k[5] * x1 + k[6] * x2 + k[7] * x3 + k[8] * v;
@@ -191,7 +197,7 @@ __device__ inline void run_epilogue(const double *cbuf, int row0, int col0, int 
       const double c0 = c[0], c1 = c[1], c2 = c[2], c3 = c[3];
       cgdouble *const in[3] = {gptr(g_ep.b0), gptr(g_ep.b1), gptr(g_ep.b2)};
       for_chunk<NW, 3>(cbuf, row0, col0, rows, cols, ldc, np, in, [&](int r, int cc, int, double v, const double *x) {
-        const double t = v + (r == cc ? c0 : 0.0) + c1 * x[0] + c2 * x[1] + c3 * x[2];
+        const double t = v + (r == cc ? c0 * idw : 0.0) + c1 * x[0] + c2 * x[1] + c3 * x[2];
         put_dst(dst, ld, nv, cx, r, cc, t);
       });
     } break;

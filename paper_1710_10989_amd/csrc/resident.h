@@ -385,6 +385,18 @@ __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, i
         bad |= !isfinite(X0[i][r]);
         csum += fabs(X0[i][r]);
       }
+    if (cx) {
+      // complex input: the 1-norm of A itself, sum_i |z_ij| over the columns of the X block
+      // (which holds the real parts; the imaginary parts are read beside them)
+      csum = 0.0;
+#pragma unroll
+      for (int i = 0; i < T; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * i + 4 * r + lk;
+          if (row < nin && c < nin) csum += hypot(X0[i][r], Ag[2 * ((size_t)row * nin + c) + 1]);
+        }
+    }
     csum += __shfl_xor(csum, 16);
     csum += __shfl_xor(csum, 32);
   }

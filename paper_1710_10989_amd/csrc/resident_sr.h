@@ -173,6 +173,17 @@ __device__ void run_sr(const FusedArgs &a, int64_t b, int n, int nin, int cx, in
         bad |= !isfinite(x);
         csum += fabs(x);
       }
+    if (cx) {
+      // complex input: the 1-norm of A itself, sum_i |z_ij| over the columns of the X block
+      csum = 0.0;
+#pragma unroll
+      for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * (G::I0 + i) + 4 * r + lk;
+          if (row < nin && c < nin) csum += hypot(X0[i][r], Ag[2 * ((size_t)row * nin + c) + 1]);
+        }
+    }
   }
   bad = ufi(__syncthreads_or(bad));
   const double eta = sr_colmax(csum, ln, H, act, 16 * T, red);

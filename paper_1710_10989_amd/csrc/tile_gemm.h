@@ -144,7 +144,7 @@ __device__ inline void issue_panel(cgdouble *P, int ldp, cgdouble *Q, int ldq, i
 
 // Multiplies the panel held in (lp, lq) into acc: kend = 16, or fewer for a K tail (a tail
 // only occurs with PREC_F64 on orders that are odd multiples of 16).
-template <class S, int PREC>
+template <class S, int PREC, bool NEG = false>
 __device__ inline void mma_panel(const double *lp, const double *lq, int wr_row, int wc_col, int kend,
                                  typename AccOf<PREC>::T (&acc)[S::TPW]) {
   int lane = threadIdx.x & 63;
@@ -163,7 +163,7 @@ __device__ inline void mma_panel(const double *lp, const double *lq, int wr_row,
         for (int i = 0; i < S::BR; ++i) {
           const int r = wr_row + i * 16 + lr;  // row within the chunk
           const int slot = (k >> 1) ^ ((r >> 1) & 7);
-          a[i] = lp[r * kKP + 2 * slot + (k & 1)];
+          a[i] = NEG ? -lp[r * kKP + 2 * slot + (k & 1)] : lp[r * kKP + 2 * slot + (k & 1)];
         }
 #pragma unroll
         for (int j = 0; j < S::BC; ++j) {
@@ -184,14 +184,17 @@ __device__ inline void mma_panel(const double *lp, const double *lq, int wr_row,
 
 // Full K loop for one chunk.  `active`: this wave owns a block inside the matrix.  The caller
 // must have passed a workgroup barrier since the stages were last read.  On return every
-// panel load has completed, but other waves may still be reading the last stage.
-template <class S, int PREC = PREC_F64>
+// panel load has completed, but other waves may still be reading the last stage.  acc = P Q,
+// or with ACC acc += P Q, or with NEG acc -= P Q (the four real products of a complex one).
+template <class S, int PREC = PREC_F64, bool ACC = false, bool NEG = false>
 __device__ inline void tile_gemm(cgdouble *P, int ldp, cgdouble *Q, int ldq, int M, int N, int K,
                                  int m0, int n0, TileLds<S> &L, bool active, int wr_row, int wc_col,
                                  typename AccOf<PREC>::T (&acc)[S::TPW]) {
   typedef typename AccOf<PREC>::T AT;
+  if constexpr (!ACC) {
 #pragma unroll
-  for (int i = 0; i < S::TPW; ++i) acc[i] = AT{0, 0, 0, 0};
+    for (int i = 0; i < S::TPW; ++i) acc[i] = AT{0, 0, 0, 0};
+  }
   const int npan = (K + kKP - 1) / kKP;
   issue_panel<S>(P, ldp, Q, ldq, M, N, K, m0, n0, 0, L.p[0], L.q[0]);
   if (npan > 1) issue_panel<S>(P, ldp, Q, ldq, M, N, K, m0, n0, kKP, L.p[1], L.q[1]);
@@ -201,7 +204,7 @@ __device__ inline void tile_gemm(cgdouble *P, int ldp, cgdouble *Q, int ldq, int
     lds_barrier();
     if (kp + 2 < npan) issue_panel<S>(P, ldp, Q, ldq, M, N, K, m0, n0, (kp + 2) * kKP, np_p, np_q);
     const int kend = (K - kp * kKP) < kKP ? (K - kp * kKP) : kKP;
-    if (active) mma_panel<S, PREC>(lp, lq, wr_row, wc_col, kend, acc);
+    if (active) mma_panel<S, PREC, NEG>(lp, lq, wr_row, wc_col, kend, acc);
   };
   for (int kp = 0; kp < npan; kp += 3) {
     step(kp, L.p[0], L.q[0], L.p[2], L.q[2]);

@@ -101,7 +101,8 @@ def _hermitian(g, n, t):
     return -1j * H * t
 
 
-@pytest.mark.parametrize("n,t", [(24, 0.3), (64, 5.0), (128, 40.0), (160, 3.0), (256, 20.0)])
+@pytest.mark.parametrize("n,t", [(5, 2.0), (24, 0.3), (64, 5.0), (96, 1.0), (128, 40.0), (160, 3.0), (256, 20.0),
+                                 (300, 0.05)])
 def test_complex_unitary(P, orc, n, t):
     g = np.random.default_rng(n)
     A = _hermitian(g, n, t)
@@ -111,9 +112,9 @@ def test_complex_unitary(P, orc, n, t):
     assert int(st.item()) == 0
     Eh = E.cpu().numpy()
     assert np.abs(Eh.conj().T @ Eh - np.eye(n)).sum(0).max() <= 1e-12 * (1 << max(int(s.item()), 0))
-    # selection uses the 1-norm of the real form [[X, -Y], [Y, X]]
-    R = np.block([[A.real, -A.imag], [A.imag, A.real]])
-    assert (int(m.item()), int(s.item())) == orc.select_plain(orc.norm1(R))
+    # selection uses the 1-norm of A itself, sum_i |z_ij| (native path above order 128 and the
+    # real-form kernels below alike)
+    assert (int(m.item()), int(s.item())) == orc.select_plain(orc.norm1(A))
     if n <= 160:
         ref, _ = orc.expm_taylor(A)
         assert orc.rel_err_1(Eh, ref) <= TOL
@@ -203,3 +204,34 @@ def test_complex_config_size_vs_oracle(P, orc):
         say("  dt=%.3g (m, s)=(%d, %d) rel err %.2e unitarity %.2e" % (dts[i], int(m[j]), int(s[j]), err, unit))
         assert err <= TOL, (i, err)
         assert unit <= 1e-12 * (1 << max(int(s[j]), 0)), (i, unit)
+
+
+def test_complex_native_alpha_ps_batch(P, orc):
+    """The native complex path (order above 128): the alpha rule (norms of the complex powers,
+    sum |z|), Paterson-Stockmeyer, and a uniform batch of several matrices per group, against
+    the long-double complex oracle."""
+    g = np.random.default_rng(33)
+    A = _hermitian(g, 150, 12.0) + 0.3 * (g.standard_normal((150, 150)) + 1j * g.standard_normal((150, 150))) / 150
+    say("case complex native alpha")
+    E, m, s, st = P.taylor(dev(A), selector="alpha")
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    nk = [orc.norm1(np.linalg.matrix_power(A, k)) for k in (1, 2, 3)]
+    ma, sa = orc.select_alpha(orc.alpha_bounds(nk[0], nk[1], nk[2]))
+    assert (int(m.item()), int(s.item())) == (ma, sa)
+    ref, _ = orc.expm_taylor(A)
+    assert orc.rel_err_1(E.cpu().numpy(), ref) <= TOL
+    say("case complex native ps")
+    E, m, s, st = P.taylor(dev(A), method="ps")
+    torch.cuda.synchronize()
+    assert (int(m.item()), int(s.item())) == orc.select_ps(orc.norm1(A))
+    assert orc.rel_err_1(E.cpu().numpy(), ref) <= TOL
+    mats = [_hermitian(g, 140, t) for t in (0.02, 0.7, 9.0, 60.0)]
+    say("case complex native batch")
+    E, m, s, st = P.batched_uniform(dev(np.stack(mats)))
+    torch.cuda.synchronize()
+    assert bool((st == 0).all())
+    for i, Z in enumerate(mats):
+        assert (int(m[i]), int(s[i])) == orc.select_plain(orc.norm1(Z))
+        ref, _ = orc.expm_taylor(Z)
+        assert orc.rel_err_1(E[i].cpu().numpy(), ref) <= TOL, i
