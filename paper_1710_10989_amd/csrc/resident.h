@@ -671,13 +671,9 @@ __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, i
         L[o.at(i, r)] = k[0] * d + k[1] * a1 + k[2] * a2 + k[3] * a3;  // B_1
         const double b2 = k[4] * d + k[5] * a1 + k[6] * a2 + k[7] * a3 + k[8] * a6;
         const double b3 = k[9] * d + k[10] * a1 + k[11] * a2 + k[12] * a3 + k[13] * a6;
-        if constexpr (kPark) {
-          P0.put(i, r, b2);
-          P1.put(i, r, b3);
-        } else {
-          X0[i][r] = b2;
-          X2[i][r] = b3;
-        }
+        X0[i][r] = b2;
+        if constexpr (kPark) P1.put(i, r, b3);
+        else X2[i][r] = b3;
         AC[i][r] = k[14] * d + k[15] * a1 + k[16] * a2 + k[17] * a3 + k[18] * a6;  // B_4
         X1[i][r] = k[19] * d + k[20] * a1 + k[21] * a2 + k[22] * a3 + k[23] * a6;  // B_5
       });
@@ -685,11 +681,6 @@ __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, i
     __syncthreads();
     if constexpr (act) {
       rgemm_reg<T>(L, ln, X1, AC);  // A_9 = B_1 B_5 + B_4
-      if constexpr (kPark) P0.get_all(X1);  // B_2, in flight while Y is formed
-      else {
-#pragma unroll
-        for (int i = 0; i < T; ++i) X1[i] = X0[i];
-      }
     }
     __syncthreads();
     if constexpr (act) {  // Y = B_3 + A_9 becomes the resident matrix
@@ -698,9 +689,9 @@ __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, i
     }
     __syncthreads();
     if constexpr (act) {
-      rgemm_reg<T>(L, ln, AC, X1);  // T = B_2 + Y A_9
+      rgemm_reg<T>(L, ln, AC, X0);  // T = B_2 + Y A_9
 #pragma unroll
-      for (int i = 0; i < T; ++i) AC[i] = X1[i];
+      for (int i = 0; i < T; ++i) AC[i] = X0[i];
     }
   }
 
