@@ -8,8 +8,12 @@
 // exact: every polynomial in the padded matrix is block diagonal, so the leading n x n block
 // is p(A).
 //
-// Scaling (Sec. 1, eq. eses) is folded into the coefficients: X^k = 2^(-sk) A^k, so the
-// stored powers are those of A and no pass rescales a matrix.
+// Scaling (Sec. 1, eq. eses): X^k = 2^(-sk) A^k goes into the coefficients of the linear
+// combinations, so the stored powers are those of A, with no pass over a matrix, whenever no
+// power up to the sixth can overflow (||A||_1 <= 2^150).  Above that the matrix is scaled once
+// its 1-norm is known, to X_p = 2^(-s_p) A with s_p the plain rule's s (exact), and only the
+// difference between the chosen s and s_p goes into the coefficients (or, when that difference
+// is extreme, into the matrices).
 //
 // Two instantiations: 8 waves (orders 80..256, one workgroup per CU) take the front of the
 // queue, 4 waves (orders up to 64, two workgroups per CU) take the rest.
@@ -277,8 +281,10 @@ __device__ void run_one(const FusedArgs &a, int64_t b, double *slot, double *red
     }
     if (cx) {  // complex input: the 1-norm of A itself, sum_i |z_ij|
       colsum = 0.0;
-      if (tid < nin)
+      if (tid < nin) {
+#pragma unroll 8
         for (int r = 0; r < nin; ++r) colsum += hypot(Ag[2 * ((size_t)r * nin + tid)], Ag[2 * ((size_t)r * nin + tid) + 1]);
+      }
     }
   }
   bad = __syncthreads_or(bad);
@@ -306,14 +312,31 @@ __device__ void run_one(const FusedArgs &a, int64_t b, double *slot, double *red
   __syncthreads();
   const int m_plain = sh_ms[0], s_plain = sh_ms[1];
   // buffer B *= 2^e exactly (elementwise)
+  // (16 loads in flight per thread, then 16 stores: a pass costs a few memory latencies, not
+  // one per element)
   auto rescale = [&](double *B, int e2) {
     if (e2 == 0) return;
     gdouble *Bg = gptr(B);
-    for (int e = tid; e < (int)nn; e += NT) Bg[e] = ldexp(Bg[e], e2);
+    for (int e0 = tid; e0 < (int)nn; e0 += 16 * NT) {
+      double v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int e = e0 + u * NT;
+        v[u] = e < (int)nn ? Bg[e] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int e = e0 + u * NT;
+        if (e < (int)nn) Bg[e] = ldexp(v[u], e2);
+      }
+    }
     __syncthreads();
   };
-  // X_p = 2^-sp A (sp the plain rule's s): every power formed from here on stays in range
-  rescale(buf[0], -s_plain);
+  // The buffer holds X_b = 2^eb A: A itself (eb = 0) when no power up to the sixth can overflow
+  // (||A||_1 <= 2^150), else X_p = 2^-sp A (sp the plain rule's s), whose powers stay in range
+  // at any norm.  Either way exact.
+  const int eb = eta <= 0x1p150 ? 0 : -s_plain;
+  rescale(buf[0], eb);
 
   // ---- powers A^2 (buffer 1), A^3 (buffer 2) as the selection needs them ----
   bool have2 = false, have3 = false;
@@ -339,10 +362,10 @@ __device__ void run_one(const FusedArgs &a, int64_t b, double *slot, double *red
   if (a.features) {
     // feature row and training label of the learned selector (no e^A)
     form3();
-    n2 = unscale_norm(block_norm1<NT>(buf[1], np, red), 2, s_plain);
-    n3 = unscale_norm(block_norm1<NT>(buf[2], np, red), 3, s_plain);
-    const double tr = ldexp(block_trace<NT>(buf[0], np, red), s_plain);
-    const double asym = ldexp(block_asym1<NT>(buf[0], np, red), s_plain);
+    n2 = unscale_norm(block_norm1<NT>(buf[1], np, red), 2, -eb);
+    n3 = unscale_norm(block_norm1<NT>(buf[2], np, red), 3, -eb);
+    const double tr = ldexp(block_trace<NT>(buf[0], np, red), -eb);
+    const double asym = ldexp(block_asym1<NT>(buf[0], np, red), -eb);
     if (tid == 0) {
       double *row = a.features + b * kFeatRow;
       learned_features(eta, n2, tr, asym, n, row);
@@ -357,8 +380,8 @@ __device__ void run_one(const FusedArgs &a, int64_t b, double *slot, double *red
     __syncthreads();
     return;
   } else if (a.sel == EXPM_SEL_ALPHA) {
-    if (m_plain >= 2) { form2(); n2 = unscale_norm(block_norm1<NT>(buf[1], np, red), 2, s_plain); }
-    if (m_plain >= 12) { form3(); n3 = unscale_norm(block_norm1<NT>(buf[2], np, red), 3, s_plain); }
+    if (m_plain >= 2) { form2(); n2 = unscale_norm(block_norm1<NT>(buf[1], np, red), 2, -eb); }
+    if (m_plain >= 12) { form3(); n3 = unscale_norm(block_norm1<NT>(buf[2], np, red), 3, -eb); }
     if (m_plain >= 2) {
       if (tid == 0) select_ms(a.k.theta, 1, eta, n2, n3, &sh_ms[0], &sh_ms[1]);
       __syncthreads();
@@ -368,28 +391,32 @@ __device__ void run_one(const FusedArgs &a, int64_t b, double *slot, double *red
     // proposal from the MLP on features available once A^2 exists; kept only if the alpha
     // bound holds for it (with ||A^3|| when the proposal forms A^3 anyway), else the plain rule
     form2();
-    n2 = unscale_norm(block_norm1<NT>(buf[1], np, red), 2, s_plain);
-    const double tr = ldexp(block_trace<NT>(buf[0], np, red), s_plain);
-    const double asym = ldexp(block_asym1<NT>(buf[0], np, red), s_plain);
+    n2 = unscale_norm(block_norm1<NT>(buf[1], np, red), 2, -eb);
+    const double tr = ldexp(block_trace<NT>(buf[0], np, red), -eb);
+    const double asym = ldexp(block_asym1<NT>(buf[0], np, red), -eb);
     const int cls = mlp_infer<NT>(eta, n2, tr, asym, n);
     int mq, sq;
     mlp_class_ms(cls, &mq, &sq);
-    if (mq >= 12) { form3(); n3 = unscale_norm(block_norm1<NT>(buf[2], np, red), 3, s_plain); }
+    if (mq >= 12) { form3(); n3 = unscale_norm(block_norm1<NT>(buf[2], np, red), 3, -eb); }
     const bool ok = proposal_ok(a.k.theta, eta, n2, mq >= 12 ? n3 : -1.0, mq, sq);
     if (ok) { m = mq; s = sq; } else { m = m_plain; s = s_plain; }
     if (tid == 0) atomicAdd(&g_learned_counts[ok ? 0 : 1], 1ull);
   }
-  // the powers formed so far are those of X_p; X^k = 2^(k (sp - s)) X_p^k (exact) when another
-  // rule chose s != sp; the missing powers are then formed from X itself
-  if (s != s_plain) {
-    rescale(buf[0], s_plain - s);
-    if (have2) rescale(buf[1], 2 * (s_plain - s));
-    if (have3) rescale(buf[2], 3 * (s_plain - s));
+  // X = 2^-s A = 2^-sc X_b with sc = s + eb, so X^k = 2^(-k sc) X_b^k.  The factors go into the
+  // coefficients when they stay far from overflow (|sc| <= 150: k sc is within the exponent
+  // range for k <= 6); otherwise the powers formed so far are rescaled (exact) and the missing
+  // ones are formed from X itself.  No pass over a buffer in the common case.
+  const int sc = s + eb;
+  const bool fold = sc >= -150 && sc <= 150;
+  if (!fold) {
+    rescale(buf[0], -sc);
+    if (have2) rescale(buf[1], -2 * sc);
+    if (have3) rescale(buf[2], -3 * sc);
   }
   if (m >= 2) form2();
   if (m >= 12) form3();
   if (tid == 0) {
-    make_coefs(a.k, m, 0, g_ep.c);  // the scaling is in the matrices
+    make_coefs(a.k, m, fold ? sc : 0, g_ep.c);
     a.m_out[b] = m; a.s_out[b] = s;
     if (a.status) a.status[b] = EXPM_OK;
   }

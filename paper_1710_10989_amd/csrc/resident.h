@@ -710,10 +710,20 @@ __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, i
   if constexpr (act) {
     gdouble *E = gptr(a.E + off);
     const int lk = opq(ln.lk), col = opq(ln.col);
+    if (!cx) {  // real output: row-major, the padding dropped (one uniform branch, not one per element)
 #pragma unroll
-    for (int i = 0; i < T; ++i)
+      for (int i = 0; i < T; ++i)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) put_dst(E, n, nin, cx, 16 * i + 4 * r + lk, col, AC[i][r]);
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * i + 4 * r + lk;
+          if (row < n && col < n) E[(size_t)row * n + col] = AC[i][r];
+        }
+    } else {
+#pragma unroll
+      for (int i = 0; i < T; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) put_dst(E, n, nin, cx, 16 * i + 4 * r + lk, col, AC[i][r]);
+    }
   }
   __syncthreads();
 }

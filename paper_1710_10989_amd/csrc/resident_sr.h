@@ -478,10 +478,20 @@ __device__ void run_sr(const FusedArgs &a, int64_t b, int n, int nin, int cx, in
   if constexpr (act) {
     gdouble *E = gptr(a.E + off);
     const int lk = opq(ln.lk), col = opq(ln.col);
+    if (!cx) {  // real output: row-major, the padding dropped (one uniform branch, not one per element)
 #pragma unroll
-    for (int i = 0; i < RT; ++i)
+      for (int i = 0; i < RT; ++i)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) put_dst(E, n, nin, cx, 16 * (G::I0 + i) + 4 * r + lk, col, AC[i][r]);
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * (G::I0 + i) + 4 * r + lk;
+          if (row < n && col < n) E[(size_t)row * n + col] = AC[i][r];
+        }
+    } else {
+#pragma unroll
+      for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) put_dst(E, n, nin, cx, 16 * (G::I0 + i) + 4 * r + lk, col, AC[i][r]);
+    }
   }
   __syncthreads();
 }
