@@ -29,7 +29,9 @@
  *  - The scaling X = 2^-s A (eq. eses) is applied to the matrix when it is loaded (exactly,
  *    a power of two), before any power is formed, so no intermediate overflows whatever
  *    ||A||_1 is; entries of X that fall below the normal range lose bits (as they would in any
- *    evaluation of 2^-s A).
+ *    evaluation of 2^-s A).  The global-memory kernel (real orders 144..256) instead puts
+ *    2^-ks into the coefficient of A^k (the same exact result) while ||A||_1 <= 2^150, where no
+ *    power it forms can overflow, and scales at load above that.
  */
 #ifndef EXPM_H_
 #define EXPM_H_
