@@ -536,7 +536,7 @@ __device__ inline Sweep sweep_of(const FusedArgs &a) {
 
 // Persistent loop: each workgroup pops the next queue entry of its range until it is empty.
 template <class F>
-__device__ inline void sweep(const FusedArgs &a, const F &run) {
+__device__ __attribute__((always_inline)) inline void sweep(const FusedArgs &a, const F &run) {
   __shared__ int64_t sh_idx;
   const Sweep w = sweep_of(a);
   for (int64_t it = w.lo + blockIdx.x;; it += gridDim.x) {
@@ -577,7 +577,9 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 2 : 1) void expm_resident_kernel
   __shared__ double red[64 * NW + 16];
   double *slot = a.slots ? a.slots + (size_t)blockIdx.x * a.slot_doubles : nullptr;
   res_init<NW>(a);
-  sweep(a, [&](int64_t b) { run_res_dispatch<NW, SEL>(a, b, slot, red); });
+  // (inlined all the way down: an out-of-line call would copy the kernel arguments to private
+  // memory and spill the register matrices around it)
+  sweep(a, [&](int64_t b) __attribute__((always_inline)) { run_res_dispatch<NW, SEL>(a, b, slot, red); });
 }
 
 template <int SEL>

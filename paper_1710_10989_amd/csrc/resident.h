@@ -335,13 +335,13 @@ __device__ __noinline__ int res_mlp(double n1, double n2, double tr, double asym
 // working waves update their register matrices unconditionally (a run-time guard around an
 // update would keep the old and the new values alive together).
 template <int NW, int SEL, int T, bool IDLE>
-__device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, int64_t off, double *slot,
+__device__ __attribute__((always_inline)) void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, int64_t off, double *slot,
                         double *red) {
   double *L = res_lds<NW>();
   const int tid = threadIdx.x;
   const Lane ln;
   constexpr bool act = !IDLE;
-  dbl4 X0[T], X1[T], X2[T], AC[T];
+  dbl4 X0[T];
 
   // ---- load A (real form of a complex input); finiteness, 1-norm; then X_p = 2^-sp A with sp
   // the plain rule's s (exact), into LDS: every power formed from here on stays in range. ----
@@ -415,11 +415,10 @@ __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, i
   }
 
   // plain rule, evaluated by every lane on the (uniform) norm: integer work on bit patterns
-  int m_plain, s_plain;
-  select_ms(sh_consts.theta, 0, eta, -1.0, -1.0, &m_plain, &s_plain);
-  m_plain = ufi(m_plain);
+  int m_rule, s_plain;
+  select_ms(sh_consts.theta, 0, eta, -1.0, -1.0, &m_rule, &s_plain);
+  m_rule = ufi(m_rule);
   s_plain = ufi(s_plain);
-  int m = m_plain, s = s_plain;
   if constexpr (act) {
     if (s_plain > 0) {
 #pragma unroll
@@ -431,305 +430,327 @@ __device__ void run_res(const FusedArgs &a, int64_t b, int n, int nin, int cx, i
   }
   __syncthreads();
 
-  // ---- A^2 (X1), the norms the selector needs, then A^3 (X2) at most once ----
-  if (m_plain >= 2 && !IDLE) {
-    zero<T>(X1);
-    rgemm_reg<T>(L, ln, X0, X1);
-  }
-  double n2 = -1.0, n3 = -1.0;
-  bool need3 = false;
-  int mq = 0, sq = 0;
-  if (SEL == EXPM_SEL_ALPHA && m_plain >= 2) {
-    n2 = unscale_norm(norm1<NW, T>(X1, act, red), 2, s_plain);
-    need3 = m_plain >= 12;
-  } else if (SEL == EXPM_SEL_LEARNED && m_plain >= 2) {
-    n2 = unscale_norm(norm1<NW, T>(X1, act, red), 2, s_plain);
-    double tr = 0.0, asy = 0.0;
-    if constexpr (act) {
-      constexpr int S = Res<T>::S;
-      const Own<T> o(ln);
-      const int lk = opq(ln.lk), col = opq(ln.col);
-#pragma unroll
-      for (int i = 0; i < T; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          tr += o.delta(i, r) * X0[i][r];
-          const int row = 16 * i + 4 * r + lk;  // A^T element from the resident A
-          asy += fabs(X0[i][r] - L[col * S + (row ^ swz(col))]);
-        }
-      asy += __shfl_xor(asy, 16);
-      asy += __shfl_xor(asy, 32);
+  // The rest of the method.  Under the plain rule the degree is known here, so it runs once
+  // per degree, each with the degree as a compile-time constant and its own register matrices
+  // (their registers are allotted per degree, so one degree's pressure does not spill
+  // another's); under the other rules, once with the degree chosen at run time.
+  auto rest = [&](auto Mc) __attribute__((always_inline)) {
+    constexpr int MC = decltype(Mc)::value;
+    const int m_plain = MC == 0 ? m_rule : MC == 2 ? (m_rule <= 1 ? 1 : 2) : MC;
+    int m = m_plain, s = s_plain;
+    dbl4 X1[T], X2[T], AC[T];
+
+    // ---- A^2 (X1), the norms the selector needs, then A^3 (X2) at most once ----
+    if (m_plain >= 2 && !IDLE) {
+      zero<T>(X1);
+      rgemm_reg<T>(L, ln, X0, X1);
     }
-    tr = ldexp(wg_sum<NW>(act ? tr : 0.0, red), s_plain);  // of A, not of X_p
-    asy = ldexp(wg_max<NW>(act ? asy : 0.0, red), s_plain);
-    const int cls = ufi(res_mlp<64 * NW>(eta, n2, tr, asy, n));
-    mlp_class_ms(cls, &mq, &sq);
-    if (mq >= 12) {
-      need3 = true;  // the acceptance test uses ||A^3||
+    double n2 = -1.0, n3 = -1.0;
+    bool need3 = false;
+    int mq = 0, sq = 0;
+    if (SEL == EXPM_SEL_ALPHA && m_plain >= 2) {
+      n2 = unscale_norm(norm1<NW, T>(X1, act, red), 2, s_plain);
+      need3 = m_plain >= 12;
+    } else if (SEL == EXPM_SEL_LEARNED && m_plain >= 2) {
+      n2 = unscale_norm(norm1<NW, T>(X1, act, red), 2, s_plain);
+      double tr = 0.0, asy = 0.0;
+      if constexpr (act) {
+        constexpr int S = Res<T>::S;
+        const Own<T> o(ln);
+        const int lk = opq(ln.lk), col = opq(ln.col);
+  #pragma unroll
+        for (int i = 0; i < T; ++i)
+  #pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            tr += o.delta(i, r) * X0[i][r];
+            const int row = 16 * i + 4 * r + lk;  // A^T element from the resident A
+            asy += fabs(X0[i][r] - L[col * S + (row ^ swz(col))]);
+          }
+        asy += __shfl_xor(asy, 16);
+        asy += __shfl_xor(asy, 32);
+      }
+      tr = ldexp(wg_sum<NW>(act ? tr : 0.0, red), s_plain);  // of A, not of X_p
+      asy = ldexp(wg_max<NW>(act ? asy : 0.0, red), s_plain);
+      const int cls = ufi(res_mlp<64 * NW>(eta, n2, tr, asy, n));
+      mlp_class_ms(cls, &mq, &sq);
+      if (mq >= 12) {
+        need3 = true;  // the acceptance test uses ||A^3||
+      } else {
+        const bool ok = ufi(res_proposal_ok(sh_consts.theta, eta, n2, -1.0, mq, sq)) != 0;
+        if (ok) { m = mq; s = sq; }
+        if (tid == 0) atomicAdd(&g_learned_counts[ok ? 0 : 1], 1ull);
+        need3 = m >= 12;
+      }
     } else {
-      const bool ok = ufi(res_proposal_ok(sh_consts.theta, eta, n2, -1.0, mq, sq)) != 0;
-      if (ok) { m = mq; s = sq; }
-      if (tid == 0) atomicAdd(&g_learned_counts[ok ? 0 : 1], 1ull);
-      need3 = m >= 12;
+      need3 = m_plain >= 12;
     }
-  } else {
-    need3 = m_plain >= 12;
-  }
 
-  // From here on A is read elementwise only: at np >= 96 on 8 waves it waits in the
-  // workgroup's HBM slot (region 0), so that no phase holds more than two register matrices
-  // besides the accumulator.
-  constexpr bool kPark = NW == 8 && T >= kResParkT;
-  const Park<NW, T> P0(slot, 0), P1(slot, 1);
-  if constexpr (kPark) {
-    if constexpr (act) P0.put_all(X0);
-  }
-
-  if (need3) {
-    if constexpr (act) {
-      zero<T>(X2);
-      rgemm_reg<T>(L, ln, X1, X2);
+    // From here on A is read elementwise only: at np >= 96 on 8 waves it waits in the
+    // workgroup's HBM slot (region 0), so that no phase holds more than two register matrices
+    // besides the accumulator.
+    constexpr bool kPark = NW == 8 && T >= kResParkT;
+    const Park<NW, T> P0(slot, 0), P1(slot, 1);
+    if constexpr (kPark) {
+      if constexpr (act) P0.put_all(X0);
     }
-    if (SEL == EXPM_SEL_ALPHA) {
-      n3 = unscale_norm(norm1<NW, T>(X2, act, red), 3, s_plain);
-      if (tid == 0) res_select(sh_consts.theta, 1, eta, n2, n3, &sh_ms[0], &sh_ms[1]);
+
+    if (need3) {
+      if constexpr (act) {
+        zero<T>(X2);
+        rgemm_reg<T>(L, ln, X1, X2);
+      }
+      if (SEL == EXPM_SEL_ALPHA) {
+        n3 = unscale_norm(norm1<NW, T>(X2, act, red), 3, s_plain);
+        if (tid == 0) res_select(sh_consts.theta, 1, eta, n2, n3, &sh_ms[0], &sh_ms[1]);
+        __syncthreads();
+        m = ufi(sh_ms[0]); s = ufi(sh_ms[1]);
+      } else if (SEL == EXPM_SEL_LEARNED && mq >= 12) {
+        n3 = unscale_norm(norm1<NW, T>(X2, act, red), 3, s_plain);
+        const bool ok = ufi(res_proposal_ok(sh_consts.theta, eta, n2, n3, mq, sq)) != 0;
+        if (ok) { m = mq; s = sq; }
+        if (tid == 0) atomicAdd(&g_learned_counts[ok ? 0 : 1], 1ull);
+      }
+    } else if (SEL == EXPM_SEL_ALPHA && m_plain >= 2) {
+      // plain m < 12 implies s = 0 and an alpha choice of m <= 8: A^3 is never needed here
+      if (tid == 0) res_select(sh_consts.theta, 1, eta, n2, -1.0, &sh_ms[0], &sh_ms[1]);
       __syncthreads();
       m = ufi(sh_ms[0]); s = ufi(sh_ms[1]);
-    } else if (SEL == EXPM_SEL_LEARNED && mq >= 12) {
-      n3 = unscale_norm(norm1<NW, T>(X2, act, red), 3, s_plain);
-      const bool ok = ufi(res_proposal_ok(sh_consts.theta, eta, n2, n3, mq, sq)) != 0;
-      if (ok) { m = mq; s = sq; }
-      if (tid == 0) atomicAdd(&g_learned_counts[ok ? 0 : 1], 1ull);
     }
-  } else if (SEL == EXPM_SEL_ALPHA && m_plain >= 2) {
-    // plain m < 12 implies s = 0 and an alpha choice of m <= 8: A^3 is never needed here
-    if (tid == 0) res_select(sh_consts.theta, 1, eta, n2, -1.0, &sh_ms[0], &sh_ms[1]);
-    __syncthreads();
-    m = ufi(sh_ms[0]); s = ufi(sh_ms[1]);
-  }
-  if (tid == 0) {
-    a.m_out[b] = m; a.s_out[b] = s;
-    if (a.status) a.status[b] = EXPM_OK;
-  }
-  if (a.select_only) {
-    __syncthreads();
-    return;
-  }
-  // The powers held so far are those of X_p = 2^-sp A; the other rules may have chosen s != sp:
-  // X = 2^(sp - s) X_p, so X^k = 2^(k (sp - s)) X_p^k, rescaled exactly here (A itself when its
-  // elements are read below, through x1).
-  const int dsc = s_plain - s;
-  if (SEL != EXPM_SEL_PLAIN && dsc != 0 && act) {
-    if (m_plain >= 2) {
-#pragma unroll
-      for (int i = 0; i < T; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) X1[i][r] = ldexp(X1[i][r], 2 * dsc);
+    if (tid == 0) {
+      a.m_out[b] = m; a.s_out[b] = s;
+      if (a.status) a.status[b] = EXPM_OK;
     }
-    if (need3) {
-#pragma unroll
-      for (int i = 0; i < T; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) X2[i][r] = ldexp(X2[i][r], 3 * dsc);
+    if (a.select_only) {
+      __syncthreads();
+      return;
     }
-  }
-  auto x1 = [&](double v) {
-    if constexpr (SEL == EXPM_SEL_PLAIN) return v;
-    else return ldexp(v, dsc);
-  };
-  // coefficients of degree M (the scaling is in the matrices), computed by every lane from the
-  // constants in LDS and moved to scalar registers
-  auto coefs = [&](auto deg, double *c, int count) {
-    double t[24];
-    make_coefs(sh_consts, decltype(deg)::value, 0, t);
-    for (int j = 0; j < count; ++j) c[j] = uni(t[j]);
-  };
+    // The powers held so far are those of X_p = 2^-sp A; the other rules may have chosen s != sp:
+    // X = 2^(sp - s) X_p, so X^k = 2^(k (sp - s)) X_p^k, rescaled exactly here (A itself when its
+    // elements are read below, through x1).
+    const int dsc = s_plain - s;
+    if (SEL != EXPM_SEL_PLAIN && dsc != 0 && act) {
+      if (m_plain >= 2) {
+  #pragma unroll
+        for (int i = 0; i < T; ++i)
+  #pragma unroll
+          for (int r = 0; r < 4; ++r) X1[i][r] = ldexp(X1[i][r], 2 * dsc);
+      }
+      if (need3) {
+  #pragma unroll
+        for (int i = 0; i < T; ++i)
+  #pragma unroll
+          for (int r = 0; r < 4; ++r) X2[i][r] = ldexp(X2[i][r], 3 * dsc);
+      }
+    }
+    auto x1 = [&](double v) {
+      if constexpr (SEL == EXPM_SEL_PLAIN) return v;
+      else return ldexp(v, dsc);
+    };
+    // coefficients of degree M (the scaling is in the matrices), computed by every lane from the
+    // constants in LDS and moved to scalar registers
+    auto coefs = [&](auto deg, double *c, int count) {
+      double t[24];
+      make_coefs(sh_consts, decltype(deg)::value, 0, t);
+      for (int j = 0; j < count; ++j) c[j] = uni(t[j]);
+    };
 
-  // ---- T_m(X) into AC.  Products of polynomials in A commute, so each product is
-  // ordered to make the operand that is not at hand in registers the resident one.  Every
-  // elementwise pass writes its results in place of inputs that die with it, so no pass
-  // holds more register matrices than the product that follows it. ----
-  if (m <= 2) {
-    double c[2];
-    if (m == 2) coefs(std::integral_constant<int, 2>(), c, 2);
-    else { coefs(std::integral_constant<int, 1>(), c, 1); c[1] = 0.0; }
-    if constexpr (act) {
-      const Own<T> o(ln);
-      each_elem<kPark>(P0, X0, [&](int i, int r, double a1r) {
-        const double a1 = x1(a1r);
-        X1[i][r] = o.delta(i, r) + c[0] * a1 + (m == 2 ? c[1] * X1[i][r] : 0.0);
-      });
-#pragma unroll
-      for (int i = 0; i < T; ++i) AC[i] = X1[i];
+    // ---- T_m(X) into AC.  Products of polynomials in A commute, so each product is
+    // ordered to make the operand that is not at hand in registers the resident one.  Every
+    // elementwise pass writes its results in place of inputs that die with it, so no pass
+    // holds more register matrices than the product that follows it. ----
+    if (m <= 2) {
+      double c[2];
+      if (m == 2) coefs(std::integral_constant<int, 2>(), c, 2);
+      else { coefs(std::integral_constant<int, 1>(), c, 1); c[1] = 0.0; }
+      if constexpr (act) {
+        const Own<T> o(ln);
+        each_elem<kPark>(P0, X0, [&](int i, int r, double a1r) {
+          const double a1 = x1(a1r);
+          X1[i][r] = o.delta(i, r) + c[0] * a1 + (m == 2 ? c[1] * X1[i][r] : 0.0);
+        });
+  #pragma unroll
+        for (int i = 0; i < T; ++i) AC[i] = X1[i];
+      }
+    } else if (m == 4) {
+      // T = I + c0 A + c1 V, V = A^2 W = (c3 A + c4 A^2) A^2 + c2 A^2
+      double c[5];
+      coefs(std::integral_constant<int, 4>(), c, 5);
+      __syncthreads();
+      if constexpr (act) {
+        const Own<T> o(ln);
+        each_elem<kPark>(P0, X0, [&](int i, int r, double a1r) {
+          const double a1 = x1(a1r); L[o.at(i, r)] = c[3] * a1 + c[4] * X1[i][r]; });
+      }
+      __syncthreads();
+      if constexpr (act) {
+        zero<T>(AC);
+        rgemm_reg<T>(L, ln, X1, AC);
+        const Own<T> o(ln);
+        each_elem<kPark>(P0, X0, [&](int i, int r, double a1r) {
+          const double a1 = x1(a1r);
+          AC[i][r] = o.delta(i, r) + c[0] * a1 + c[1] * (AC[i][r] + c[2] * X1[i][r]);
+        });
+      }
+    } else if (m == 8) {
+      // V = W1 A^2 (W1 = c0 A + c1 A^2); A_4 = c2 V; Lm = c3 A^2 + A_4;
+      // Rm = c4 I + c5 A + c6 A^2 + c7 A_4; T = Lm Rm + c8 I + c9 A + c10 A^2   (eq. Algorithm83eA)
+      double c[11];
+      coefs(std::integral_constant<int, 8>(), c, 11);
+      __syncthreads();
+      if constexpr (act) {
+        const Own<T> o(ln);
+        each_elem<kPark>(P0, X0, [&](int i, int r, double a1r) {
+          const double a1 = x1(a1r); L[o.at(i, r)] = c[0] * a1 + c[1] * X1[i][r]; });
+      }
+      __syncthreads();
+      if constexpr (act) {
+        zero<T>(AC);
+        rgemm_reg<T>(L, ln, X1, AC);  // V
+      }
+      __syncthreads();
+      if constexpr (act) {
+        const Own<T> o(ln);
+        each_elem<kPark>(P0, X0, [&](int i, int r, double a1r) {
+          const double a1 = x1(a1r);
+          const double d = o.delta(i, r), a2 = X1[i][r], a4 = c[2] * AC[i][r];
+          L[o.at(i, r)] = c[3] * a2 + a4;                                 // Lm
+          X1[i][r] = c[4] * d + c[5] * a1 + c[6] * a2 + c[7] * a4;         // Rm
+          AC[i][r] = c[8] * d + c[9] * a1 + c[10] * a2;
+        });
+      }
+      __syncthreads();
+      if constexpr (act) rgemm_reg<T>(L, ln, X1, AC);
+    } else if (m == 12) {
+      // B_j over (I, A, A^2, A^3); A_6 = B_3 + B_4^2; T = B_1 + (B_2 + A_6) A_6   (eq. poly12)
+      double k[16];
+      coefs(std::integral_constant<int, 12>(), k, 16);
+      __syncthreads();
+      if constexpr (act) {
+        const Own<T> o(ln);
+        each_elem<kPark>(P0, X0, [&](int i, int r, double a1r) {
+          const double a1 = x1(a1r);
+          const double d = o.delta(i, r), a2 = X1[i][r], a3 = X2[i][r];
+          L[o.at(i, r)] = k[12] * d + k[13] * a1 + k[14] * a2 + k[15] * a3;  // B_4
+          const double b1 = k[0] * d + k[1] * a1 + k[2] * a2 + k[3] * a3;
+          if constexpr (kPark) P0.put(i, r, b1);
+          else X0[i][r] = b1;
+          X1[i][r] = k[4] * d + k[5] * a1 + k[6] * a2 + k[7] * a3;   // B_2
+          X2[i][r] = k[8] * d + k[9] * a1 + k[10] * a2 + k[11] * a3;  // B_3
+        });
+      }
+      __syncthreads();
+      if constexpr (act) {
+        rgemm_sq<T>(L, ln, X2);  // A_6 = B_3 + B_4 B_4
+  #pragma unroll
+        for (int i = 0; i < T; ++i) X1[i] += X2[i];  // Y = B_2 + A_6
+      }
+      __syncthreads();
+      if constexpr (act) {
+        to_lds<T>(L, ln, X1);
+        if constexpr (kPark) P0.get_all(X1);  // B_1
+        else {
+  #pragma unroll
+          for (int i = 0; i < T; ++i) X1[i] = X0[i];
+        }
+      }
+      __syncthreads();
+      if constexpr (act) {
+        rgemm_reg<T>(L, ln, X2, X1);  // T = B_1 + Y A_6
+  #pragma unroll
+        for (int i = 0; i < T; ++i) AC[i] = X1[i];
+      }
+    } else {
+      // m == 18: A^6 = A^3 A^3; B_1 over (I, A, A^2, A^3), B_2..B_5 over (I, A, A^2, A^3, A^6);
+      // A_9 = B_1 B_5 + B_4; T = B_2 + (B_3 + A_9) A_9   (eq. poly.18)
+      double k[24];
+      coefs(std::integral_constant<int, 18>(), k, 24);
+      __syncthreads();
+      if constexpr (act) to_lds<T>(L, ln, X2);
+      __syncthreads();
+      if constexpr (act) {
+        zero<T>(AC);
+        rgemm_sq<T>(L, ln, AC);  // A^6
+      }
+      __syncthreads();
+      if constexpr (act) {
+        const Own<T> o(ln);
+        each_elem<kPark>(P0, X0, [&](int i, int r, double a1r) {
+          const double a1 = x1(a1r);
+          const double d = o.delta(i, r), a2 = X1[i][r], a3 = L[o.at(i, r)], a6 = AC[i][r];
+          L[o.at(i, r)] = k[0] * d + k[1] * a1 + k[2] * a2 + k[3] * a3;  // B_1
+          const double b2 = k[4] * d + k[5] * a1 + k[6] * a2 + k[7] * a3 + k[8] * a6;
+          const double b3 = k[9] * d + k[10] * a1 + k[11] * a2 + k[12] * a3 + k[13] * a6;
+          X0[i][r] = b2;
+          if constexpr (kPark) P1.put(i, r, b3);
+          else X2[i][r] = b3;
+          AC[i][r] = k[14] * d + k[15] * a1 + k[16] * a2 + k[17] * a3 + k[18] * a6;  // B_4
+          X1[i][r] = k[19] * d + k[20] * a1 + k[21] * a2 + k[22] * a3 + k[23] * a6;  // B_5
+        });
+      }
+      __syncthreads();
+      if constexpr (act) {
+        rgemm_reg<T>(L, ln, X1, AC);  // A_9 = B_1 B_5 + B_4
+      }
+      __syncthreads();
+      if constexpr (act) {  // Y = B_3 + A_9 becomes the resident matrix
+        const Own<T> o(ln);
+        each_elem<kPark>(P1, X2, [&](int i, int r, double b3) { L[o.at(i, r)] = b3 + AC[i][r]; });
+      }
+      __syncthreads();
+      if constexpr (act) {
+        rgemm_reg<T>(L, ln, AC, X0);  // T = B_2 + Y A_9
+  #pragma unroll
+        for (int i = 0; i < T; ++i) AC[i] = X0[i];
+      }
     }
-  } else if (m == 4) {
-    // T = I + c0 A + c1 V, V = A^2 W = (c3 A + c4 A^2) A^2 + c2 A^2
-    double c[5];
-    coefs(std::integral_constant<int, 4>(), c, 5);
-    __syncthreads();
-    if constexpr (act) {
-      const Own<T> o(ln);
-      each_elem<kPark>(P0, X0, [&](int i, int r, double a1r) {
-        const double a1 = x1(a1r); L[o.at(i, r)] = c[3] * a1 + c[4] * X1[i][r]; });
+
+    // ---- s squarings: the resident matrix is both operands ----
+    for (int q = 0; q < s; ++q) {
+      __syncthreads();
+      if constexpr (act) to_lds<T>(L, ln, AC);
+      __syncthreads();
+      if constexpr (act) {
+        zero<T>(AC);
+        rgemm_sq<T>(L, ln, AC);
+      }
     }
-    __syncthreads();
+
+    // ---- e^A ----
     if constexpr (act) {
-      zero<T>(AC);
-      rgemm_reg<T>(L, ln, X1, AC);
-      const Own<T> o(ln);
-      each_elem<kPark>(P0, X0, [&](int i, int r, double a1r) {
-        const double a1 = x1(a1r);
-        AC[i][r] = o.delta(i, r) + c[0] * a1 + c[1] * (AC[i][r] + c[2] * X1[i][r]);
-      });
-    }
-  } else if (m == 8) {
-    // V = W1 A^2 (W1 = c0 A + c1 A^2); A_4 = c2 V; Lm = c3 A^2 + A_4;
-    // Rm = c4 I + c5 A + c6 A^2 + c7 A_4; T = Lm Rm + c8 I + c9 A + c10 A^2   (eq. Algorithm83eA)
-    double c[11];
-    coefs(std::integral_constant<int, 8>(), c, 11);
-    __syncthreads();
-    if constexpr (act) {
-      const Own<T> o(ln);
-      each_elem<kPark>(P0, X0, [&](int i, int r, double a1r) {
-        const double a1 = x1(a1r); L[o.at(i, r)] = c[0] * a1 + c[1] * X1[i][r]; });
-    }
-    __syncthreads();
-    if constexpr (act) {
-      zero<T>(AC);
-      rgemm_reg<T>(L, ln, X1, AC);  // V
-    }
-    __syncthreads();
-    if constexpr (act) {
-      const Own<T> o(ln);
-      each_elem<kPark>(P0, X0, [&](int i, int r, double a1r) {
-        const double a1 = x1(a1r);
-        const double d = o.delta(i, r), a2 = X1[i][r], a4 = c[2] * AC[i][r];
-        L[o.at(i, r)] = c[3] * a2 + a4;                                 // Lm
-        X1[i][r] = c[4] * d + c[5] * a1 + c[6] * a2 + c[7] * a4;         // Rm
-        AC[i][r] = c[8] * d + c[9] * a1 + c[10] * a2;
-      });
-    }
-    __syncthreads();
-    if constexpr (act) rgemm_reg<T>(L, ln, X1, AC);
-  } else if (m == 12) {
-    // B_j over (I, A, A^2, A^3); A_6 = B_3 + B_4^2; T = B_1 + (B_2 + A_6) A_6   (eq. poly12)
-    double k[16];
-    coefs(std::integral_constant<int, 12>(), k, 16);
-    __syncthreads();
-    if constexpr (act) {
-      const Own<T> o(ln);
-      each_elem<kPark>(P0, X0, [&](int i, int r, double a1r) {
-        const double a1 = x1(a1r);
-        const double d = o.delta(i, r), a2 = X1[i][r], a3 = X2[i][r];
-        L[o.at(i, r)] = k[12] * d + k[13] * a1 + k[14] * a2 + k[15] * a3;  // B_4
-        const double b1 = k[0] * d + k[1] * a1 + k[2] * a2 + k[3] * a3;
-        if constexpr (kPark) P0.put(i, r, b1);
-        else X0[i][r] = b1;
-        X1[i][r] = k[4] * d + k[5] * a1 + k[6] * a2 + k[7] * a3;   // B_2
-        X2[i][r] = k[8] * d + k[9] * a1 + k[10] * a2 + k[11] * a3;  // B_3
-      });
-    }
-    __syncthreads();
-    if constexpr (act) {
-      rgemm_sq<T>(L, ln, X2);  // A_6 = B_3 + B_4 B_4
-#pragma unroll
-      for (int i = 0; i < T; ++i) X1[i] += X2[i];  // Y = B_2 + A_6
-    }
-    __syncthreads();
-    if constexpr (act) {
-      to_lds<T>(L, ln, X1);
-      if constexpr (kPark) P0.get_all(X1);  // B_1
-      else {
-#pragma unroll
-        for (int i = 0; i < T; ++i) X1[i] = X0[i];
+      gdouble *E = gptr(a.E + off);
+      const int lk = opq(ln.lk), col = opq(ln.col);
+      if (!cx) {  // real output: row-major, the padding dropped (one uniform branch, not one per element)
+  #pragma unroll
+        for (int i = 0; i < T; ++i)
+  #pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = 16 * i + 4 * r + lk;
+            if (row < n && col < n) E[(size_t)row * n + col] = AC[i][r];
+          }
+      } else {
+  #pragma unroll
+        for (int i = 0; i < T; ++i)
+  #pragma unroll
+          for (int r = 0; r < 4; ++r) put_dst(E, n, nin, cx, 16 * i + 4 * r + lk, col, AC[i][r]);
       }
     }
     __syncthreads();
-    if constexpr (act) {
-      rgemm_reg<T>(L, ln, X2, X1);  // T = B_1 + Y A_6
-#pragma unroll
-      for (int i = 0; i < T; ++i) AC[i] = X1[i];
+  };
+  if constexpr (SEL == EXPM_SEL_PLAIN) {
+    switch (m_rule) {
+      case 18: rest(std::integral_constant<int, 18>()); break;
+      case 12: rest(std::integral_constant<int, 12>()); break;
+      case 8: rest(std::integral_constant<int, 8>()); break;
+      case 4: rest(std::integral_constant<int, 4>()); break;
+      default: rest(std::integral_constant<int, 2>()); break;
     }
   } else {
-    // m == 18: A^6 = A^3 A^3; B_1 over (I, A, A^2, A^3), B_2..B_5 over (I, A, A^2, A^3, A^6);
-    // A_9 = B_1 B_5 + B_4; T = B_2 + (B_3 + A_9) A_9   (eq. poly.18)
-    double k[24];
-    coefs(std::integral_constant<int, 18>(), k, 24);
-    __syncthreads();
-    if constexpr (act) to_lds<T>(L, ln, X2);
-    __syncthreads();
-    if constexpr (act) {
-      zero<T>(AC);
-      rgemm_sq<T>(L, ln, AC);  // A^6
-    }
-    __syncthreads();
-    if constexpr (act) {
-      const Own<T> o(ln);
-      each_elem<kPark>(P0, X0, [&](int i, int r, double a1r) {
-        const double a1 = x1(a1r);
-        const double d = o.delta(i, r), a2 = X1[i][r], a3 = L[o.at(i, r)], a6 = AC[i][r];
-        L[o.at(i, r)] = k[0] * d + k[1] * a1 + k[2] * a2 + k[3] * a3;  // B_1
-        const double b2 = k[4] * d + k[5] * a1 + k[6] * a2 + k[7] * a3 + k[8] * a6;
-        const double b3 = k[9] * d + k[10] * a1 + k[11] * a2 + k[12] * a3 + k[13] * a6;
-        X0[i][r] = b2;
-        if constexpr (kPark) P1.put(i, r, b3);
-        else X2[i][r] = b3;
-        AC[i][r] = k[14] * d + k[15] * a1 + k[16] * a2 + k[17] * a3 + k[18] * a6;  // B_4
-        X1[i][r] = k[19] * d + k[20] * a1 + k[21] * a2 + k[22] * a3 + k[23] * a6;  // B_5
-      });
-    }
-    __syncthreads();
-    if constexpr (act) {
-      rgemm_reg<T>(L, ln, X1, AC);  // A_9 = B_1 B_5 + B_4
-    }
-    __syncthreads();
-    if constexpr (act) {  // Y = B_3 + A_9 becomes the resident matrix
-      const Own<T> o(ln);
-      each_elem<kPark>(P1, X2, [&](int i, int r, double b3) { L[o.at(i, r)] = b3 + AC[i][r]; });
-    }
-    __syncthreads();
-    if constexpr (act) {
-      rgemm_reg<T>(L, ln, AC, X0);  // T = B_2 + Y A_9
-#pragma unroll
-      for (int i = 0; i < T; ++i) AC[i] = X0[i];
-    }
+    rest(std::integral_constant<int, 0>());
   }
-
-  // ---- s squarings: the resident matrix is both operands ----
-  for (int q = 0; q < s; ++q) {
-    __syncthreads();
-    if constexpr (act) to_lds<T>(L, ln, AC);
-    __syncthreads();
-    if constexpr (act) {
-      zero<T>(AC);
-      rgemm_sq<T>(L, ln, AC);
-    }
-  }
-
-  // ---- e^A ----
-  if constexpr (act) {
-    gdouble *E = gptr(a.E + off);
-    const int lk = opq(ln.lk), col = opq(ln.col);
-    if (!cx) {  // real output: row-major, the padding dropped (one uniform branch, not one per element)
-#pragma unroll
-      for (int i = 0; i < T; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = 16 * i + 4 * r + lk;
-          if (row < n && col < n) E[(size_t)row * n + col] = AC[i][r];
-        }
-    } else {
-#pragma unroll
-      for (int i = 0; i < T; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) put_dst(E, n, nin, cx, 16 * i + 4 * r + lk, col, AC[i][r]);
-    }
-  }
-  __syncthreads();
 }
 
 template <int NW, int SEL>
-__device__ void run_res_dispatch(const FusedArgs &a, int64_t b, double *slot, double *red) {
+__device__ __attribute__((always_inline)) void run_res_dispatch(const FusedArgs &a, int64_t b, double *slot, double *red) {
   const int tid = threadIdx.x;
   const int nin = ufi(a.ns ? a.ns[b] : a.n_uniform);
   const int cx = a.cplx;
