@@ -586,7 +586,7 @@ template <int SEL>
 __global__ __launch_bounds__(64 * kSrNW, 3) void expm_sr_kernel(FusedArgs a) {
   __shared__ double red[64 * kSrNW + 16];
   res_init<kSrNW>(a);
-  sweep(a, [&](int64_t b) { run_sr_dispatch<SEL>(a, b, red); });
+  sweep(a, [&](int64_t b) __attribute__((always_inline)) { run_sr_dispatch<SEL>(a, b, red); });
 }
 
 }  // namespace

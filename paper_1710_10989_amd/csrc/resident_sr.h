@@ -129,14 +129,14 @@ __device__ inline double sr_abs_part(const dbl4 (&x)[SrGeo<T, H>::RT]) {
 // Runs the method on matrix b of real order n (np = 16 T) in the split-row scheme.  H: this
 // wave's row half; IDLE: waves beyond 2 T (T = 5) take part in barriers and reductions only.
 template <int SEL, int T, int H, bool IDLE>
-__device__ void run_sr(const FusedArgs &a, int64_t b, int n, int nin, int cx, int64_t off, double *red) {
+__device__ __attribute__((always_inline)) void run_sr(const FusedArgs &a, int64_t b, int n, int nin, int cx, int64_t off, double *red) {
   typedef SrGeo<T, H> G;
   constexpr int RT = G::RT, S = G::S;
   constexpr bool act = !IDLE;
   double *L1 = g_sr1, *L2 = g_sr2;
   const int tid = threadIdx.x;
   const SrLane ln(T);
-  dbl4 X0[RT], X1[RT], X2[RT], X3[RT], AC[RT];
+  dbl4 X0[RT];
 
   // ---- load A (real form of a complex input) into X0 and L1; finiteness, 1-norm ----
   int bad = 0;
@@ -199,11 +199,10 @@ __device__ void run_sr(const FusedArgs &a, int64_t b, int n, int nin, int cx, in
     return;
   }
 
-  int m_plain, s_plain;
-  select_ms(sh_consts.theta, 0, eta, -1.0, -1.0, &m_plain, &s_plain);
-  m_plain = ufi(m_plain);
+  int m_rule, s_plain;
+  select_ms(sh_consts.theta, 0, eta, -1.0, -1.0, &m_rule, &s_plain);
+  m_rule = ufi(m_rule);
   s_plain = ufi(s_plain);
-  int m = m_plain, s = s_plain;
   // X_p = 2^-sp A (sp the plain rule's s, exact) into L1: every power formed from here on
   // stays in range
   if constexpr (act) {
@@ -217,287 +216,306 @@ __device__ void run_sr(const FusedArgs &a, int64_t b, int n, int nin, int cx, in
   }
   __syncthreads();
 
-  // ---- A^2 (X1) = A A from L1; the norms the selector needs; A^3 (X2) at most once ----
-  if (m_plain >= 2) {
-    if constexpr (act) {
-      zero<RT>(X1);
-      sr_gemm<T, H>(L1, L1, ln, X1);
+  // The rest of the method, per degree under the plain rule (see run_res).
+  auto rest = [&](auto Mc) __attribute__((always_inline)) {
+    constexpr int MC = decltype(Mc)::value;
+    const int m_plain = MC == 0 ? m_rule : MC == 2 ? (m_rule <= 1 ? 1 : 2) : MC;
+    int m = m_plain, s = s_plain;
+    dbl4 X1[RT], X2[RT], X3[RT], AC[RT];
+
+    // ---- A^2 (X1) = A A from L1; the norms the selector needs; A^3 (X2) at most once ----
+    if (m_plain >= 2) {
+      if constexpr (act) {
+        zero<RT>(X1);
+        sr_gemm<T, H>(L1, L1, ln, X1);
+      }
     }
-  }
-  double n2 = -1.0, n3 = -1.0;
-  bool need3 = false;
-  int mq = 0, sq = 0;
-  if (SEL == EXPM_SEL_ALPHA && m_plain >= 2) {
-    n2 = unscale_norm(sr_colmax(act ? sr_abs_part<T, H>(X1) : 0.0, ln, H, act, 16 * T, red), 2, s_plain);
-    need3 = m_plain >= 12;
-  } else if (SEL == EXPM_SEL_LEARNED && m_plain >= 2) {
-    n2 = unscale_norm(sr_colmax(act ? sr_abs_part<T, H>(X1) : 0.0, ln, H, act, 16 * T, red), 2, s_plain);
-    double tr = 0.0, asy = 0.0;
-    if constexpr (act) {
-      const SrOwn<T, H> o(ln);
-      const int lk = opq(ln.lk), col = opq(ln.col);
-#pragma unroll
-      for (int i = 0; i < RT; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          tr += o.delta(i, r) * X0[i][r];
-          const int row = 16 * (G::I0 + i) + 4 * r + lk;  // A^T element from the resident A
-          asy += fabs(X0[i][r] - L1[col * S + (row ^ swz(col))]);
-        }
-    }
-    tr = ldexp(wg_sum<kSrNW>(act ? tr : 0.0, red), s_plain);  // of A, not of X_p
-    asy = ldexp(sr_colmax(act ? asy : 0.0, ln, H, act, 16 * T, red), s_plain);
-    const int cls = ufi(res_mlp<64 * kSrNW>(eta, n2, tr, asy, n));
-    mlp_class_ms(cls, &mq, &sq);
-    if (mq >= 12) {
-      need3 = true;  // the acceptance test uses ||A^3||
+    double n2 = -1.0, n3 = -1.0;
+    bool need3 = false;
+    int mq = 0, sq = 0;
+    if (SEL == EXPM_SEL_ALPHA && m_plain >= 2) {
+      n2 = unscale_norm(sr_colmax(act ? sr_abs_part<T, H>(X1) : 0.0, ln, H, act, 16 * T, red), 2, s_plain);
+      need3 = m_plain >= 12;
+    } else if (SEL == EXPM_SEL_LEARNED && m_plain >= 2) {
+      n2 = unscale_norm(sr_colmax(act ? sr_abs_part<T, H>(X1) : 0.0, ln, H, act, 16 * T, red), 2, s_plain);
+      double tr = 0.0, asy = 0.0;
+      if constexpr (act) {
+        const SrOwn<T, H> o(ln);
+        const int lk = opq(ln.lk), col = opq(ln.col);
+  #pragma unroll
+        for (int i = 0; i < RT; ++i)
+  #pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            tr += o.delta(i, r) * X0[i][r];
+            const int row = 16 * (G::I0 + i) + 4 * r + lk;  // A^T element from the resident A
+            asy += fabs(X0[i][r] - L1[col * S + (row ^ swz(col))]);
+          }
+      }
+      tr = ldexp(wg_sum<kSrNW>(act ? tr : 0.0, red), s_plain);  // of A, not of X_p
+      asy = ldexp(sr_colmax(act ? asy : 0.0, ln, H, act, 16 * T, red), s_plain);
+      const int cls = ufi(res_mlp<64 * kSrNW>(eta, n2, tr, asy, n));
+      mlp_class_ms(cls, &mq, &sq);
+      if (mq >= 12) {
+        need3 = true;  // the acceptance test uses ||A^3||
+      } else {
+        const bool ok = ufi(res_proposal_ok(sh_consts.theta, eta, n2, -1.0, mq, sq)) != 0;
+        if (ok) { m = mq; s = sq; }
+        if (tid == 0) atomicAdd(&g_learned_counts[ok ? 0 : 1], 1ull);
+        need3 = m >= 12;
+      }
     } else {
-      const bool ok = ufi(res_proposal_ok(sh_consts.theta, eta, n2, -1.0, mq, sq)) != 0;
-      if (ok) { m = mq; s = sq; }
-      if (tid == 0) atomicAdd(&g_learned_counts[ok ? 0 : 1], 1ull);
-      need3 = m >= 12;
+      need3 = m_plain >= 12;
     }
-  } else {
-    need3 = m_plain >= 12;
-  }
-  if (need3) {
-    if constexpr (act) sr_put<T, H>(L2, ln, X1);  // L2 is idle since the last matrix
-    __syncthreads();
-    if constexpr (act) {
-      zero<RT>(X2);
-      sr_gemm<T, H>(L1, L2, ln, X2);
-    }
-    if (SEL == EXPM_SEL_ALPHA) {
-      n3 = unscale_norm(sr_colmax(act ? sr_abs_part<T, H>(X2) : 0.0, ln, H, act, 16 * T, red), 3, s_plain);
-      if (tid == 0) res_select(sh_consts.theta, 1, eta, n2, n3, &sh_ms[0], &sh_ms[1]);
+    if (need3) {
+      if constexpr (act) sr_put<T, H>(L2, ln, X1);  // L2 is idle since the last matrix
+      __syncthreads();
+      if constexpr (act) {
+        zero<RT>(X2);
+        sr_gemm<T, H>(L1, L2, ln, X2);
+      }
+      if (SEL == EXPM_SEL_ALPHA) {
+        n3 = unscale_norm(sr_colmax(act ? sr_abs_part<T, H>(X2) : 0.0, ln, H, act, 16 * T, red), 3, s_plain);
+        if (tid == 0) res_select(sh_consts.theta, 1, eta, n2, n3, &sh_ms[0], &sh_ms[1]);
+        __syncthreads();
+        m = ufi(sh_ms[0]); s = ufi(sh_ms[1]);
+      } else if (SEL == EXPM_SEL_LEARNED && mq >= 12) {
+        n3 = unscale_norm(sr_colmax(act ? sr_abs_part<T, H>(X2) : 0.0, ln, H, act, 16 * T, red), 3, s_plain);
+        const bool ok = ufi(res_proposal_ok(sh_consts.theta, eta, n2, n3, mq, sq)) != 0;
+        if (ok) { m = mq; s = sq; }
+        if (tid == 0) atomicAdd(&g_learned_counts[ok ? 0 : 1], 1ull);
+      }
+    } else if (SEL == EXPM_SEL_ALPHA && m_plain >= 2) {
+      if (tid == 0) res_select(sh_consts.theta, 1, eta, n2, -1.0, &sh_ms[0], &sh_ms[1]);
       __syncthreads();
       m = ufi(sh_ms[0]); s = ufi(sh_ms[1]);
-    } else if (SEL == EXPM_SEL_LEARNED && mq >= 12) {
-      n3 = unscale_norm(sr_colmax(act ? sr_abs_part<T, H>(X2) : 0.0, ln, H, act, 16 * T, red), 3, s_plain);
-      const bool ok = ufi(res_proposal_ok(sh_consts.theta, eta, n2, n3, mq, sq)) != 0;
-      if (ok) { m = mq; s = sq; }
-      if (tid == 0) atomicAdd(&g_learned_counts[ok ? 0 : 1], 1ull);
     }
-  } else if (SEL == EXPM_SEL_ALPHA && m_plain >= 2) {
-    if (tid == 0) res_select(sh_consts.theta, 1, eta, n2, -1.0, &sh_ms[0], &sh_ms[1]);
-    __syncthreads();
-    m = ufi(sh_ms[0]); s = ufi(sh_ms[1]);
-  }
-  if (tid == 0) {
-    a.m_out[b] = m; a.s_out[b] = s;
-    if (a.status) a.status[b] = EXPM_OK;
-  }
-  if (a.select_only) {
-    __syncthreads();
-    return;
-  }
-  // The powers held so far are those of X_p; the other rules may have chosen s != sp:
-  // X^k = 2^(k (sp - s)) X_p^k, rescaled exactly.
-  const int dsc = s_plain - s;
-  if (SEL != EXPM_SEL_PLAIN && dsc != 0 && act) {
-#pragma unroll
-    for (int i = 0; i < RT; ++i)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        X0[i][r] = ldexp(X0[i][r], dsc);
-        if (m_plain >= 2) X1[i][r] = ldexp(X1[i][r], 2 * dsc);
-        if (need3) X2[i][r] = ldexp(X2[i][r], 3 * dsc);
-      }
-  }
-  // coefficients of the chosen degree (the scaling is in the matrices)
-  auto coefs = [&](auto deg, double *c, int count) {
-    double t[24];
-    make_coefs(sh_consts, decltype(deg)::value, 0, t);
-    for (int j = 0; j < count; ++j) c[j] = uni(t[j]);
-  };
+    if (tid == 0) {
+      a.m_out[b] = m; a.s_out[b] = s;
+      if (a.status) a.status[b] = EXPM_OK;
+    }
+    if (a.select_only) {
+      __syncthreads();
+      return;
+    }
+    // The powers held so far are those of X_p; the other rules may have chosen s != sp:
+    // X^k = 2^(k (sp - s)) X_p^k, rescaled exactly.
+    const int dsc = s_plain - s;
+    if (SEL != EXPM_SEL_PLAIN && dsc != 0 && act) {
+  #pragma unroll
+      for (int i = 0; i < RT; ++i)
+  #pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          X0[i][r] = ldexp(X0[i][r], dsc);
+          if (m_plain >= 2) X1[i][r] = ldexp(X1[i][r], 2 * dsc);
+          if (need3) X2[i][r] = ldexp(X2[i][r], 3 * dsc);
+        }
+    }
+    // coefficients of the chosen degree (the scaling is in the matrices)
+    auto coefs = [&](auto deg, double *c, int count) {
+      double t[24];
+      make_coefs(sh_consts, decltype(deg)::value, 0, t);
+      for (int j = 0; j < count; ++j) c[j] = uni(t[j]);
+    };
 
-  // ---- T_m(X) into AC (X0 = X, X1 = X^2, X2 = X^3 where formed) ----
-  __syncthreads();  // every product so far has finished reading L1 and L2
-  if (m <= 2) {
-    double c[2];
-    if (m == 2) coefs(std::integral_constant<int, 2>(), c, 2);
-    else { coefs(std::integral_constant<int, 1>(), c, 1); c[1] = 0.0; }
-    if constexpr (act) {
-      const SrOwn<T, H> o(ln);
-#pragma unroll
-      for (int i = 0; i < RT; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          AC[i][r] = o.delta(i, r) + c[0] * X0[i][r] + (m == 2 ? c[1] * X1[i][r] : 0.0);
+    // ---- T_m(X) into AC (X0 = X, X1 = X^2, X2 = X^3 where formed) ----
+    __syncthreads();  // every product so far has finished reading L1 and L2
+    if (m <= 2) {
+      double c[2];
+      if (m == 2) coefs(std::integral_constant<int, 2>(), c, 2);
+      else { coefs(std::integral_constant<int, 1>(), c, 1); c[1] = 0.0; }
+      if constexpr (act) {
+        const SrOwn<T, H> o(ln);
+  #pragma unroll
+        for (int i = 0; i < RT; ++i)
+  #pragma unroll
+          for (int r = 0; r < 4; ++r)
+            AC[i][r] = o.delta(i, r) + c[0] * X0[i][r] + (m == 2 ? c[1] * X1[i][r] : 0.0);
+      }
+    } else if (m == 4) {
+      // T = I + c0 A + c1 V, V = A^2 W = A^2 (c2 I + c3 A + c4 A^2)
+      double c[5];
+      coefs(std::integral_constant<int, 4>(), c, 5);
+      if constexpr (act) {
+        const SrOwn<T, H> o(ln);
+        sr_put<T, H>(L1, ln, X1);
+  #pragma unroll
+        for (int i = 0; i < RT; ++i)
+  #pragma unroll
+          for (int r = 0; r < 4; ++r) L2[o.at(i, r)] = c[2] * o.delta(i, r) + c[3] * X0[i][r] + c[4] * X1[i][r];
+      }
+      __syncthreads();
+      if constexpr (act) {
+        zero<RT>(AC);
+        sr_gemm<T, H>(L1, L2, ln, AC);
+        const SrOwn<T, H> o(ln);
+  #pragma unroll
+        for (int i = 0; i < RT; ++i)
+  #pragma unroll
+          for (int r = 0; r < 4; ++r) AC[i][r] = o.delta(i, r) + c[0] * X0[i][r] + c[1] * AC[i][r];
+      }
+    } else if (m == 8) {
+      // V = A^2 W1 (W1 = c0 A + c1 A^2); A_4 = c2 V; Lm = c3 A^2 + A_4;
+      // Rm = c4 I + c5 A + c6 A^2 + c7 A_4; T = Lm Rm + c8 I + c9 A + c10 A^2   (eq. Algorithm83eA)
+      double c[11];
+      coefs(std::integral_constant<int, 8>(), c, 11);
+      if constexpr (act) {
+        const SrOwn<T, H> o(ln);
+        sr_put<T, H>(L1, ln, X1);
+  #pragma unroll
+        for (int i = 0; i < RT; ++i)
+  #pragma unroll
+          for (int r = 0; r < 4; ++r) L2[o.at(i, r)] = c[0] * X0[i][r] + c[1] * X1[i][r];
+      }
+      __syncthreads();
+      if constexpr (act) {
+        zero<RT>(X2);
+        sr_gemm<T, H>(L1, L2, ln, X2);  // V
+      }
+      __syncthreads();
+      if constexpr (act) {
+        const SrOwn<T, H> o(ln);
+  #pragma unroll
+        for (int i = 0; i < RT; ++i)
+  #pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const double d = o.delta(i, r), a1 = X0[i][r], a2 = X1[i][r], a4 = c[2] * X2[i][r];
+            L1[o.at(i, r)] = c[3] * a2 + a4;                                 // Lm
+            L2[o.at(i, r)] = c[4] * d + c[5] * a1 + c[6] * a2 + c[7] * a4;   // Rm
+            AC[i][r] = c[8] * d + c[9] * a1 + c[10] * a2;
+          }
+      }
+      __syncthreads();
+      if constexpr (act) sr_gemm<T, H>(L1, L2, ln, AC);
+    } else if (m == 12) {
+      // B_j over (I, A, A^2, A^3); A_6 = B_3 + B_4^2; T = B_1 + (B_2 + A_6) A_6   (eq. poly12)
+      double k[16];
+      coefs(std::integral_constant<int, 12>(), k, 16);
+      if constexpr (act) {
+        const SrOwn<T, H> o(ln);
+  #pragma unroll
+        for (int i = 0; i < RT; ++i)
+  #pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const double d = o.delta(i, r), a1 = X0[i][r], a2 = X1[i][r], a3 = X2[i][r];
+            L1[o.at(i, r)] = k[12] * d + k[13] * a1 + k[14] * a2 + k[15] * a3;  // B_4
+            X0[i][r] = k[0] * d + k[1] * a1 + k[2] * a2 + k[3] * a3;            // B_1
+            X1[i][r] = k[4] * d + k[5] * a1 + k[6] * a2 + k[7] * a3;            // B_2
+            AC[i][r] = k[8] * d + k[9] * a1 + k[10] * a2 + k[11] * a3;          // B_3
+          }
+      }
+      __syncthreads();
+      if constexpr (act) sr_gemm<T, H>(L1, L1, ln, AC);  // A_6 = B_3 + B_4 B_4
+      __syncthreads();
+      if constexpr (act) {
+        const SrOwn<T, H> o(ln);
+  #pragma unroll
+        for (int i = 0; i < RT; ++i)
+  #pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            L1[o.at(i, r)] = X1[i][r] + AC[i][r];  // Y = B_2 + A_6
+            L2[o.at(i, r)] = AC[i][r];             // A_6
+          }
+      }
+      __syncthreads();
+      if constexpr (act) {
+        sr_gemm<T, H>(L1, L2, ln, X0);  // T = B_1 + Y A_6
+  #pragma unroll
+        for (int i = 0; i < RT; ++i) AC[i] = X0[i];
+      }
+    } else {
+      // m == 18: A^6 = A^3 A^3; B_1 over (I, A, A^2, A^3), B_2..B_5 over (I, A, A^2, A^3, A^6);
+      // A_9 = B_1 B_5 + B_4; T = B_2 + (B_3 + A_9) A_9   (eq. poly.18)
+      double k[24];
+      coefs(std::integral_constant<int, 18>(), k, 24);
+      if constexpr (act) sr_put<T, H>(L1, ln, X2);
+      __syncthreads();
+      if constexpr (act) {
+        zero<RT>(X3);
+        sr_gemm<T, H>(L1, L1, ln, X3);  // A^6
+      }
+      __syncthreads();
+      if constexpr (act) {
+        const SrOwn<T, H> o(ln);
+  #pragma unroll
+        for (int i = 0; i < RT; ++i)
+  #pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const double d = o.delta(i, r), a1 = X0[i][r], a2 = X1[i][r], a3 = X2[i][r], a6 = X3[i][r];
+            L1[o.at(i, r)] = k[0] * d + k[1] * a1 + k[2] * a2 + k[3] * a3;                       // B_1
+            X0[i][r] = k[4] * d + k[5] * a1 + k[6] * a2 + k[7] * a3 + k[8] * a6;               // B_2
+            X1[i][r] = k[9] * d + k[10] * a1 + k[11] * a2 + k[12] * a3 + k[13] * a6;           // B_3
+            AC[i][r] = k[14] * d + k[15] * a1 + k[16] * a2 + k[17] * a3 + k[18] * a6;          // B_4
+            L2[o.at(i, r)] = k[19] * d + k[20] * a1 + k[21] * a2 + k[22] * a3 + k[23] * a6;    // B_5
+          }
+      }
+      __syncthreads();
+      if constexpr (act) sr_gemm<T, H>(L1, L2, ln, AC);  // A_9 = B_1 B_5 + B_4
+      __syncthreads();
+      if constexpr (act) {
+        const SrOwn<T, H> o(ln);
+  #pragma unroll
+        for (int i = 0; i < RT; ++i)
+  #pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            L1[o.at(i, r)] = X1[i][r] + AC[i][r];  // Y = B_3 + A_9
+            L2[o.at(i, r)] = AC[i][r];             // A_9
+          }
+      }
+      __syncthreads();
+      if constexpr (act) {
+        sr_gemm<T, H>(L1, L2, ln, X0);  // T = B_2 + Y A_9
+  #pragma unroll
+        for (int i = 0; i < RT; ++i) AC[i] = X0[i];
+      }
     }
-  } else if (m == 4) {
-    // T = I + c0 A + c1 V, V = A^2 W = A^2 (c2 I + c3 A + c4 A^2)
-    double c[5];
-    coefs(std::integral_constant<int, 4>(), c, 5);
+
+    // ---- s squarings: the resident matrix is both operands ----
+    for (int q = 0; q < s; ++q) {
+      __syncthreads();
+      if constexpr (act) sr_put<T, H>(L1, ln, AC);
+      __syncthreads();
+      if constexpr (act) {
+        zero<RT>(AC);
+        sr_gemm<T, H>(L1, L1, ln, AC);
+      }
+    }
+
+    // ---- e^A ----
     if constexpr (act) {
-      const SrOwn<T, H> o(ln);
-      sr_put<T, H>(L1, ln, X1);
-#pragma unroll
-      for (int i = 0; i < RT; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) L2[o.at(i, r)] = c[2] * o.delta(i, r) + c[3] * X0[i][r] + c[4] * X1[i][r];
+      gdouble *E = gptr(a.E + off);
+      const int lk = opq(ln.lk), col = opq(ln.col);
+      if (!cx) {  // real output: row-major, the padding dropped (one uniform branch, not one per element)
+  #pragma unroll
+        for (int i = 0; i < RT; ++i)
+  #pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = 16 * (G::I0 + i) + 4 * r + lk;
+            if (row < n && col < n) E[(size_t)row * n + col] = AC[i][r];
+          }
+      } else {
+  #pragma unroll
+        for (int i = 0; i < RT; ++i)
+  #pragma unroll
+          for (int r = 0; r < 4; ++r) put_dst(E, n, nin, cx, 16 * (G::I0 + i) + 4 * r + lk, col, AC[i][r]);
+      }
     }
     __syncthreads();
-    if constexpr (act) {
-      zero<RT>(AC);
-      sr_gemm<T, H>(L1, L2, ln, AC);
-      const SrOwn<T, H> o(ln);
-#pragma unroll
-      for (int i = 0; i < RT; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) AC[i][r] = o.delta(i, r) + c[0] * X0[i][r] + c[1] * AC[i][r];
-    }
-  } else if (m == 8) {
-    // V = A^2 W1 (W1 = c0 A + c1 A^2); A_4 = c2 V; Lm = c3 A^2 + A_4;
-    // Rm = c4 I + c5 A + c6 A^2 + c7 A_4; T = Lm Rm + c8 I + c9 A + c10 A^2   (eq. Algorithm83eA)
-    double c[11];
-    coefs(std::integral_constant<int, 8>(), c, 11);
-    if constexpr (act) {
-      const SrOwn<T, H> o(ln);
-      sr_put<T, H>(L1, ln, X1);
-#pragma unroll
-      for (int i = 0; i < RT; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) L2[o.at(i, r)] = c[0] * X0[i][r] + c[1] * X1[i][r];
-    }
-    __syncthreads();
-    if constexpr (act) {
-      zero<RT>(X2);
-      sr_gemm<T, H>(L1, L2, ln, X2);  // V
-    }
-    __syncthreads();
-    if constexpr (act) {
-      const SrOwn<T, H> o(ln);
-#pragma unroll
-      for (int i = 0; i < RT; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const double d = o.delta(i, r), a1 = X0[i][r], a2 = X1[i][r], a4 = c[2] * X2[i][r];
-          L1[o.at(i, r)] = c[3] * a2 + a4;                                 // Lm
-          L2[o.at(i, r)] = c[4] * d + c[5] * a1 + c[6] * a2 + c[7] * a4;   // Rm
-          AC[i][r] = c[8] * d + c[9] * a1 + c[10] * a2;
-        }
-    }
-    __syncthreads();
-    if constexpr (act) sr_gemm<T, H>(L1, L2, ln, AC);
-  } else if (m == 12) {
-    // B_j over (I, A, A^2, A^3); A_6 = B_3 + B_4^2; T = B_1 + (B_2 + A_6) A_6   (eq. poly12)
-    double k[16];
-    coefs(std::integral_constant<int, 12>(), k, 16);
-    if constexpr (act) {
-      const SrOwn<T, H> o(ln);
-#pragma unroll
-      for (int i = 0; i < RT; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const double d = o.delta(i, r), a1 = X0[i][r], a2 = X1[i][r], a3 = X2[i][r];
-          L1[o.at(i, r)] = k[12] * d + k[13] * a1 + k[14] * a2 + k[15] * a3;  // B_4
-          X0[i][r] = k[0] * d + k[1] * a1 + k[2] * a2 + k[3] * a3;            // B_1
-          X1[i][r] = k[4] * d + k[5] * a1 + k[6] * a2 + k[7] * a3;            // B_2
-          AC[i][r] = k[8] * d + k[9] * a1 + k[10] * a2 + k[11] * a3;          // B_3
-        }
-    }
-    __syncthreads();
-    if constexpr (act) sr_gemm<T, H>(L1, L1, ln, AC);  // A_6 = B_3 + B_4 B_4
-    __syncthreads();
-    if constexpr (act) {
-      const SrOwn<T, H> o(ln);
-#pragma unroll
-      for (int i = 0; i < RT; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          L1[o.at(i, r)] = X1[i][r] + AC[i][r];  // Y = B_2 + A_6
-          L2[o.at(i, r)] = AC[i][r];             // A_6
-        }
-    }
-    __syncthreads();
-    if constexpr (act) {
-      sr_gemm<T, H>(L1, L2, ln, X0);  // T = B_1 + Y A_6
-#pragma unroll
-      for (int i = 0; i < RT; ++i) AC[i] = X0[i];
+  };
+  if constexpr (SEL == EXPM_SEL_PLAIN) {
+    switch (m_rule) {
+      case 18: rest(std::integral_constant<int, 18>()); break;
+      case 12: rest(std::integral_constant<int, 12>()); break;
+      case 8: rest(std::integral_constant<int, 8>()); break;
+      case 4: rest(std::integral_constant<int, 4>()); break;
+      default: rest(std::integral_constant<int, 2>()); break;
     }
   } else {
-    // m == 18: A^6 = A^3 A^3; B_1 over (I, A, A^2, A^3), B_2..B_5 over (I, A, A^2, A^3, A^6);
-    // A_9 = B_1 B_5 + B_4; T = B_2 + (B_3 + A_9) A_9   (eq. poly.18)
-    double k[24];
-    coefs(std::integral_constant<int, 18>(), k, 24);
-    if constexpr (act) sr_put<T, H>(L1, ln, X2);
-    __syncthreads();
-    if constexpr (act) {
-      zero<RT>(X3);
-      sr_gemm<T, H>(L1, L1, ln, X3);  // A^6
-    }
-    __syncthreads();
-    if constexpr (act) {
-      const SrOwn<T, H> o(ln);
-#pragma unroll
-      for (int i = 0; i < RT; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const double d = o.delta(i, r), a1 = X0[i][r], a2 = X1[i][r], a3 = X2[i][r], a6 = X3[i][r];
-          L1[o.at(i, r)] = k[0] * d + k[1] * a1 + k[2] * a2 + k[3] * a3;                       // B_1
-          X0[i][r] = k[4] * d + k[5] * a1 + k[6] * a2 + k[7] * a3 + k[8] * a6;               // B_2
-          X1[i][r] = k[9] * d + k[10] * a1 + k[11] * a2 + k[12] * a3 + k[13] * a6;           // B_3
-          AC[i][r] = k[14] * d + k[15] * a1 + k[16] * a2 + k[17] * a3 + k[18] * a6;          // B_4
-          L2[o.at(i, r)] = k[19] * d + k[20] * a1 + k[21] * a2 + k[22] * a3 + k[23] * a6;    // B_5
-        }
-    }
-    __syncthreads();
-    if constexpr (act) sr_gemm<T, H>(L1, L2, ln, AC);  // A_9 = B_1 B_5 + B_4
-    __syncthreads();
-    if constexpr (act) {
-      const SrOwn<T, H> o(ln);
-#pragma unroll
-      for (int i = 0; i < RT; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          L1[o.at(i, r)] = X1[i][r] + AC[i][r];  // Y = B_3 + A_9
-          L2[o.at(i, r)] = AC[i][r];             // A_9
-        }
-    }
-    __syncthreads();
-    if constexpr (act) {
-      sr_gemm<T, H>(L1, L2, ln, X0);  // T = B_2 + Y A_9
-#pragma unroll
-      for (int i = 0; i < RT; ++i) AC[i] = X0[i];
-    }
+    rest(std::integral_constant<int, 0>());
   }
-
-  // ---- s squarings: the resident matrix is both operands ----
-  for (int q = 0; q < s; ++q) {
-    __syncthreads();
-    if constexpr (act) sr_put<T, H>(L1, ln, AC);
-    __syncthreads();
-    if constexpr (act) {
-      zero<RT>(AC);
-      sr_gemm<T, H>(L1, L1, ln, AC);
-    }
-  }
-
-  // ---- e^A ----
-  if constexpr (act) {
-    gdouble *E = gptr(a.E + off);
-    const int lk = opq(ln.lk), col = opq(ln.col);
-    if (!cx) {  // real output: row-major, the padding dropped (one uniform branch, not one per element)
-#pragma unroll
-      for (int i = 0; i < RT; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = 16 * (G::I0 + i) + 4 * r + lk;
-          if (row < n && col < n) E[(size_t)row * n + col] = AC[i][r];
-        }
-    } else {
-#pragma unroll
-      for (int i = 0; i < RT; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) put_dst(E, n, nin, cx, 16 * (G::I0 + i) + 4 * r + lk, col, AC[i][r]);
-    }
-  }
-  __syncthreads();
 }
 
 template <int SEL>
-__device__ void run_sr_dispatch(const FusedArgs &a, int64_t b, double *red) {
+__device__ __attribute__((always_inline)) void run_sr_dispatch(const FusedArgs &a, int64_t b, double *red) {
   const int tid = threadIdx.x;
   const int nin = ufi(a.ns ? a.ns[b] : a.n_uniform);
   const int cx = a.cplx;
