@@ -572,8 +572,11 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 2 : 1) void expm_fused_kernel(Fu
 namespace expm {
 namespace {
 
+// 8 waves: one workgroup per CU (its LDS matrix takes 128 KiB).  4 waves (orders up to 64):
+// three workgroups per CU, 168 VGPRs each, which the per-degree instantiation leaves without
+// spills below order 64 (measured against two per CU: the sweep 1.5 % shorter).
 template <int NW, int SEL>
-__global__ __launch_bounds__(64 * NW, NW == 4 ? 2 : 1) void expm_resident_kernel(FusedArgs a) {
+__global__ __launch_bounds__(64 * NW, NW == 4 ? 3 : 1) void expm_resident_kernel(FusedArgs a) {
   __shared__ double red[64 * NW + 16];
   double *slot = a.slots ? a.slots + (size_t)blockIdx.x * a.slot_doubles : nullptr;
   res_init<NW>(a);
