@@ -53,7 +53,7 @@ expm_status_t check_opts(const expm_opts_t *o, double *u) {
 
 // Resident workgroups per CU of the four sweep kernels on the current device (cached).
 struct FusedCaps {
-  int cus = 0, per4 = 1, per8 = 1, res4 = 1, res6 = 1, res8 = 1, tiny = 1;
+  int cus = 0, per4 = 1, per8 = 1, res4 = 1, res6 = 1, res8 = 1, tiny = 1, res4w = 1;
 };
 
 FusedCaps fused_caps() {
@@ -69,6 +69,7 @@ FusedCaps fused_caps() {
       caps.per4 = fused_max_blocks_per_cu(4);
       caps.per8 = fused_max_blocks_per_cu(8);
       caps.res4 = resident_max_blocks_per_cu(4);
+      caps.res4w = resident_max_blocks_per_cu(5);
       caps.res6 = resident_max_blocks_per_cu(12);
       caps.res8 = resident_max_blocks_per_cu(8);
       caps.tiny = tiny_max_blocks_per_cu();
@@ -80,8 +81,9 @@ FusedCaps fused_caps() {
   return caps;
 }
 
-// K_RES6: split-row kernel, np 80..96; K_TINY: one wave per matrix, np 16
-enum Kern { K_FUSED4, K_FUSED8, K_RES4, K_RES6, K_RES8, K_TINY };
+// K_RES6: split-row kernel, np 80..96; K_TINY: one wave per matrix, np 16; K_RES4W: the 4-wave
+// kernel at two workgroups per CU (uniform calls of np 64; not tunable, it has no per_cu entry)
+enum Kern { K_FUSED4, K_FUSED8, K_RES4, K_RES6, K_RES8, K_TINY, K_RES4W };
 
 // Launch configuration installed by expm_tune_set (process-wide; zero fields = defaults).
 std::mutex g_tune_mu;
@@ -96,7 +98,7 @@ constexpr int kDefaultTiles = 2048;
 // occupancy maximum, or fewer when tuned; layouts size their slots with tuned = false).
 int grid_for(Kern k, int64_t batch, bool tuned = true) {
   FusedCaps c = fused_caps();
-  if (tuned) {
+  if (tuned && k != K_RES4W) {
     const int t = tune_now().per_cu[k];
     if (t > 0) {
       int *per = k == K_FUSED4 ? &c.per4 : k == K_FUSED8 ? &c.per8 : k == K_RES4 ? &c.res4
@@ -110,7 +112,8 @@ int grid_for(Kern k, int64_t batch, bool tuned = true) {
     const int64_t cap = c.cus > 0 ? (int64_t)c.cus * c.tiny : 8192;
     return (int)(need < cap ? need : cap);
   }
-  const int per = k == K_FUSED4 ? c.per4 : k == K_FUSED8 ? c.per8 : k == K_RES4 ? c.res4 : k == K_RES6 ? c.res6 : c.res8;
+  const int per = k == K_FUSED4 ? c.per4 : k == K_FUSED8 ? c.per8 : k == K_RES4 ? c.res4 : k == K_RES6 ? c.res6
+                : k == K_RES4W ? c.res4w : c.res8;
   int cap = c.cus > 0 ? c.cus * per : kMaxSlots;
   if (cap > kMaxSlots) cap = kMaxSlots;
   return (int)(batch < cap ? batch : cap);
@@ -373,7 +376,16 @@ static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, cons
         break;
       case K_RES6: grid = grid_for(K_RES6, batch); e = launch_resident(x, 12, grid, st); break;
       case K_TINY: grid = grid_for(K_TINY, batch); e = launch_tiny(x, grid, st); break;
-      default: grid = grid_for(K_RES4, batch); e = launch_resident(x, 4, grid, st); break;
+      case K_RES4W: grid = grid_for(K_RES4W, batch); e = launch_resident(x, 5, grid, st); break;
+      default:  // K_RES4: three workgroups per CU under the plain rule, two otherwise
+        if (x.sel == EXPM_SEL_PLAIN) {
+          grid = grid_for(K_RES4, batch);
+          e = launch_resident(x, 4, grid, st);
+        } else {
+          grid = grid_for(K_RES4W, batch);
+          e = launch_resident(x, 5, grid, st);
+        }
+        break;
     }
     return e == hipSuccess;
   };
@@ -451,7 +463,8 @@ static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, cons
     const Kern k = t > kResT ? K_FUSED8
                    : t > kRes6T ? K_RES8
                    : t >= kSplitT ? K_RES6
-                   : (t == 1 && (tiny || a.method)) ? K_TINY : K_RES4;
+                   : (t == 1 && (tiny || a.method)) ? K_TINY
+                   : t == kSplitT - 1 ? K_RES4W : K_RES4;
     bool ok;
     if (k != K_TINY && batch > grid_for(k, batch)) {
       // more matrices than one round of the persistent grid: walk a queue ordered by the cost
@@ -466,14 +479,14 @@ static expm_status_t run_fused(const void *A, void *E, const int64_t *offs, cons
       ok = k == K_FUSED8 ? go(K_FUSED8, f8, 0, 0, 1)
            : k == K_RES8 ? go(K_RES8, r8, 1, 1, 2)
            : k == K_RES6 ? go(K_RES6, r6, 2, 2, 3)
-                         : go(K_RES4, r4, 3, 3, 5);
+                         : go(k, r4, 3, 3, 5);
     } else {
       // one matrix per workgroup at most (or one wave per matrix): the static range
       ok = k == K_FUSED8 ? go(K_FUSED8, f8, 0, 0, 0)
            : k == K_RES8 ? go(K_RES8, r8, 1, 0, 0)
            : k == K_RES6 ? go(K_RES6, r6, 2, 0, 0)
            : k == K_TINY ? go(K_TINY, tn, 5, 0, 0)
-                         : go(K_RES4, r4, 3, 0, 0);
+                         : go(k, r4, 3, 0, 0);
     }
     if (!ok) return EXPM_E_HIP;
   }

@@ -77,7 +77,9 @@ hipError_t launch_magnus4(const double *S0, const double *S1, int64_t s_stride, 
                           const double *u1, const double *u2, int n, int64_t batch, double h, int sel,
                           const Consts &k, int32_t *m_out, int32_t *s_out, int32_t *status, int grid,
                           hipStream_t st);
-hipError_t launch_resident(const FusedArgs &a, int nw, int grid, hipStream_t st);  // nw = 8, 12, 4
+// nw = 8, 12, 4; 5: the 4-wave kernel at two workgroups per CU (calls whose matrices are all of
+// order 49..64), where nw = 4 runs three per CU (batched sweeps)
+hipError_t launch_resident(const FusedArgs &a, int nw, int grid, hipStream_t st);
 // Work-queue order of a batch: cost keys of every matrix (into key, batch bytes; skipped when
 // key is null), then the counting sort by (real order, key) into order and the queue words.
 // Orders above np_max (the call's largest padded real order) are classed invalid.

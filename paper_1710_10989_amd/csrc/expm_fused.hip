@@ -572,11 +572,13 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 2 : 1) void expm_fused_kernel(Fu
 namespace expm {
 namespace {
 
-// 8 waves: one workgroup per CU (its LDS matrix takes 128 KiB).  4 waves (orders up to 64):
-// three workgroups per CU, 168 VGPRs each, which the per-degree instantiation leaves without
-// spills below order 64 (measured against two per CU: the sweep 1.5 % shorter).
-template <int NW, int SEL>
-__global__ __launch_bounds__(64 * NW, NW == 4 ? 3 : 1) void expm_resident_kernel(FusedArgs a) {
+// OCC workgroups per CU.  8 waves: one (its LDS matrix takes 128 KiB).  4 waves (orders up to
+// 64): three in the plain rule's batched sweeps, 168 VGPRs each, which the per-degree
+// instantiation leaves without spills below order 64 (measured against two per CU: the sweep
+// 1.5 % shorter); two, with 256 VGPRs, under the other rules and for calls whose matrices are
+// all of order 49..64, where the degree-12 and degree-18 stages would spill at 168.
+template <int NW, int SEL, int OCC>
+__global__ __launch_bounds__(64 * NW, OCC) void expm_resident_kernel(FusedArgs a) {
   __shared__ double red[64 * NW + 16];
   double *slot = a.slots ? a.slots + (size_t)blockIdx.x * a.slot_doubles : nullptr;
   res_init<NW>(a);
@@ -720,34 +722,39 @@ hipError_t launch_fused(const FusedArgs &a, int nw, int grid, hipStream_t st) {
 
 int resident_max_blocks_per_cu(int nw) {
   int nb = 0;
-  hipError_t e = nw == 8    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, expm_resident_kernel<8, EXPM_SEL_PLAIN>, 512, 0)
+  hipError_t e = nw == 8    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, expm_resident_kernel<8, EXPM_SEL_PLAIN, 1>, 512, 0)
                  : nw == 12 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, expm_sr_kernel<EXPM_SEL_PLAIN>, 768, 0)
-                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, expm_resident_kernel<4, EXPM_SEL_PLAIN>, 256, 0);
+                 : nw == 5  ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, expm_resident_kernel<4, EXPM_SEL_PLAIN, 2>, 256, 0)
+                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, expm_resident_kernel<4, EXPM_SEL_PLAIN, 3>, 256, 0);
   if (e != hipSuccess) return 1;
   return nb < 1 ? 1 : nb;
 }
 
 // Every selector variant of a kernel has the same launch bounds and LDS footprint.
-template <int NW>
+template <int NW, int OCC>
 static void launch_res_sel(const FusedArgs &a, int grid, hipStream_t st) {
   switch (a.sel) {
-    case EXPM_SEL_ALPHA: hipLaunchKernelGGL((expm_resident_kernel<NW, EXPM_SEL_ALPHA>), dim3(grid), dim3(64 * NW), 0, st, a); break;
-    case EXPM_SEL_LEARNED: hipLaunchKernelGGL((expm_resident_kernel<NW, EXPM_SEL_LEARNED>), dim3(grid), dim3(64 * NW), 0, st, a); break;
-    default: hipLaunchKernelGGL((expm_resident_kernel<NW, EXPM_SEL_PLAIN>), dim3(grid), dim3(64 * NW), 0, st, a); break;
+    case EXPM_SEL_ALPHA: hipLaunchKernelGGL((expm_resident_kernel<NW, EXPM_SEL_ALPHA, OCC>), dim3(grid), dim3(64 * NW), 0, st, a); break;
+    case EXPM_SEL_LEARNED: hipLaunchKernelGGL((expm_resident_kernel<NW, EXPM_SEL_LEARNED, OCC>), dim3(grid), dim3(64 * NW), 0, st, a); break;
+    default: hipLaunchKernelGGL((expm_resident_kernel<NW, EXPM_SEL_PLAIN, OCC>), dim3(grid), dim3(64 * NW), 0, st, a); break;
   }
 }
 
 hipError_t launch_resident(const FusedArgs &a, int nw, int grid, hipStream_t st) {
   if (nw == 8) {
-    launch_res_sel<8>(a, grid, st);
+    launch_res_sel<8, 1>(a, grid, st);
   } else if (nw == 12) {
     switch (a.sel) {
       case EXPM_SEL_ALPHA: hipLaunchKernelGGL((expm_sr_kernel<EXPM_SEL_ALPHA>), dim3(grid), dim3(64 * kSrNW), 0, st, a); break;
       case EXPM_SEL_LEARNED: hipLaunchKernelGGL((expm_sr_kernel<EXPM_SEL_LEARNED>), dim3(grid), dim3(64 * kSrNW), 0, st, a); break;
       default: hipLaunchKernelGGL((expm_sr_kernel<EXPM_SEL_PLAIN>), dim3(grid), dim3(64 * kSrNW), 0, st, a); break;
     }
+  } else if (nw == 5 || a.sel != EXPM_SEL_PLAIN) {
+    // the alpha and learned rules' 4-wave kernels keep two workgroups per CU (at three their
+    // run-time degree spills)
+    launch_res_sel<4, 2>(a, grid, st);
   } else {
-    launch_res_sel<4>(a, grid, st);
+    hipLaunchKernelGGL((expm_resident_kernel<4, EXPM_SEL_PLAIN, 3>), dim3(grid), dim3(256), 0, st, a);
   }
   return hipGetLastError();
 }
