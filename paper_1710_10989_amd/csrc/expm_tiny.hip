@@ -102,7 +102,7 @@ __device__ inline double t_norm1(const q4 &x) {
 
 // 1-norm of an interleaved complex nin x nin matrix (nin <= 8), sum_i |z_ij| maximised over the
 // columns j: lane j < nin sums its column.
-__device__ inline double t_norm1_z(const double *A, int nin) {
+__device__ __noinline__ double t_norm1_z(const double *A, int nin) {
   cgdouble *Ag = gptr(A);
   const int l = lane_id();
   double s = 0.0;
@@ -634,15 +634,17 @@ __global__ __launch_bounds__(64 * kTinyW, SEL == EXPM_SEL_PLAIN ? 4 : 2) void ex
     const int nin = cur.nin, n = cur.n;
     const int64_t off = cur.off;
     const bool head = lane_id() == 0;
-    double eta = 0.0;  // ||A||_1, taken once the input is known to be finite
+    // ||A||_1 (a complex input's is that of A itself); taken only when the input is finite
+    const bool finite = nin >= 1 && n <= 16 &&
+                        !__any(!isfinite(Xc[0]) || !isfinite(Xc[1]) || !isfinite(Xc[2]) || !isfinite(Xc[3]));
+    const double eta = !finite ? 0.0 : cx ? t_norm1_z(a.A + off, nin) : t_norm1(Xc);
     if (nin < 1 || n > 16) {
       if (head) {
         a.m_out[b] = -1; a.s_out[b] = -1;
         if (a.status) a.status[b] = (nin < 1 || n > a.np_max) ? EXPM_E_INVALID_ARG : EXPM_E_UNSUPPORTED;
       }
-    } else if (__any(!isfinite(Xc[0]) || !isfinite(Xc[1]) || !isfinite(Xc[2]) || !isfinite(Xc[3])) ||
-               !((eta = cx ? t_norm1_z(a.A + off, nin) : t_norm1(Xc)) <= __DBL_MAX__)) {
-      // (a 1-norm that overflows is refused likewise; a complex input's is that of A itself)
+    } else if (!finite || !(eta <= __DBL_MAX__)) {
+      // (a 1-norm that overflows is refused like a non-finite entry)
       if (a.E)
         for (int e = lane_id(); e < nin * nin * (cx ? 2 : 1); e += 64) a.E[off + e] = __builtin_nan("");
       if (head) {
