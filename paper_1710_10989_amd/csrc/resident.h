@@ -485,12 +485,15 @@ __device__ __attribute__((always_inline)) void run_res(const FusedArgs &a, int64
       need3 = m_plain >= 12;
     }
 
-    // From here on A is read elementwise only: at np >= 96 on 8 waves it waits in the
-    // workgroup's HBM slot (region 0), so that no phase holds more than two register matrices
-    // besides the accumulator.
+    // From here on A is read elementwise only.  At np >= 96 on 8 waves, B_3 of the degree-18
+    // stage waits in the workgroup's HBM slot (region 1), and under the alpha and learned rules
+    // (one body for every degree) so do A and B_1 of the degree-12 stage (region 0), so that no
+    // phase holds more than two register matrices besides the accumulator.  Under the plain
+    // rule each degree has registers of its own and A stays in X0.
     constexpr bool kPark = NW == 8 && T >= kResParkT;
+    constexpr bool kParkA = kPark && MC == 0;
     const Park<NW, T> P0(slot, 0), P1(slot, 1);
-    if constexpr (kPark) {
+    if constexpr (kParkA) {
       if constexpr (act) P0.put_all(X0);
     }
 
@@ -564,7 +567,7 @@ __device__ __attribute__((always_inline)) void run_res(const FusedArgs &a, int64
       else { coefs(std::integral_constant<int, 1>(), c, 1); c[1] = 0.0; }
       if constexpr (act) {
         const Own<T> o(ln);
-        each_elem<kPark>(P0, X0, [&](int i, int r, double a1r) {
+        each_elem<kParkA>(P0, X0, [&](int i, int r, double a1r) {
           const double a1 = x1(a1r);
           X1[i][r] = o.delta(i, r) + c[0] * a1 + (m == 2 ? c[1] * X1[i][r] : 0.0);
         });
@@ -578,7 +581,7 @@ __device__ __attribute__((always_inline)) void run_res(const FusedArgs &a, int64
       __syncthreads();
       if constexpr (act) {
         const Own<T> o(ln);
-        each_elem<kPark>(P0, X0, [&](int i, int r, double a1r) {
+        each_elem<kParkA>(P0, X0, [&](int i, int r, double a1r) {
           const double a1 = x1(a1r); L[o.at(i, r)] = c[3] * a1 + c[4] * X1[i][r]; });
       }
       __syncthreads();
@@ -586,7 +589,7 @@ __device__ __attribute__((always_inline)) void run_res(const FusedArgs &a, int64
         zero<T>(AC);
         rgemm_reg<T>(L, ln, X1, AC);
         const Own<T> o(ln);
-        each_elem<kPark>(P0, X0, [&](int i, int r, double a1r) {
+        each_elem<kParkA>(P0, X0, [&](int i, int r, double a1r) {
           const double a1 = x1(a1r);
           AC[i][r] = o.delta(i, r) + c[0] * a1 + c[1] * (AC[i][r] + c[2] * X1[i][r]);
         });
@@ -599,7 +602,7 @@ __device__ __attribute__((always_inline)) void run_res(const FusedArgs &a, int64
       __syncthreads();
       if constexpr (act) {
         const Own<T> o(ln);
-        each_elem<kPark>(P0, X0, [&](int i, int r, double a1r) {
+        each_elem<kParkA>(P0, X0, [&](int i, int r, double a1r) {
           const double a1 = x1(a1r); L[o.at(i, r)] = c[0] * a1 + c[1] * X1[i][r]; });
       }
       __syncthreads();
@@ -610,7 +613,7 @@ __device__ __attribute__((always_inline)) void run_res(const FusedArgs &a, int64
       __syncthreads();
       if constexpr (act) {
         const Own<T> o(ln);
-        each_elem<kPark>(P0, X0, [&](int i, int r, double a1r) {
+        each_elem<kParkA>(P0, X0, [&](int i, int r, double a1r) {
           const double a1 = x1(a1r);
           const double d = o.delta(i, r), a2 = X1[i][r], a4 = c[2] * AC[i][r];
           L[o.at(i, r)] = c[3] * a2 + a4;                                 // Lm
@@ -627,12 +630,12 @@ __device__ __attribute__((always_inline)) void run_res(const FusedArgs &a, int64
       __syncthreads();
       if constexpr (act) {
         const Own<T> o(ln);
-        each_elem<kPark>(P0, X0, [&](int i, int r, double a1r) {
+        each_elem<kParkA>(P0, X0, [&](int i, int r, double a1r) {
           const double a1 = x1(a1r);
           const double d = o.delta(i, r), a2 = X1[i][r], a3 = X2[i][r];
           L[o.at(i, r)] = k[12] * d + k[13] * a1 + k[14] * a2 + k[15] * a3;  // B_4
           const double b1 = k[0] * d + k[1] * a1 + k[2] * a2 + k[3] * a3;
-          if constexpr (kPark) P0.put(i, r, b1);
+          if constexpr (kParkA) P0.put(i, r, b1);
           else X0[i][r] = b1;
           X1[i][r] = k[4] * d + k[5] * a1 + k[6] * a2 + k[7] * a3;   // B_2
           X2[i][r] = k[8] * d + k[9] * a1 + k[10] * a2 + k[11] * a3;  // B_3
@@ -647,7 +650,7 @@ __device__ __attribute__((always_inline)) void run_res(const FusedArgs &a, int64
       __syncthreads();
       if constexpr (act) {
         to_lds<T>(L, ln, X1);
-        if constexpr (kPark) P0.get_all(X1);  // B_1
+        if constexpr (kParkA) P0.get_all(X1);  // B_1
         else {
   #pragma unroll
           for (int i = 0; i < T; ++i) X1[i] = X0[i];
@@ -674,7 +677,7 @@ __device__ __attribute__((always_inline)) void run_res(const FusedArgs &a, int64
       __syncthreads();
       if constexpr (act) {
         const Own<T> o(ln);
-        each_elem<kPark>(P0, X0, [&](int i, int r, double a1r) {
+        each_elem<kParkA>(P0, X0, [&](int i, int r, double a1r) {
           const double a1 = x1(a1r);
           const double d = o.delta(i, r), a2 = X1[i][r], a3 = L[o.at(i, r)], a6 = AC[i][r];
           L[o.at(i, r)] = k[0] * d + k[1] * a1 + k[2] * a2 + k[3] * a3;  // B_1
