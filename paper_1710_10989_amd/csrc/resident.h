@@ -60,6 +60,15 @@ __device__ inline int opq(int x) {
 // branches, not exec-masked regions that keep both sides' values alive.
 __device__ inline int ufi(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// A wave-uniform address moved to scalar registers (a buffer resource built on it then needs
+// no per-access waterfall over the lanes' copies).
+__device__ inline void *ufp(const void *p) {
+  const unsigned long long u = (unsigned long long)p;
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)u);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(u >> 32));
+  return (void *)(((unsigned long long)hi << 32) | lo);
+}
+
 // A wave-uniform double moved to scalar registers (coefficients of the linear combinations).
 __device__ inline double uni(double x) {
   const long long u = __double_as_longlong(x);
@@ -350,34 +359,45 @@ __device__ __attribute__((always_inline)) void run_res(const FusedArgs &a, int64
   if constexpr (act) {
     cgdouble *Ag = gptr(a.A + off);
     const int lk = opq(ln.lk), c = opq(ln.col);
-    // every lane loads (indices clamped into the matrix) and zeroes what lies outside, so the
-    // loads are issued back to back instead of one masked branch at a time
     const bool cin = c < n;
     const int cc = cin ? c : n - 1;
-    const int ci = cc < nin ? cc : cc - nin;
+    if (!cx) {
+      // real input: one buffer load per element at a 32-bit byte offset, issued back to back
+      // with no per-element branch or 64-bit address; padding rows and columns lie past the
+      // buffer's n^2 elements and read as zero
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(ufp(a.A + off), 0, n * n * 8, kBufWord3);
+      const int lb = cin ? (lk * n + c) * 8 : n * n * 8;
 #pragma unroll
-    for (int i = 0; i < T; ++i)
+      for (int i = 0; i < T; ++i)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = 16 * i + 4 * r + lk;
-        const int rr = row < n ? row : n - 1;
-        if (!cx) {
-          X0[i][r] = Ag[(size_t)rr * n + cc];
-        } else {
+        for (int r = 0; r < 4; ++r) {
+          const u2v v = __builtin_amdgcn_raw_buffer_load_b64(rs, lb + (16 * i + 4 * r) * n * 8, 0, 0);
+          X0[i][r] = __longlong_as_double((long long)(((unsigned long long)v[1] << 32) | v[0]));
+        }
+    } else {
+      // complex input (real form): every lane loads (indices clamped into the matrix) and
+      // zeroes what lies outside
+      const int ci = cc < nin ? cc : cc - nin;
+#pragma unroll
+      for (int i = 0; i < T; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * i + 4 * r + lk;
+          const int rr = row < n ? row : n - 1;
           const int ri = rr < nin ? rr : rr - nin;
           const bool im = (rr < nin) != (cc < nin);
           X0[i][r] = Ag[2 * ((size_t)ri * nin + ci) + (im ? 1 : 0)];
         }
-      }
 #pragma unroll
-    for (int i = 0; i < T; ++i)
+      for (int i = 0; i < T; ++i)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = 16 * i + 4 * r + lk;
-        double x = X0[i][r];
-        if (cx && (row < nin) && !(cc < nin)) x = -x;  // -Y block of the real form
-        X0[i][r] = (row < n && cin) ? x : 0.0;
-      }
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * i + 4 * r + lk;
+          double x = X0[i][r];
+          if ((row < nin) && !(cc < nin)) x = -x;  // -Y block of the real form
+          X0[i][r] = (row < n && cin) ? x : 0.0;
+        }
+    }
 #pragma unroll
     for (int i = 0; i < T; ++i)
 #pragma unroll
@@ -722,13 +742,17 @@ __device__ __attribute__((always_inline)) void run_res(const FusedArgs &a, int64
     if constexpr (act) {
       gdouble *E = gptr(a.E + off);
       const int lk = opq(ln.lk), col = opq(ln.col);
-      if (!cx) {  // real output: row-major, the padding dropped (one uniform branch, not one per element)
+      if (!cx) {
+        // real output: row-major through a buffer over the n^2 elements; stores of padding
+        // rows and columns fall past its end and are dropped
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(ufp(a.E + off), 0, n * n * 8, kBufWord3);
+        const int lb = col < n ? (lk * n + col) * 8 : n * n * 8;
   #pragma unroll
         for (int i = 0; i < T; ++i)
   #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int row = 16 * i + 4 * r + lk;
-            if (row < n && col < n) E[(size_t)row * n + col] = AC[i][r];
+            const unsigned long long u = (unsigned long long)__double_as_longlong(AC[i][r]);
+            __builtin_amdgcn_raw_buffer_store_b64(u2v{(unsigned)u, (unsigned)(u >> 32)}, rs, lb + (16 * i + 4 * r) * n * 8, 0, 0);
           }
       } else {
   #pragma unroll
