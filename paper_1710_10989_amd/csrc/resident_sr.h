@@ -146,21 +146,31 @@ __device__ __attribute__((always_inline)) void run_sr(const FusedArgs &a, int64_
     const int lk = opq(ln.lk), c = opq(ln.col);
     const bool cin = c < n;
     const int cc = cin ? c : n - 1;
-    const int ci = cc < nin ? cc : cc - nin;
+    if (!cx) {
+      // real input: one buffer load per element at a 32-bit byte offset; padding rows and
+      // columns lie past the buffer's n^2 elements and read as zero
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(ufp(a.A + off), 0, n * n * 8, kBufWord3);
+      const int lb = cin ? (lk * n + c) * 8 : n * n * 8;
 #pragma unroll
-    for (int i = 0; i < RT; ++i)
+      for (int i = 0; i < RT; ++i)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = 16 * (G::I0 + i) + 4 * r + lk;
-        const int rr = row < n ? row : n - 1;
-        if (!cx) {
-          X0[i][r] = Ag[(size_t)rr * n + cc];
-        } else {
+        for (int r = 0; r < 4; ++r) {
+          const u2v v = __builtin_amdgcn_raw_buffer_load_b64(rs, lb + (16 * (G::I0 + i) + 4 * r) * n * 8, 0, 0);
+          X0[i][r] = __longlong_as_double((long long)(((unsigned long long)v[1] << 32) | v[0]));
+        }
+    } else {
+      const int ci = cc < nin ? cc : cc - nin;
+#pragma unroll
+      for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * (G::I0 + i) + 4 * r + lk;
+          const int rr = row < n ? row : n - 1;
           const int ri = rr < nin ? rr : rr - nin;
           const bool im = (rr < nin) != (cc < nin);
           X0[i][r] = Ag[2 * ((size_t)ri * nin + ci) + (im ? 1 : 0)];
         }
-      }
+    }
 #pragma unroll
     for (int i = 0; i < RT; ++i)
 #pragma unroll
@@ -484,13 +494,18 @@ __device__ __attribute__((always_inline)) void run_sr(const FusedArgs &a, int64_
     if constexpr (act) {
       gdouble *E = gptr(a.E + off);
       const int lk = opq(ln.lk), col = opq(ln.col);
-      if (!cx) {  // real output: row-major, the padding dropped (one uniform branch, not one per element)
+      if (!cx) {
+        // real output through a buffer over the n^2 elements; stores of padding rows and
+        // columns fall past its end and are dropped
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(ufp(a.E + off), 0, n * n * 8, kBufWord3);
+        const int lb = col < n ? (lk * n + col) * 8 : n * n * 8;
   #pragma unroll
         for (int i = 0; i < RT; ++i)
   #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int row = 16 * (G::I0 + i) + 4 * r + lk;
-            if (row < n && col < n) E[(size_t)row * n + col] = AC[i][r];
+            const unsigned long long u = (unsigned long long)__double_as_longlong(AC[i][r]);
+            __builtin_amdgcn_raw_buffer_store_b64(u2v{(unsigned)u, (unsigned)(u >> 32)}, rs,
+                                                  lb + (16 * (G::I0 + i) + 4 * r) * n * 8, 0, 0);
           }
       } else {
   #pragma unroll
