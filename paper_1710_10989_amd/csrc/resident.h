@@ -59,6 +59,10 @@ __device__ inline int opq(int x) {
 // Wave-uniform integer moved to a scalar register: branches on it are then uniform
 // branches, not exec-masked regions that keep both sides' values alive.
 __device__ inline int ufi(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ inline int64_t ufl(int64_t x) {
+  return (int64_t)(((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(x >> 32)) << 32) |
+                   (unsigned)__builtin_amdgcn_readfirstlane((int)x));
+}
 
 // A wave-uniform address moved to scalar registers (a buffer resource built on it then needs
 // no per-access waterfall over the lanes' copies).
@@ -779,10 +783,13 @@ __device__ __attribute__((always_inline)) void run_res(const FusedArgs &a, int64
 template <int NW, int SEL>
 __device__ __attribute__((always_inline)) void run_res_dispatch(const FusedArgs &a, int64_t b, double *slot, double *red) {
   const int tid = threadIdx.x;
-  const int nin = ufi(a.ns ? a.ns[b] : a.n_uniform);
+  // the order and the offset both depend on b only: both loads are issued before either is used
+  const int32_t nraw = a.ns ? ((__attribute__((address_space(1))) const int32_t *)a.ns)[b] : a.n_uniform;
+  const int64_t oraw = a.offs ? ((__attribute__((address_space(1))) const int64_t *)a.offs)[b] : 0;
+  const int nin = ufi(nraw);
   const int cx = a.cplx;
   const int n = cx ? 2 * nin : nin;
-  const int64_t off = (a.offs ? a.offs[b] : b * (int64_t)nin * nin) * (cx ? 2 : 1);
+  const int64_t off = (a.offs ? ufl(oraw) : b * (int64_t)nin * nin) * (cx ? 2 : 1);
   const int t = (n + 15) >> 4;
   const bool fits = NW == 8 ? (t > kRes6T && t <= kResT) : (t >= 1 && t < kSplitT);
   if (nin < 1 || n > a.np_max || !fits) {  // invalid order, or routed to the wrong variant

@@ -532,10 +532,13 @@ __device__ __attribute__((always_inline)) void run_sr(const FusedArgs &a, int64_
 template <int SEL>
 __device__ __attribute__((always_inline)) void run_sr_dispatch(const FusedArgs &a, int64_t b, double *red) {
   const int tid = threadIdx.x;
-  const int nin = ufi(a.ns ? a.ns[b] : a.n_uniform);
+  // the order and the offset both depend on b only: both loads are issued before either is used
+  const int32_t nraw = a.ns ? ((__attribute__((address_space(1))) const int32_t *)a.ns)[b] : a.n_uniform;
+  const int64_t oraw = a.offs ? ((__attribute__((address_space(1))) const int64_t *)a.offs)[b] : 0;
+  const int nin = ufi(nraw);
   const int cx = a.cplx;
   const int n = cx ? 2 * nin : nin;
-  const int64_t off = (a.offs ? a.offs[b] : b * (int64_t)nin * nin) * (cx ? 2 : 1);
+  const int64_t off = (a.offs ? ufl(oraw) : b * (int64_t)nin * nin) * (cx ? 2 : 1);
   const int t = (n + 15) >> 4;
   if (nin < 1 || n > a.np_max || t < kSrTMin || t > kSrTMax) {  // invalid order, or wrong variant
     if (tid == 0) {
