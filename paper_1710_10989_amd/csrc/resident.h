@@ -510,12 +510,15 @@ __device__ __attribute__((always_inline)) void run_res(const FusedArgs &a, int64
     }
 
     // From here on A is read elementwise only.  At np >= 96 on 8 waves, B_3 of the degree-18
-    // stage waits in the workgroup's HBM slot (region 1), and under the alpha and learned rules
-    // (one body for every degree) so do A and B_1 of the degree-12 stage (region 0), so that no
-    // phase holds more than two register matrices besides the accumulator.  Under the plain
-    // rule each degree has registers of its own and A stays in X0.
+    // stage waits in the workgroup's HBM slot (region 1) and B_1 of the degree-12 stage in
+    // region 0; under the alpha and learned rules (one body for every degree) so does A
+    // (region 0), so that no phase holds more than two register matrices besides the
+    // accumulator.  Under the plain rule each degree has registers of its own and A stays in
+    // X0 (B_1 of the degree-12 stage is still parked: held in registers through the product
+    // B_4 B_4 it was partly spilled and reloaded one element at a time).
     constexpr bool kPark = NW == 8 && T >= kResParkT;
     constexpr bool kParkA = kPark && MC == 0;
+    constexpr bool kParkB1 = kPark && (MC == 0 || MC == 12);
     const Park<NW, T> P0(slot, 0), P1(slot, 1);
     if constexpr (kParkA) {
       if constexpr (act) P0.put_all(X0);
@@ -659,7 +662,7 @@ __device__ __attribute__((always_inline)) void run_res(const FusedArgs &a, int64
           const double d = o.delta(i, r), a2 = X1[i][r], a3 = X2[i][r];
           L[o.at(i, r)] = k[12] * d + k[13] * a1 + k[14] * a2 + k[15] * a3;  // B_4
           const double b1 = k[0] * d + k[1] * a1 + k[2] * a2 + k[3] * a3;
-          if constexpr (kParkA) P0.put(i, r, b1);
+          if constexpr (kParkB1) P0.put(i, r, b1);
           else X0[i][r] = b1;
           X1[i][r] = k[4] * d + k[5] * a1 + k[6] * a2 + k[7] * a3;   // B_2
           X2[i][r] = k[8] * d + k[9] * a1 + k[10] * a2 + k[11] * a3;  // B_3
@@ -674,7 +677,7 @@ __device__ __attribute__((always_inline)) void run_res(const FusedArgs &a, int64
       __syncthreads();
       if constexpr (act) {
         to_lds<T>(L, ln, X1);
-        if constexpr (kParkA) P0.get_all(X1);  // B_1
+        if constexpr (kParkB1) P0.get_all(X1);  // B_1
         else {
   #pragma unroll
           for (int i = 0; i < T; ++i) X1[i] = X0[i];
